@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput of the prior-preconditioned CG sampler on one MI355X.
+
+A step is one Gibbs beta-draw (Prop 2.1): counter-based eta and delta, the
+right-hand side b, prior-preconditioned CG to the stopping rule, the FP64 true
+residual and, in the FP32 form, the refinement restart when the true residual
+misses the rule.  The workload is n = 1e5 observations, p = 2e4 binary
+features with log-uniform column densities in [1e-4, 0.2], tau = 1e-3 and
+50 signal columns, relative preconditioned residual 1e-6.
+
+Prints one JSON line (rank 0): draws/s of the chosen form (FP32 vectors,
+FP64 scalars), with the plain FP64 form, the HBM roofline of the dominant
+kernel (the X pass, timed with HIP events on the solver's stream during the
+timed draws) and the CPU oracle timed on this host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "Gibbs beta-draws/sec + SpMV-CG HBM GB/s (% peak), n=1e5 p=2e4, rel err<=1e-5"
+SEED = 12437
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 form")
+    ap.add_argument("--cpu-iters", type=int, default=40,
+                    help="oracle CG iterations in the bounded CPU sample")
+    return ap.parse_args()
+
+
+def pass_bytes(P, sv):
+    """Algorithmic bytes of one launch of each X pass (what the index-only
+    CSR/CSC format moves): the int32 index stream, the segment offsets and ids
+    of the non-empty segments, the per-chunk tables, the gathered vector read
+    once, the row scale (omega, row pass only) and the output."""
+    nnz, n, p = P.nnz, P.n, P.p
+    chunk = 2048
+    nch = (nnz + chunk - 1) // chunk
+    rows = int(np.count_nonzero(np.diff(P.row_ptr)))
+    cols = int(np.count_nonzero(np.bincount(P.col_idx, minlength=p)))
+    csr = 4 * nnz + 8 * (rows + 1) + 4 * rows + 8 * nch + sv * p + sv * n + sv * rows
+    csc = 4 * nnz + 8 * (cols + 1) + 4 * cols + 8 * nch + sv * n + sv * cols
+    return csr, csc
+
+
+def vec_bytes(p, sv):
+    """Bytes of the three p-vector phases of one CG iteration: <s, q + d s>;
+    beta += alpha s, r -= alpha q, rho; s = M^-1 r + ratio s."""
+    dot = p * (sv + sv + 8)
+    upd = p * (sv + sv + 8 + 8 + 8 + 8 + 8 + 8)
+    direc = p * (8 + 8 + sv + sv)
+    return dot + upd + direc
+
+
+def run_form(pk, torch, X, P, dtype, steps, warmup, tol, profile):
+    dt = torch.float32 if dtype == pk.F32 else torch.float64
+    om = torch.as_tensor(P.omega, device="cuda").to(dt)
+    z = torch.as_tensor(P.z, device="cuda").to(dt)
+    lam = torch.as_tensor(P.lam, device="cuda").to(dt)
+    for w in range(warmup):
+        pk.draw(X, om, z, lam, P.tau, SEED, 0, 1000 + w, tol=tol)
+    torch.cuda.synchronize()
+    if profile:
+        X.profile(True)
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        _, info = pk.draw(X, om, z, lam, P.tau, SEED, 0, k, tol=tol)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = X.stats() if profile else None
+    if profile:
+        X.profile(False)
+    return t1 - t0, infos, stats
+
+
+def cpu_baseline(P, K_mean, tol, iters):
+    """The oracle as it stands, on this host: Prop 2.1's b and a bounded
+    number of CG iterations on the same workload, extrapolated to the GPU's
+    mean iterations per draw."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import philox_ref, ppcg_ref
+
+    with threadpool_limits(1):
+        X = ppcg_ref.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+        t0 = time.perf_counter()
+        eta, delta = philox_ref.eta_delta(SEED, 0, 0, P.n, P.p)
+        b = ppcg_ref.rhs_b(X, P.omega, P.z, P.lam, P.tau, eta, delta)
+        t1 = time.perf_counter()
+        res = ppcg_ref.pcg_solve(X, P.omega, P.lam, P.tau, b, tol=tol, max_iter=iters)
+        t2 = time.perf_counter()
+    t_iter = (t2 - t1) / max(res.iters, 1)
+    t_draw = (t1 - t0) + K_mean * t_iter
+    return {
+        "value": 1.0 / t_draw, "unit": "draws/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle (NumPy/SciPy FP64, 1 thread) at n=1e5 p=2e4: Prop 2.1 b plus "
+                   f"{res.iters} CG iterations timed ({t2 - t0:.1f} s), extrapolated to "
+                   f"{K_mean:.1f} iterations per draw"),
+        "sec_per_cg_iter": t_iter,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the sampler's "
+              "data-parallel path is measured on a single MI355X; see DESIGN.md for how it "
+              "would shard.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1810_12437_amd as pk
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    print("[bench] generating workload n=1e5 p=2e4 ...", file=sys.stderr, flush=True)
+    P = synth.make_problem("c1")
+    X = pk.Matrix.from_problem(P)
+    print(f"[bench] nnz={P.nnz}; timing FP32 form ({args.warmup}+{args.steps} draws)",
+          file=sys.stderr, flush=True)
+    rel_err = None
+    gold = os.path.join(ROOT, "tests", "golden", "c1_draw0_reference.npz")
+    if os.path.exists(gold):
+        # Accuracy of the timed configuration: draw (SEED, 0, 0) against the
+        # oracle's solution of the same draw (stored by the oracle-only script
+        # tests/golden/make_c1_reference.py).
+        g = np.load(gold)
+        om = torch.as_tensor(P.omega, device="cuda").float()
+        zz = torch.as_tensor(P.z, device="cuda").float()
+        la = torch.as_tensor(P.lam, device="cuda").float()
+        b0, _ = pk.draw(X, om, zz, la, P.tau, int(g["seed"]), int(g["chain"]), int(g["draw"]),
+                        tol=args.tol)
+        ref = g["beta_f32"]
+        rel_err = float(np.linalg.norm(b0.double().cpu().numpy() - ref) / np.linalg.norm(ref))
+    el, infos, st = run_form(pk, torch, X, P, pk.F32, args.steps, args.warmup, args.tol, True)
+    iters = np.array([i["iters"] + i["refine_iters"] for i in infos], dtype=np.float64)
+    K = float(iters.mean())
+    csr_b, csc_b = pass_bytes(P, 4)
+    t_pass = (st["csr_ms"] + st["csc_ms"]) / max(st["csr_launches"] + st["csc_launches"], 1)
+    bytes_per_launch = 0.5 * (csr_b + csc_b)
+    achieved = bytes_per_launch / (t_pass * 1e-3) / 1e9
+    iter_bytes = csr_b + csc_b + vec_bytes(P.p, 4)
+    cg_gbps = iter_bytes * iters.sum() / el / 1e9
+    out = {
+        "metric": METRIC,
+        "value": args.steps / el,
+        "unit": "draws/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("n=1e5 p=2e4 binary X, column densities log-uniform [1e-4, 0.2], "
+                         "tau=1e-3, 50 signal columns; FP32 vectors + FP64 scalars; "
+                         f"relative preconditioned residual {args.tol:g}"),
+            "nnz": P.nnz, "n": P.n, "p": P.p, "tol": args.tol, "seed": SEED,
+        },
+        "rel_err_vs_oracle": rel_err,
+        "cg_iters_mean": K,
+        "cg_iters_per_s": float(iters.sum() / el),
+        "cg_hbm_gbps": cg_gbps,
+        "cg_hbm_frac": cg_gbps / HBM_PEAK_GBPS,
+        "refined_draws": int(sum(i["refined"] for i in infos)),
+        "max_true_resid_over_tol": float(max(i["resid_true"] for i in infos)),
+        "roofline": {
+            "kernel": "k_segsum<float,8> (row pass u = omega.*(X s) and column pass q = X^T u)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+            "avg_launch_us": 1e3 * t_pass,
+            "row_pass_us": 1e3 * st["csr_ms"] / max(st["csr_launches"], 1),
+            "col_pass_us": 1e3 * st["csc_ms"] / max(st["csc_launches"], 1),
+            "bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_f64:
+        steps64 = max(3, args.steps // 4)
+        print(f"[bench] timing FP64 form (1+{steps64} draws)", file=sys.stderr, flush=True)
+        el64, inf64, st64 = run_form(pk, torch, X, P, pk.F64, steps64, 1, args.tol, True)
+        it64 = np.array([i["iters"] + i["refine_iters"] for i in inf64], dtype=np.float64)
+        c64, s64 = pass_bytes(P, 8)
+        t64 = (st64["csr_ms"] + st64["csc_ms"]) / max(st64["csr_launches"] + st64["csc_launches"], 1)
+        out["plain_f64"] = {
+            "draws_per_s": steps64 / el64, "cg_iters_mean": float(it64.mean()),
+            "cg_iters_per_s": float(it64.sum() / el64),
+            "cg_hbm_gbps": (c64 + s64 + vec_bytes(P.p, 8)) * it64.sum() / el64 / 1e9,
+            "pass_gbps": 0.5 * (c64 + s64) / (t64 * 1e-3) / 1e9,
+        }
+    if not args.no_cpu:
+        print(f"[bench] CPU oracle sample ({args.cpu_iters} iterations)", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(P, K, args.tol, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

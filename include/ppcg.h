@@ -1,0 +1,226 @@
+/*
+ * ppcg.h -- C ABI of the prior-preconditioned conjugate-gradient sampler.
+ *
+ * Nishimura & Suchard, "Prior-preconditioned conjugate gradient method for
+ * accelerated Gibbs sampling in 'large n & large p' Bayesian sparse
+ * regression".  The library draws
+ *
+ *     beta ~ N(Phi^-1 X^T Omega z, Phi^-1),  Phi = X^T Omega X + tau^-2 Lambda^-2
+ *
+ * (Section 1, eq. beta_conditional) by Prop 2.1: it forms the random vector
+ *
+ *     b = X^T Omega z + X^T Omega^1/2 eta + tau^-1 Lambda^-1 delta
+ *
+ * (eq. cg_sampler_target_vector) and solves Phi beta = b (eq.
+ * linear_system_for_cg_sampler) by conjugate gradient (Supplement S2)
+ * preconditioned with the prior precision M = tau^-2 Lambda^-2 (Section 2.4),
+ * touching X only through the products v -> X v and w -> X^T w.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - X is binary (every stored entry equals one) and is given once as CSR
+ *   index arrays; the handle owns device copies of the CSR and CSC index
+ *   arrays and of its workspace.
+ * - Vector arguments are DEVICE pointers owned by the caller, contiguous, with
+ *   element type given by `dtype` (PPCG_F64: double, PPCG_F32: float).  The
+ *   library keeps no pointer to them after the call returns.
+ * - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream).
+ *   Entry points that take a `ppcg_info*` block the host until the result is
+ *   written (the solver checks convergence from the host between batches of
+ *   iterations); the others are asynchronous on `stream`.
+ * - tau > 0, omega_i > 0 and lambda_j > 0 are the caller's responsibility for
+ *   device vectors (they are not read back); violations give non-finite
+ *   results or PPCG_EBREAKDOWN, not memory faults.
+ * - Return values report synchronous problems (PPCG_EINVAL, PPCG_ENOMEM,
+ *   PPCG_EHIP).  Convergence problems (PPCG_ENOTCONV, PPCG_EBREAKDOWN) are
+ *   reported in ppcg_info.status and are also returned.
+ * - No C++ exception crosses this interface.  A handle must not be used by
+ *   two calls at the same time (it holds the solver's workspace).
+ */
+#ifndef PPCG_H
+#define PPCG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PPCG_OK 0
+#define PPCG_EINVAL 1     /* bad argument (size, pointer, index out of range, unsorted) */
+#define PPCG_ENOMEM 2     /* device or host allocation failed                         */
+#define PPCG_EHIP 3       /* a HIP runtime call or kernel launch failed               */
+#define PPCG_ENOTCONV 4   /* max_iter reached; the last iterate is returned           */
+#define PPCG_EBREAKDOWN 5 /* <s, Phi s> <= 0 or non-finite (Phi not positive definite) */
+#define PPCG_ENODEV 6     /* no HIP device                                            */
+
+/* Element type of vector arguments (and of the CG iteration's matvecs). */
+#define PPCG_F64 0 /* FP64 vectors and matvecs throughout                               */
+#define PPCG_F32 1 /* FP32 matvec vectors; FP64 state, inner products, scalars, RHS,
+                      true residual; optional FP64-residual refinement restart       */
+
+/* Stopping rules, all on the prior-preconditioned residual r~ = tau lambda (b - Phi beta)
+ * of Supplement S4.2 (|| r~ ||^2 = <r, M^-1 r>) unless noted. */
+#define PPCG_REL_PRECOND 0     /* ||r~_k|| <= tol * ||tau lambda b||                        */
+#define PPCG_RMS_PRECOND_ABS 1 /* p^-1/2 ||r~_k|| <= tol  (eq. mean_sq_resid_for_cg_termination) */
+#define PPCG_REL_PLAIN 2       /* ||r_k|| <= tol * ||b||  (the usual l2 rule, for comparison) */
+
+/* Where ppcg_matrix_create reads its index arrays from. */
+#define PPCG_MEM_HOST 0
+#define PPCG_MEM_DEVICE 1
+
+/* Random streams of the counter-based generator (ppcg_normals). */
+#define PPCG_STREAM_ETA 0
+#define PPCG_STREAM_DELTA 1
+
+typedef struct ppcg_matrix ppcg_matrix;
+
+typedef struct ppcg_options {
+  int32_t dtype;      /* PPCG_F64 or PPCG_F32                                        */
+  int32_t criterion;  /* PPCG_REL_PRECOND (default), PPCG_RMS_PRECOND_ABS, PPCG_REL_PLAIN */
+  int32_t max_iter;   /* cap on CG iterations per phase; <= 0 means p (CG is exact
+                         in p steps in exact arithmetic, Section 2.2)             */
+  int32_t refine;     /* 1: after convergence, if the FP64 true residual misses the
+                         rule, restart once from it; -1: default (1 for F32, 0 for F64) */
+  double tol;         /* tolerance of the stopping rule (default 1e-6)           */
+  int32_t true_resid; /* 1 (default): recompute b - Phi beta in FP64 at the end     */
+  int32_t check_every;/* host convergence check period in iterations (0: default) */
+  int32_t reserved[6];
+} ppcg_options;
+
+typedef struct ppcg_info {
+  int32_t status;       /* PPCG_OK, PPCG_ENOTCONV or PPCG_EBREAKDOWN               */
+  int32_t iters;        /* CG iterations of the first phase                        */
+  int32_t refine_iters; /* CG iterations of the refinement restart (0 if none)     */
+  int32_t refined;      /* 1 if the refinement restart ran                          */
+  double resid_rec;     /* rule value of the recursive residual at exit, divided by
+                           tol (<= 1 means the rule holds)                          */
+  double resid_true;    /* the same for the FP64 true residual b - Phi beta (-1 when
+                           not computed)                                            */
+  double rms_precond;   /* p^-1/2 ||tau lambda (b - Phi beta)|| (the paper's measure) */
+  double bnorm_precond; /* ||tau lambda b||                                         */
+} ppcg_info;
+
+/* Fills `opt` with the defaults listed above for the given dtype. */
+void ppcg_options_default(ppcg_options* opt, int32_t dtype);
+
+/* Static string for a status code. */
+const char* ppcg_status_string(int status);
+
+/* Library version string. */
+const char* ppcg_version(void);
+
+/*
+ * Creates a handle for the n x p binary design X (Section 1; the application's
+ * X is sparse and binary, Section 4).  `row_ptr` (int64, n+1 entries, row_ptr[0]
+ * = 0, non-decreasing, row_ptr[n] = nnz) and `col_idx` (int32, nnz entries,
+ * strictly increasing within each row, in [0, p)) are host or device pointers
+ * as `mem` says; they are copied.  `values` must be NULL (binary X).  Validates
+ * the arrays (PPCG_EINVAL on any violation) and builds the CSC twin and the
+ * chunk tables of the matvec kernels.  n, p >= 1; nnz >= 0.
+ */
+int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
+                       const int64_t* row_ptr, const int32_t* col_idx,
+                       const void* values, int32_t mem, hipStream_t stream);
+
+/* Releases the handle and its device memory (NULL is allowed). */
+int ppcg_matrix_destroy(ppcg_matrix* X);
+
+/* Sizes of a handle (any output pointer may be NULL). */
+int ppcg_matrix_shape(const ppcg_matrix* X, int64_t* n, int64_t* p, int64_t* nnz);
+
+/*
+ * out = Phi v = X^T (omega .* (X v)) + tau^-2 lambda^-2 .* v  (the product CG
+ * needs, Section 2.2; Phi from eq. beta_conditional).  omega: n, lambda, v,
+ * out: p, all `dtype`.  Asynchronous on `stream`.
+ */
+int ppcg_phi_matvec(const ppcg_matrix* X, const void* omega, const void* lambda,
+                    double tau, const void* v, void* out, int32_t dtype,
+                    hipStream_t stream);
+
+/*
+ * Writes `count` standard normals of one stream of the counter-based generator
+ * (FP64, device pointer `out`): Philox4x64-10 with key (seed, 0) and counter
+ * (i, stream_id, chain, draw_index); block i gives elements 4i..4i+3 by the
+ * Box-Muller transform.  These are the eta (stream 0) and delta (stream 1) of
+ * Prop 2.1 for draw (seed, chain, draw_index).  Asynchronous.
+ */
+int ppcg_normals(uint64_t seed, uint64_t stream_id, uint64_t chain,
+                 uint64_t draw_index, int64_t count, double* out,
+                 hipStream_t stream);
+
+/*
+ * b = X^T Omega z + X^T Omega^1/2 eta + tau^-1 Lambda^-1 delta (Prop 2.1,
+ * eq. cg_sampler_target_vector) with eta, delta from the generator above.
+ * omega, z: n; lambda: p, all `dtype`; b_out: p doubles (always FP64).
+ * Asynchronous.
+ */
+int ppcg_rhs(const ppcg_matrix* X, const void* omega, const void* z,
+             const void* lambda, double tau, uint64_t seed, uint64_t chain,
+             uint64_t draw_index, int32_t dtype, double* b_out,
+             hipStream_t stream);
+
+/*
+ * Solves Phi beta = b (eq. linear_system_for_cg_sampler) by CG preconditioned
+ * with M = tau^-2 Lambda^-2 (Section 2.4), starting from beta0 (NULL: zero,
+ * Section 2.6).  omega: n; lambda, b, beta0, beta_out: p; all opt->dtype.
+ * `opt` NULL means defaults for PPCG_F64.  `info` (host pointer, may be NULL)
+ * receives iteration counts and residuals.  Blocks until beta_out is written.
+ */
+int ppcg_solve(const ppcg_matrix* X, const void* omega, const void* lambda,
+               double tau, const void* b, const void* beta0,
+               const ppcg_options* opt, void* beta_out, ppcg_info* info,
+               hipStream_t stream);
+
+/*
+ * One draw of beta ~ N(Phi^-1 X^T Omega z, Phi^-1) by Prop 2.1: eta, delta from
+ * (seed, chain, draw_index), b as in ppcg_rhs, then ppcg_solve from zero.  The
+ * draw is a pure function of its arguments.  omega, z: n; lambda, beta_out: p;
+ * all opt->dtype.  Blocks until beta_out is written.
+ */
+int ppcg_draw(const ppcg_matrix* X, const void* omega, const void* z,
+              const void* lambda, double tau, uint64_t seed, uint64_t chain,
+              uint64_t draw_index, const ppcg_options* opt, void* beta_out,
+              ppcg_info* info, hipStream_t stream);
+
+/*
+ * Adjoint of beta = Phi(lambda, tau)^-1 b for a loss L with g = dL/dbeta:
+ * solves Phi a = g with the same preconditioned CG, then
+ *   grad_b = a,  grad_loglambda_j = 2 d_j a_j beta_j,  grad_logtau = sum_j of those,
+ * d_j = tau^-2 lambda_j^-2 (differentiating eq. beta_conditional: only the
+ * prior term of Phi depends on lambda and tau).  b is an independent input.
+ * beta, grad_beta, grad_b, grad_loglambda: p, opt->dtype; grad_logtau: one
+ * double in device memory.  Blocks until the outputs are written.
+ */
+int ppcg_solve_backward(const ppcg_matrix* X, const void* omega,
+                        const void* lambda, double tau, const void* beta,
+                        const void* grad_beta, const ppcg_options* opt,
+                        void* grad_b, void* grad_loglambda,
+                        double* grad_logtau, ppcg_info* info,
+                        hipStream_t stream);
+
+/*
+ * Kernel timing of the two X passes of the CG iteration (v -> omega .* X v
+ * and w -> X^T w, the products Section 2.2 says dominate each iteration's
+ * cost).  With `enable` != 0 the handle brackets every pass launch of the CG
+ * loop with HIP events on the caller's stream and accumulates the elapsed
+ * times; enabling resets the totals.  Host-only bookkeeping; PPCG_EINVAL for a
+ * NULL handle.
+ */
+int ppcg_matrix_profile(ppcg_matrix* X, int32_t enable);
+
+/*
+ * Totals since the last ppcg_matrix_profile(X, 1): milliseconds and launch
+ * counts of the row pass (CSR, v -> omega .* X v) and of the column pass (CSC,
+ * w -> X^T w).  Any output pointer may be NULL.
+ */
+int ppcg_matrix_stats(const ppcg_matrix* X, double* csr_ms, int64_t* csr_launches,
+                      double* csc_ms, int64_t* csc_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPCG_H */

@@ -1,0 +1,372 @@
+"""Prior-preconditioned CG sampler on MI355X: Python binding of libppcg.so.
+
+Argument marshalling only: every step of the sampler runs in the HIP library
+(``csrc/``) behind the C ABI declared in ``include/ppcg.h``.  There is no CPU
+fallback; importing works without the library, but every call raises
+``PPCGUnavailable`` when ``libppcg.so`` is missing.
+
+Vectors are torch CUDA (HIP) tensors; PyTorch is used for device memory and
+the current stream only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "F64", "F32", "REL_PRECOND", "RMS_PRECOND_ABS", "REL_PLAIN",
+    "STREAM_ETA", "STREAM_DELTA", "Matrix", "Options", "Info",
+    "phi_matvec", "normals", "rhs", "solve", "draw", "solve_backward",
+    "PPCGSolve", "PPCGError", "PPCGUnavailable", "lib", "LIB_PATH", "EXPORTED_SYMBOLS",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppcg.so")
+
+F64, F32 = 0, 1
+REL_PRECOND, RMS_PRECOND_ABS, REL_PLAIN = 0, 1, 2
+MEM_HOST, MEM_DEVICE = 0, 1
+STREAM_ETA, STREAM_DELTA = 0, 1
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENODEV = 0, 1, 2, 3, 4, 5, 6
+_SOLVER_STATUS = (OK, ENOTCONV, EBREAKDOWN)
+
+EXPORTED_SYMBOLS = (
+    "ppcg_options_default", "ppcg_status_string", "ppcg_version",
+    "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
+    "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
+    "ppcg_solve_backward", "ppcg_matrix_profile", "ppcg_matrix_stats",
+)
+
+
+class PPCGError(RuntimeError):
+    def __init__(self, what, code):
+        super().__init__(f"{what}: {_status_string(code)} (code {code})")
+        self.code = code
+
+
+class PPCGUnavailable(ImportError):
+    pass
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32), ("criterion", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32), ("refine", ctypes.c_int32),
+        ("tol", ctypes.c_double), ("true_resid", ctypes.c_int32),
+        ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32), ("refined", ctypes.c_int32),
+        ("resid_rec", ctypes.c_double), ("resid_true", ctypes.c_double),
+        ("rms_precond", ctypes.c_double), ("bnorm_precond", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp, _i32, _i64, _u64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+
+
+def _declare(L):
+    L.ppcg_options_default.argtypes = [ctypes.POINTER(Options), _i32]
+    L.ppcg_options_default.restype = None
+    L.ppcg_status_string.argtypes = [ctypes.c_int]
+    L.ppcg_status_string.restype = ctypes.c_char_p
+    L.ppcg_version.argtypes = []
+    L.ppcg_version.restype = ctypes.c_char_p
+    L.ppcg_matrix_create.argtypes = [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _vp, _i32, _vp]
+    L.ppcg_matrix_destroy.argtypes = [_vp]
+    L.ppcg_matrix_shape.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+    L.ppcg_phi_matvec.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, _i32, _vp]
+    L.ppcg_normals.argtypes = [_u64, _u64, _u64, _u64, _i64, _vp, _vp]
+    L.ppcg_rhs.argtypes = [_vp, _vp, _vp, _vp, _dbl, _u64, _u64, _u64, _i32, _vp, _vp]
+    L.ppcg_solve.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, ctypes.POINTER(Options), _vp,
+                             ctypes.POINTER(Info), _vp]
+    L.ppcg_draw.argtypes = [_vp, _vp, _vp, _vp, _dbl, _u64, _u64, _u64, ctypes.POINTER(Options),
+                            _vp, ctypes.POINTER(Info), _vp]
+    L.ppcg_solve_backward.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, ctypes.POINTER(Options),
+                                      _vp, _vp, _vp, ctypes.POINTER(Info), _vp]
+    L.ppcg_matrix_profile.argtypes = [_vp, _i32]
+    L.ppcg_matrix_stats.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64),
+                                    ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]
+    for name in ("ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
+                 "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
+                 "ppcg_solve_backward"):
+        getattr(L, name).restype = ctypes.c_int
+
+
+def lib():
+    """The loaded libppcg.so (raises PPCGUnavailable when it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PPCGUnavailable(
+                f"{LIB_PATH} is not built; build it with __graft_entry__.build(). "
+                "The sampler has no CPU fallback.")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _status_string(code):
+    try:
+        return lib().ppcg_status_string(int(code)).decode()
+    except Exception:  # pragma: no cover - library missing
+        return "status"
+
+
+def _check(rc, what, solver=False):
+    if rc == OK or (solver and rc in _SOLVER_STATUS):
+        return rc
+    raise PPCGError(what, rc)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_TDTYPE = {}
+
+
+def _tdtype(dtype):
+    torch = _torch()
+    return torch.float64 if dtype == F64 else torch.float32
+
+
+def _dtype_of(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"vectors must be float32 or float64, got {t.dtype}")
+
+
+def _dev(t, dtype, n, name):
+    """Device pointer of a contiguous CUDA tensor of the given dtype and length."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != _tdtype(dtype):
+        raise TypeError(f"{name} must be {_tdtype(dtype)}, got {t.dtype}")
+    if t.dim() != 1 or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous vector of length {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Matrix:
+    """Handle of a binary design X (CSR index arrays, copied to the device)."""
+
+    def __init__(self, n, p, row_ptr, col_idx):
+        L = lib()
+        torch = _torch()
+        self.n, self.p = int(n), int(p)
+        h = ctypes.c_void_p()
+        if isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda:
+            rp = row_ptr.to(torch.int64).contiguous()
+            ci = col_idx.to(torch.int32).contiguous()
+            nnz = int(ci.numel())
+            rc = L.ppcg_matrix_create(ctypes.byref(h), self.n, self.p, nnz,
+                                      ctypes.c_void_p(rp.data_ptr()),
+                                      ctypes.c_void_p(ci.data_ptr() if nnz else 0), None,
+                                      MEM_DEVICE, _stream())
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+            nnz = int(ci.size)
+            rc = L.ppcg_matrix_create(ctypes.byref(h), self.n, self.p, nnz,
+                                      rp.ctypes.data_as(ctypes.c_void_p),
+                                      ci.ctypes.data_as(ctypes.c_void_p) if nnz else None,
+                                      None, MEM_HOST, _stream())
+        _check(rc, "ppcg_matrix_create")
+        self.nnz = nnz
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("matrix handle is closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.ppcg_matrix_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable=True):
+        """Start (and reset) or stop timing of the two X passes of the CG loop."""
+        _check(lib().ppcg_matrix_profile(self.handle, 1 if enable else 0), "ppcg_matrix_profile")
+
+    def stats(self):
+        """{'csr_ms', 'csr_launches', 'csc_ms', 'csc_launches'} since profile(True)."""
+        a, b = _dbl(), _dbl()
+        na, nb = _i64(), _i64()
+        _check(lib().ppcg_matrix_stats(self.handle, ctypes.byref(a), ctypes.byref(na),
+                                       ctypes.byref(b), ctypes.byref(nb)), "ppcg_matrix_stats")
+        return {"csr_ms": a.value, "csr_launches": na.value, "csc_ms": b.value,
+                "csc_launches": nb.value}
+
+    @classmethod
+    def from_problem(cls, P):
+        return cls(P.n, P.p, P.row_ptr, P.col_idx)
+
+
+def make_options(dtype=F64, tol=1e-6, criterion=REL_PRECOND, max_iter=0, refine=-1,
+                 true_resid=1, check_every=0):
+    o = Options()
+    lib().ppcg_options_default(ctypes.byref(o), int(dtype))
+    o.tol = float(tol)
+    o.criterion = int(criterion)
+    o.max_iter = int(max_iter)
+    o.refine = int(refine)
+    o.true_resid = int(true_resid)
+    o.check_every = int(check_every)
+    return o
+
+
+def phi_matvec(X, omega, lam, tau, v):
+    """out = Phi v (same dtype as v)."""
+    torch = _torch()
+    dt = _dtype_of(v)
+    out = torch.empty(X.p, dtype=v.dtype, device=v.device)
+    rc = lib().ppcg_phi_matvec(X.handle, _dev(omega, dt, X.n, "omega"), _dev(lam, dt, X.p, "lambda"),
+                               float(tau), _dev(v, dt, X.p, "v"), _dev(out, dt, X.p, "out"), dt,
+                               _stream())
+    _check(rc, "ppcg_phi_matvec")
+    return out
+
+
+def normals(seed, stream_id, chain, draw_index, count, device="cuda"):
+    """FP64 normals of one generator stream (eta: 0, delta: 1)."""
+    torch = _torch()
+    out = torch.empty(int(count), dtype=torch.float64, device=device)
+    rc = lib().ppcg_normals(int(seed), int(stream_id), int(chain), int(draw_index), int(count),
+                            ctypes.c_void_p(out.data_ptr()), _stream())
+    _check(rc, "ppcg_normals")
+    return out
+
+
+def rhs(X, omega, z, lam, tau, seed, chain, draw_index):
+    """FP64 b of Prop 2.1 for draw (seed, chain, draw_index)."""
+    torch = _torch()
+    dt = _dtype_of(omega)
+    b = torch.empty(X.p, dtype=torch.float64, device=omega.device)
+    rc = lib().ppcg_rhs(X.handle, _dev(omega, dt, X.n, "omega"), _dev(z, dt, X.n, "z"),
+                        _dev(lam, dt, X.p, "lambda"), float(tau), int(seed), int(chain),
+                        int(draw_index), dt, ctypes.c_void_p(b.data_ptr()), _stream())
+    _check(rc, "ppcg_rhs")
+    return b
+
+
+def solve(X, omega, lam, tau, b, beta0=None, **opts):
+    """beta = Phi^-1 b by prior-preconditioned CG; returns (beta, info dict)."""
+    torch = _torch()
+    dt = _dtype_of(b)
+    o = make_options(dtype=dt, **opts)
+    beta = torch.empty(X.p, dtype=b.dtype, device=b.device)
+    info = Info()
+    rc = lib().ppcg_solve(X.handle, _dev(omega, dt, X.n, "omega"), _dev(lam, dt, X.p, "lambda"),
+                          float(tau), _dev(b, dt, X.p, "b"),
+                          None if beta0 is None else _dev(beta0, dt, X.p, "beta0"),
+                          ctypes.byref(o), _dev(beta, dt, X.p, "beta"), ctypes.byref(info),
+                          _stream())
+    _check(rc, "ppcg_solve", solver=True)
+    return beta, info.as_dict()
+
+
+def draw(X, omega, z, lam, tau, seed, chain=0, draw_index=0, **opts):
+    """One draw of beta ~ N(Phi^-1 X^T Omega z, Phi^-1); returns (beta, info dict)."""
+    torch = _torch()
+    dt = _dtype_of(omega)
+    o = make_options(dtype=dt, **opts)
+    beta = torch.empty(X.p, dtype=omega.dtype, device=omega.device)
+    info = Info()
+    rc = lib().ppcg_draw(X.handle, _dev(omega, dt, X.n, "omega"), _dev(z, dt, X.n, "z"),
+                         _dev(lam, dt, X.p, "lambda"), float(tau), int(seed), int(chain),
+                         int(draw_index), ctypes.byref(o), _dev(beta, dt, X.p, "beta"),
+                         ctypes.byref(info), _stream())
+    _check(rc, "ppcg_draw", solver=True)
+    return beta, info.as_dict()
+
+
+def solve_backward(X, omega, lam, tau, beta, grad_beta, **opts):
+    """Adjoint of beta = Phi^-1 b: returns (grad_b, grad_loglambda, grad_logtau, info)."""
+    torch = _torch()
+    dt = _dtype_of(beta)
+    o = make_options(dtype=dt, **opts)
+    gb = torch.empty_like(beta)
+    gl = torch.empty_like(beta)
+    gt = torch.empty(1, dtype=torch.float64, device=beta.device)
+    info = Info()
+    rc = lib().ppcg_solve_backward(X.handle, _dev(omega, dt, X.n, "omega"),
+                                   _dev(lam, dt, X.p, "lambda"), float(tau),
+                                   _dev(beta, dt, X.p, "beta"), _dev(grad_beta, dt, X.p, "grad_beta"),
+                                   ctypes.byref(o), _dev(gb, dt, X.p, "grad_b"),
+                                   _dev(gl, dt, X.p, "grad_loglambda"),
+                                   ctypes.c_void_p(gt.data_ptr()), ctypes.byref(info), _stream())
+    _check(rc, "ppcg_solve_backward", solver=True)
+    return gb, gl, gt, info.as_dict()
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class PPCGSolve(torch.autograd.Function):
+        """beta = Phi(lambda, tau)^-1 b with lambda = exp(log_lambda), tau =
+        exp(log_tau); gradients with respect to b, log_lambda and log_tau by
+        the adjoint CG solve (no CG iterates are stored: the backward pass
+        solves Phi a = dL/dbeta afresh)."""
+
+        @staticmethod
+        def forward(ctx, X, omega, b, log_lambda, log_tau, opts=None):
+            opts = dict(opts or {})
+            lam = torch.exp(log_lambda).contiguous()
+            tau = float(torch.exp(log_tau.detach()).item())
+            beta, info = solve(X, omega, lam, tau, b.contiguous(), **opts)
+            ctx.X, ctx.tau, ctx.opts = X, tau, opts
+            ctx.save_for_backward(omega, lam, beta)
+            ctx.info = info
+            return beta
+
+        @staticmethod
+        def backward(ctx, grad_beta):
+            omega, lam, beta = ctx.saved_tensors
+            gb, gl, gt, _ = solve_backward(ctx.X, omega, lam, ctx.tau, beta,
+                                           grad_beta.contiguous(), **ctx.opts)
+            gt = gt.reshape(()).to(beta.dtype)
+            return None, None, gb, gl, gt, None
+
+    return PPCGSolve
+
+
+class _LazyAutograd:
+    _fn = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._fn is None:
+            _LazyAutograd._fn = _autograd_function()
+        return getattr(_LazyAutograd._fn, name)
+
+
+PPCGSolve = _LazyAutograd()

@@ -1,0 +1,656 @@
+// C-ABI host layer: handle construction, validation, workspace, and the
+// host-driven CG loop (convergence is decided on the device; the host reads
+// the decision every `check_every` iterations).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "../../include/ppcg.h"
+#include "ppcg_kernels.h"
+
+using namespace ppcg;
+
+namespace {
+
+struct DevBuf {
+  std::vector<void*> ptrs;
+  template <typename T>
+  hipError_t alloc(T** out, size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return e;
+    ptrs.push_back(p);
+    *out = reinterpret_cast<T*>(p);
+    return hipSuccess;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+struct HostTable {
+  std::vector<int64_t> ptr;     // non-empty segment offsets
+  std::vector<int32_t> sid;     // segment ids
+  std::vector<int64_t> cstart;  // chunk starts (+ nnz)
+  std::vector<int32_t> cseg, cnseg;
+  std::vector<int32_t> split_seg, split_c0, split_c1;
+  int32_t nchunks = 0;
+};
+
+}  // namespace
+
+struct ppcg_matrix {
+  int64_t n = 0, p = 0, nnz = 0;
+  int device = 0;
+  int chunk = 2048;
+  DevBuf mem;
+  SegTable csr{}, csc{};
+  // workspace
+  double *u64 = nullptr, *qx64 = nullptr, *y64 = nullptr, *omega64 = nullptr;
+  double *d = nullptr, *m = nullptr, *b64 = nullptr, *beta64 = nullptr, *r64 = nullptr,
+         *s64 = nullptr;
+  float *u32 = nullptr, *qx32 = nullptr, *s32 = nullptr;
+  double* part = nullptr;
+  DevScal* sc = nullptr;
+  DevScal* h_sc = nullptr;  // pinned host mirror
+  // pass timing (ppcg_matrix_profile)
+  int profile = 0;
+  std::vector<hipEvent_t> ev;  // 4 per iteration of a check batch
+  double pass_ms[2] = {0.0, 0.0};
+  int64_t pass_cnt[2] = {0, 0};
+};
+
+#define PPCG_TRY_HIP(expr)                    \
+  do {                                        \
+    hipError_t _e = (expr);                   \
+    if (_e != hipSuccess) return PPCG_EHIP;   \
+  } while (0)
+
+#define PPCG_TRY_ALLOC(expr)                                               \
+  do {                                                                     \
+    hipError_t _e = (expr);                                                \
+    if (_e == hipErrorOutOfMemory || _e == hipErrorMemoryAllocation)       \
+      return PPCG_ENOMEM;                                                  \
+    if (_e != hipSuccess) return PPCG_EHIP;                                \
+  } while (0)
+
+namespace {
+
+// Non-empty segments and chunk table of one orientation given its offsets:
+// greedy packing of whole segments into chunks of at most C - 3 elements;
+// a segment longer than that becomes consecutive piece chunks.
+void build_table(const std::vector<int64_t>& off, int64_t nnz, int chunk, HostTable& t) {
+  const int64_t cap = chunk - 3;
+  const int64_t nseg_all = (int64_t)off.size() - 1;
+  t = HostTable();
+  for (int64_t s = 0; s < nseg_all; ++s) {
+    if (off[s + 1] > off[s]) {
+      t.ptr.push_back(off[s]);
+      t.sid.push_back((int32_t)s);
+    }
+  }
+  t.ptr.push_back(nnz);
+  const int64_t nseg = (int64_t)t.sid.size();
+  int64_t g = 0;
+  while (g < nseg) {
+    const int64_t len = t.ptr[g + 1] - t.ptr[g];
+    if (len > cap) {
+      const int32_t c0 = (int32_t)t.cstart.size();
+      for (int64_t o = t.ptr[g]; o < t.ptr[g + 1]; o += cap) {
+        t.cstart.push_back(o);
+        t.cseg.push_back((int32_t)g);
+        t.cnseg.push_back(0);
+      }
+      t.split_seg.push_back((int32_t)g);
+      t.split_c0.push_back(c0);
+      t.split_c1.push_back((int32_t)t.cstart.size() - 1);
+      ++g;
+    } else {
+      const int64_t start = t.ptr[g];
+      const int64_t first = g;
+      while (g < nseg && t.ptr[g + 1] - start <= cap) ++g;
+      t.cstart.push_back(start);
+      t.cseg.push_back((int32_t)first);
+      t.cnseg.push_back((int32_t)(g - first));
+    }
+  }
+  t.nchunks = (int32_t)t.cseg.size();
+  t.cstart.push_back(nnz);
+}
+
+template <typename V>
+int upload_vec(ppcg_matrix* X, const std::vector<V>& h, const V** out) {
+  V* d = nullptr;
+  PPCG_TRY_ALLOC(X->mem.alloc(&d, h.size()));
+  if (!h.empty())
+    PPCG_TRY_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  *out = d;
+  return PPCG_OK;
+}
+
+int upload_table(ppcg_matrix* X, const HostTable& h, const int32_t* idx_dev, int64_t nnz,
+                 SegTable& t) {
+  int rc;
+  if ((rc = upload_vec(X, h.ptr, &t.ptr))) return rc;
+  if ((rc = upload_vec(X, h.sid, &t.sid))) return rc;
+  if ((rc = upload_vec(X, h.cstart, &t.cstart))) return rc;
+  if ((rc = upload_vec(X, h.cseg, &t.cseg))) return rc;
+  if ((rc = upload_vec(X, h.cnseg, &t.cnseg))) return rc;
+  if ((rc = upload_vec(X, h.split_seg, &t.split_seg))) return rc;
+  if ((rc = upload_vec(X, h.split_c0, &t.split_c0))) return rc;
+  if ((rc = upload_vec(X, h.split_c1, &t.split_c1))) return rc;
+  double* part = nullptr;
+  PPCG_TRY_ALLOC(X->mem.alloc(&part, h.nchunks));
+  t.part = part;
+  t.idx = idx_dev;
+  t.nnz = nnz;
+  t.nseg = (int32_t)h.sid.size();
+  t.nchunks = h.nchunks;
+  t.nsplit = (int32_t)h.split_seg.size();
+  t.chunk = X->chunk;
+  return PPCG_OK;
+}
+
+int chunk_from_env() {
+  const char* s = std::getenv("PPCG_CHUNK_V");
+  if (!s) return 8;
+  const int v = std::atoi(s);
+  return (v == 4 || v == 8 || v == 16) ? v : 8;
+}
+
+bool valid_dtype(int32_t d) { return d == PPCG_F64 || d == PPCG_F32; }
+
+ppcg_options resolve(const ppcg_options* o, int64_t p) {
+  ppcg_options r;
+  if (o) {
+    r = *o;
+  } else {
+    ppcg_options_default(&r, PPCG_F64);
+  }
+  if (r.max_iter <= 0) r.max_iter = (int32_t)std::min<int64_t>(p, INT32_MAX);
+  if (r.refine < 0) r.refine = (r.dtype == PPCG_F32) ? 1 : 0;
+  if (r.check_every <= 0) r.check_every = 16;
+  return r;
+}
+
+int check_opts(const ppcg_options& o) {
+  if (!valid_dtype(o.dtype)) return PPCG_EINVAL;
+  if (o.criterion < 0 || o.criterion > 2) return PPCG_EINVAL;
+  if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return PPCG_EINVAL;
+  return PPCG_OK;
+}
+
+VecWork vw(ppcg_matrix* X) { return VecWork{X->part, X->sc}; }
+
+// FP64 product parts: u64 = omega .* (X x), qx64 = X^T u64.
+int fp64_phi_parts(ppcg_matrix* X, const double* x, const double* omega64, hipStream_t st) {
+  PPCG_TRY_HIP(launch_segsum<double>(X->csr, x, omega64, X->u64, nullptr, st));
+  PPCG_TRY_HIP(launch_segsum<double>(X->csc, X->u64, nullptr, X->qx64, nullptr, st));
+  return PPCG_OK;
+}
+
+template <typename T>
+struct Bufs;
+template <>
+struct Bufs<double> {
+  static double* s(ppcg_matrix* X) { return X->s64; }
+  static double* u(ppcg_matrix* X) { return X->u64; }
+  static double* qx(ppcg_matrix* X) { return X->qx64; }
+};
+template <>
+struct Bufs<float> {
+  static float* s(ppcg_matrix* X) { return X->s32; }
+  static float* u(ppcg_matrix* X) { return X->u32; }
+  static float* qx(ppcg_matrix* X) { return X->qx32; }
+};
+
+int sync_scal(ppcg_matrix* X, hipStream_t st) {
+  PPCG_TRY_HIP(hipMemcpyAsync(X->h_sc, X->sc, sizeof(DevScal), hipMemcpyDeviceToHost, st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  return PPCG_OK;
+}
+
+// Runs CG iterations until the device reports done; returns via h_sc.
+template <typename T>
+int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t st) {
+  T* s = Bufs<T>::s(X);
+  T* u = Bufs<T>::u(X);
+  T* qx = Bufs<T>::qx(X);
+  const int32_t* done = &X->sc->done;
+  const VecWork w = vw(X);
+  const bool prof = X->profile != 0;
+  if (prof && (int)X->ev.size() < 4 * o.check_every) {
+    while ((int)X->ev.size() < 4 * o.check_every) {
+      hipEvent_t e;
+      PPCG_TRY_HIP(hipEventCreate(&e));
+      X->ev.push_back(e);
+    }
+  }
+  for (;;) {
+    int32_t active_before = 0;
+    if (prof) active_before = X->h_sc->done ? 0 : 1;
+    for (int i = 0; i < o.check_every; ++i) {
+      if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 0], st));
+      PPCG_TRY_HIP(launch_segsum<T>(X->csr, s, omegaT, u, done, st));
+      if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 1], st));
+      PPCG_TRY_HIP(launch_segsum<T>(X->csc, u, nullptr, qx, done, st));
+      if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 2], st));
+      PPCG_TRY_HIP(launch_cg_dot<T>(w, s, qx, X->d, X->p, st));
+      PPCG_TRY_HIP(launch_cg_update<T>(w, s, qx, X->d, X->m, X->beta64, X->r64, X->p, st));
+      PPCG_TRY_HIP(launch_cg_direction<T>(w, X->m, X->r64, s, X->p, st));
+    }
+    const int32_t it0 = prof ? X->h_sc->iters : 0;
+    PPCG_TRY_HIP(hipMemcpyAsync(X->h_sc, X->sc, sizeof(DevScal), hipMemcpyDeviceToHost, st));
+    PPCG_TRY_HIP(hipStreamSynchronize(st));
+    if (prof && active_before) {
+      // Only the iterations that ran (the rest exited at once) are counted.
+      const int ran = std::min(o.check_every, (int)(X->h_sc->iters - it0));
+      for (int i = 0; i < ran; ++i) {
+        float a = 0.f, b = 0.f;
+        PPCG_TRY_HIP(hipEventElapsedTime(&a, X->ev[4 * i + 0], X->ev[4 * i + 1]));
+        PPCG_TRY_HIP(hipEventElapsedTime(&b, X->ev[4 * i + 1], X->ev[4 * i + 2]));
+        X->pass_ms[0] += a;
+        X->pass_ms[1] += b;
+        X->pass_cnt[0] += 1;
+        X->pass_cnt[1] += 1;
+      }
+    }
+    if (X->h_sc->done) return PPCG_OK;
+  }
+}
+
+
+double ratio(double meas, double thresh2) {
+  if (thresh2 > 0.0) return std::sqrt(meas / thresh2);
+  return meas > 0.0 ? std::numeric_limits<double>::infinity() : 0.0;
+}
+
+// CG from the state prepared in b64 (and beta64 when have_beta0), then the
+// optional FP64 true residual and refinement restart.
+template <typename T>
+int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have_beta0,
+               const ppcg_options& o, ppcg_info* info, hipStream_t st) {
+  const VecWork w = vw(X);
+  T* s = Bufs<T>::s(X);
+  const double* qx0 = nullptr;
+  if (have_beta0) {
+    int rc = fp64_phi_parts(X, X->beta64, omega64, st);
+    if (rc) return rc;
+    qx0 = X->qx64;
+  }
+  PPCG_TRY_HIP(launch_cg_start<T>(w, 0, X->b64, qx0, X->d, X->m, X->beta64, X->r64, s, X->p,
+                                  o.tol, o.criterion, o.max_iter, st));
+  if (X->profile) {
+    int rc0 = sync_scal(X, st);
+    if (rc0) return rc0;
+  }
+  int rc = run_loop<T>(X, omegaT, o, st);
+  if (rc) return rc;
+  ppcg_info inf{};
+  inf.status = X->h_sc->status;
+  inf.iters = X->h_sc->iters;
+  inf.resid_rec = ratio(X->h_sc->meas, X->h_sc->thresh2);
+  inf.resid_true = -1.0;
+  inf.bnorm_precond = std::sqrt(X->h_sc->bm2);
+  inf.rms_precond = -1.0;
+  if (o.true_resid || o.refine) {
+    rc = fp64_phi_parts(X, X->beta64, omega64, st);
+    if (rc) return rc;
+    PPCG_TRY_HIP(launch_cg_start<T>(w, 2, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
+                                    X->p, o.tol, o.criterion, o.max_iter, st));
+    rc = sync_scal(X, st);
+    if (rc) return rc;
+    inf.resid_true = ratio(X->h_sc->true_meas, X->h_sc->thresh2);
+    inf.rms_precond = std::sqrt(X->h_sc->true_rm / (double)X->p);
+    if (o.refine && inf.status == PPCG_OK && X->h_sc->true_meas > X->h_sc->thresh2) {
+      // Restart once from the FP64 true residual r = b - Phi beta (qx64 holds
+      // the product parts of the current beta).
+      PPCG_TRY_HIP(launch_cg_start<T>(w, 1, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
+                                      X->p, o.tol, o.criterion, o.max_iter, st));
+      if (X->profile) {
+        rc = sync_scal(X, st);
+        if (rc) return rc;
+      }
+      rc = run_loop<T>(X, omegaT, o, st);
+      if (rc) return rc;
+      inf.refined = 1;
+      inf.refine_iters = X->h_sc->iters;
+      inf.status = X->h_sc->status;
+      inf.resid_rec = ratio(X->h_sc->meas, X->h_sc->thresh2);
+      rc = fp64_phi_parts(X, X->beta64, omega64, st);
+      if (rc) return rc;
+      PPCG_TRY_HIP(launch_cg_start<T>(w, 2, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
+                                      X->p, o.tol, o.criterion, o.max_iter, st));
+      rc = sync_scal(X, st);
+      if (rc) return rc;
+      inf.resid_true = ratio(X->h_sc->true_meas, X->h_sc->thresh2);
+      inf.rms_precond = std::sqrt(X->h_sc->true_rm / (double)X->p);
+    }
+  }
+  if (info) *info = inf;
+  return inf.status;
+}
+
+// omega pointers for the two precisions: the caller's array when its dtype
+// matches, else the handle's FP64 copy filled by launch_prep.
+const double* omega_f64(ppcg_matrix* X, const void* omega, int dtype) {
+  return dtype == PPCG_F64 ? reinterpret_cast<const double*>(omega) : X->omega64;
+}
+
+int prepare(ppcg_matrix* X, const void* omega, const void* lambda, double tau, int dtype,
+            hipStream_t st) {
+  PPCG_TRY_HIP(launch_prep(lambda, omega, dtype, tau, X->n, X->p, X->d, X->m,
+                           dtype == PPCG_F64 ? nullptr : X->omega64, st));
+  return PPCG_OK;
+}
+
+int dispatch_solve(ppcg_matrix* X, const void* omega, int dtype, bool have_beta0,
+                   const ppcg_options& o, ppcg_info* info, hipStream_t st) {
+  const double* om64 = omega_f64(X, omega, dtype);
+  if (dtype == PPCG_F64)
+    return solve_core<double>(X, reinterpret_cast<const double*>(omega), om64, have_beta0, o,
+                              info, st);
+  return solve_core<float>(X, reinterpret_cast<const float*>(omega), om64, have_beta0, o, info,
+                           st);
+}
+
+bool bad_tau(double tau) { return !(tau > 0.0) || !std::isfinite(tau); }
+
+}  // namespace
+
+extern "C" {
+
+void ppcg_options_default(ppcg_options* opt, int32_t dtype) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->dtype = dtype;
+  opt->criterion = PPCG_REL_PRECOND;
+  opt->max_iter = 0;
+  opt->refine = -1;
+  opt->tol = 1e-6;
+  opt->true_resid = 1;
+  opt->check_every = 0;
+}
+
+const char* ppcg_status_string(int status) {
+  switch (status) {
+    case PPCG_OK: return "ok";
+    case PPCG_EINVAL: return "invalid argument";
+    case PPCG_ENOMEM: return "out of memory";
+    case PPCG_EHIP: return "HIP runtime error";
+    case PPCG_ENOTCONV: return "not converged within max_iter";
+    case PPCG_EBREAKDOWN: return "CG breakdown (<s, Phi s> <= 0 or non-finite)";
+    case PPCG_ENODEV: return "no HIP device";
+    default: return "unknown status";
+  }
+}
+
+const char* ppcg_version(void) { return "ppcg-mi355x 0.1 (gfx950)"; }
+
+int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
+                       const int64_t* row_ptr, const int32_t* col_idx, const void* values,
+                       int32_t mem, hipStream_t stream) {
+  try {
+    if (!out) return PPCG_EINVAL;
+    *out = nullptr;
+    if (n < 1 || p < 1 || nnz < 0 || values != nullptr || !row_ptr) return PPCG_EINVAL;
+    if (nnz > 0 && !col_idx) return PPCG_EINVAL;
+    if (n >= INT32_MAX || p >= INT32_MAX || nnz >= ((int64_t)INT32_MAX) * 1024) return PPCG_EINVAL;
+    if (mem != PPCG_MEM_HOST && mem != PPCG_MEM_DEVICE) return PPCG_EINVAL;
+
+    std::vector<int64_t> rp(n + 1);
+    std::vector<int32_t> ci(nnz);
+    if (mem == PPCG_MEM_HOST) {
+      std::memcpy(rp.data(), row_ptr, (n + 1) * sizeof(int64_t));
+      if (nnz) std::memcpy(ci.data(), col_idx, nnz * sizeof(int32_t));
+    } else {
+      int nd = 0;
+      if (hipGetDeviceCount(&nd) != hipSuccess || nd < 1) return PPCG_ENODEV;
+      PPCG_TRY_HIP(hipMemcpyAsync(rp.data(), row_ptr, (n + 1) * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, stream));
+      if (nnz)
+        PPCG_TRY_HIP(hipMemcpyAsync(ci.data(), col_idx, nnz * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, stream));
+      PPCG_TRY_HIP(hipStreamSynchronize(stream));
+    }
+    // Validate CSR: offsets monotone from 0 to nnz; columns in range and
+    // strictly increasing within a row (binary X has no duplicates).
+    if (rp[0] != 0 || rp[n] != nnz) return PPCG_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+      if (rp[i + 1] < rp[i]) return PPCG_EINVAL;
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int32_t c = ci[k];
+        if (c < 0 || c >= p) return PPCG_EINVAL;
+        if (k > rp[i] && c <= ci[k - 1]) return PPCG_EINVAL;
+      }
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PPCG_ENODEV;
+    // CSC twin by a counting sort over columns (rows stay increasing).
+    std::vector<int64_t> cp(p + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;
+    for (int64_t j = 0; j < p; ++j) cp[j + 1] += cp[j];
+    std::vector<int32_t> ri(nnz);
+    {
+      std::vector<int64_t> fill(cp.begin(), cp.end() - 1);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) ri[fill[ci[k]]++] = (int32_t)i;
+    }
+
+    ppcg_matrix* X = new (std::nothrow) ppcg_matrix();
+    if (!X) return PPCG_ENOMEM;
+    auto fail = [&](int rc) {
+      X->mem.release();
+      if (X->h_sc) (void)hipHostFree(X->h_sc);
+      delete X;
+      return rc;
+    };
+    X->n = n;
+    X->p = p;
+    X->nnz = nnz;
+    (void)hipGetDevice(&X->device);
+    X->chunk = kWG * chunk_from_env();
+
+    int32_t *dci = nullptr, *dri = nullptr;
+    hipError_t e;
+    if ((e = X->mem.alloc(&dci, nnz)) != hipSuccess) return fail(PPCG_ENOMEM);
+    if ((e = X->mem.alloc(&dri, nnz)) != hipSuccess) return fail(PPCG_ENOMEM);
+    if (nnz) {
+      if (hipMemcpy(dci, ci.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(PPCG_EHIP);
+      if (hipMemcpy(dri, ri.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(PPCG_EHIP);
+    }
+    HostTable hr, hc;
+    build_table(rp, nnz, X->chunk, hr);
+    build_table(cp, nnz, X->chunk, hc);
+    int rc = upload_table(X, hr, dci, nnz, X->csr);
+    if (rc) return fail(rc);
+    rc = upload_table(X, hc, dri, nnz, X->csc);
+    if (rc) return fail(rc);
+
+    const size_t N = (size_t)n, P = (size_t)p;
+    bool ok = X->mem.alloc(&X->u64, N) == hipSuccess && X->mem.alloc(&X->qx64, P) == hipSuccess &&
+              X->mem.alloc(&X->y64, N) == hipSuccess && X->mem.alloc(&X->omega64, N) == hipSuccess &&
+              X->mem.alloc(&X->d, P) == hipSuccess && X->mem.alloc(&X->m, P) == hipSuccess &&
+              X->mem.alloc(&X->b64, P) == hipSuccess && X->mem.alloc(&X->beta64, P) == hipSuccess &&
+              X->mem.alloc(&X->r64, P) == hipSuccess && X->mem.alloc(&X->s64, P) == hipSuccess &&
+              X->mem.alloc(&X->u32, N) == hipSuccess && X->mem.alloc(&X->qx32, P) == hipSuccess &&
+              X->mem.alloc(&X->s32, P) == hipSuccess &&
+              X->mem.alloc(&X->part, (size_t)kMaxRedBlocks * 4) == hipSuccess &&
+              X->mem.alloc(&X->sc, 1) == hipSuccess;
+    if (!ok) return fail(PPCG_ENOMEM);
+    // Empty rows / columns are never written by the passes: their outputs
+    // stay at the zero set here.
+    if (hipMemset(X->u64, 0, N * 8) != hipSuccess || hipMemset(X->qx64, 0, P * 8) != hipSuccess ||
+        hipMemset(X->u32, 0, N * 4) != hipSuccess || hipMemset(X->qx32, 0, P * 4) != hipSuccess ||
+        hipMemset(X->sc, 0, sizeof(DevScal)) != hipSuccess)
+      return fail(PPCG_EHIP);
+    if (hipHostMalloc(reinterpret_cast<void**>(&X->h_sc), sizeof(DevScal), 0) != hipSuccess) {
+      X->h_sc = nullptr;
+      return fail(PPCG_ENOMEM);
+    }
+    std::memset(X->h_sc, 0, sizeof(DevScal));
+    if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);
+    *out = X;
+    return PPCG_OK;
+  } catch (const std::bad_alloc&) {
+    return PPCG_ENOMEM;
+  } catch (...) {
+    return PPCG_EINVAL;
+  }
+}
+
+int ppcg_matrix_profile(ppcg_matrix* X, int32_t enable) {
+  if (!X) return PPCG_EINVAL;
+  X->profile = enable ? 1 : 0;
+  if (enable) {
+    X->pass_ms[0] = X->pass_ms[1] = 0.0;
+    X->pass_cnt[0] = X->pass_cnt[1] = 0;
+  }
+  return PPCG_OK;
+}
+
+int ppcg_matrix_stats(const ppcg_matrix* X, double* csr_ms, int64_t* csr_launches,
+                      double* csc_ms, int64_t* csc_launches) {
+  if (!X) return PPCG_EINVAL;
+  if (csr_ms) *csr_ms = X->pass_ms[0];
+  if (csr_launches) *csr_launches = X->pass_cnt[0];
+  if (csc_ms) *csc_ms = X->pass_ms[1];
+  if (csc_launches) *csc_launches = X->pass_cnt[1];
+  return PPCG_OK;
+}
+
+int ppcg_matrix_destroy(ppcg_matrix* X) {
+  if (!X) return PPCG_OK;
+  (void)hipDeviceSynchronize();
+  for (hipEvent_t e : X->ev) (void)hipEventDestroy(e);
+  X->mem.release();
+  if (X->h_sc) (void)hipHostFree(X->h_sc);
+  delete X;
+  return PPCG_OK;
+}
+
+int ppcg_matrix_shape(const ppcg_matrix* X, int64_t* n, int64_t* p, int64_t* nnz) {
+  if (!X) return PPCG_EINVAL;
+  if (n) *n = X->n;
+  if (p) *p = X->p;
+  if (nnz) *nnz = X->nnz;
+  return PPCG_OK;
+}
+
+int ppcg_phi_matvec(const ppcg_matrix* Xc, const void* omega, const void* lambda, double tau,
+                    const void* v, void* out, int32_t dtype, hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !omega || !lambda || !v || !out || !valid_dtype(dtype) || bad_tau(tau))
+    return PPCG_EINVAL;
+  int rc = prepare(X, omega, lambda, tau, dtype, st);
+  if (rc) return rc;
+  if (dtype == PPCG_F64) {
+    const double* om = reinterpret_cast<const double*>(omega);
+    const double* vv = reinterpret_cast<const double*>(v);
+    PPCG_TRY_HIP(launch_segsum<double>(X->csr, vv, om, X->u64, nullptr, st));
+    PPCG_TRY_HIP(launch_segsum<double>(X->csc, X->u64, nullptr, X->qx64, nullptr, st));
+    PPCG_TRY_HIP(launch_phi_finish<double>(X->qx64, X->d, vv, X->p, reinterpret_cast<double*>(out), st));
+  } else {
+    const float* om = reinterpret_cast<const float*>(omega);
+    const float* vv = reinterpret_cast<const float*>(v);
+    PPCG_TRY_HIP(launch_segsum<float>(X->csr, vv, om, X->u32, nullptr, st));
+    PPCG_TRY_HIP(launch_segsum<float>(X->csc, X->u32, nullptr, X->qx32, nullptr, st));
+    PPCG_TRY_HIP(launch_phi_finish<float>(X->qx32, X->d, vv, X->p, reinterpret_cast<float*>(out), st));
+  }
+  return PPCG_OK;
+}
+
+int ppcg_normals(uint64_t seed, uint64_t stream_id, uint64_t chain, uint64_t draw_index,
+                 int64_t count, double* out, hipStream_t st) {
+  if (count < 0 || (count > 0 && !out)) return PPCG_EINVAL;
+  PPCG_TRY_HIP(launch_normals(seed, stream_id, chain, draw_index, count, out, st));
+  return PPCG_OK;
+}
+
+static int form_rhs(ppcg_matrix* X, const void* omega, const void* z, const void* lambda,
+                    double tau, uint64_t seed, uint64_t chain, uint64_t draw, int dtype,
+                    double* b_out, hipStream_t st) {
+  int rc = prepare(X, omega, lambda, tau, dtype, st);
+  if (rc) return rc;
+  const double* om64 = omega_f64(X, omega, dtype);
+  PPCG_TRY_HIP(launch_y_draw(om64, z, dtype, seed, chain, draw, X->n, X->y64, st));
+  PPCG_TRY_HIP(launch_segsum<double>(X->csc, X->y64, nullptr, X->qx64, nullptr, st));
+  PPCG_TRY_HIP(launch_rhs_fin(X->qx64, lambda, dtype, tau, seed, chain, draw, X->p, b_out, st));
+  return PPCG_OK;
+}
+
+int ppcg_rhs(const ppcg_matrix* Xc, const void* omega, const void* z, const void* lambda,
+             double tau, uint64_t seed, uint64_t chain, uint64_t draw_index, int32_t dtype,
+             double* b_out, hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !omega || !z || !lambda || !b_out || !valid_dtype(dtype) || bad_tau(tau))
+    return PPCG_EINVAL;
+  return form_rhs(X, omega, z, lambda, tau, seed, chain, draw_index, dtype, b_out, st);
+}
+
+int ppcg_solve(const ppcg_matrix* Xc, const void* omega, const void* lambda, double tau,
+               const void* b, const void* beta0, const ppcg_options* opt, void* beta_out,
+               ppcg_info* info, hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !omega || !lambda || !b || !beta_out || bad_tau(tau)) return PPCG_EINVAL;
+  const ppcg_options o = resolve(opt, X->p);
+  if (check_opts(o)) return PPCG_EINVAL;
+  int rc = prepare(X, omega, lambda, tau, o.dtype, st);
+  if (rc) return rc;
+  PPCG_TRY_HIP(launch_convert_to_f64(b, o.dtype, X->p, X->b64, st));
+  if (beta0) PPCG_TRY_HIP(launch_convert_to_f64(beta0, o.dtype, X->p, X->beta64, st));
+  const int status = dispatch_solve(X, omega, o.dtype, beta0 != nullptr, o, info, st);
+  if (status == PPCG_EINVAL || status == PPCG_ENOMEM || status == PPCG_EHIP) return status;
+  PPCG_TRY_HIP(launch_convert_from_f64(X->beta64, o.dtype, X->p, beta_out, st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  return status;
+}
+
+int ppcg_draw(const ppcg_matrix* Xc, const void* omega, const void* z, const void* lambda,
+              double tau, uint64_t seed, uint64_t chain, uint64_t draw_index,
+              const ppcg_options* opt, void* beta_out, ppcg_info* info, hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !omega || !z || !lambda || !beta_out || bad_tau(tau)) return PPCG_EINVAL;
+  const ppcg_options o = resolve(opt, X->p);
+  if (check_opts(o)) return PPCG_EINVAL;
+  int rc = form_rhs(X, omega, z, lambda, tau, seed, chain, draw_index, o.dtype, X->b64, st);
+  if (rc) return rc;
+  const int status = dispatch_solve(X, omega, o.dtype, false, o, info, st);
+  if (status == PPCG_EINVAL || status == PPCG_ENOMEM || status == PPCG_EHIP) return status;
+  PPCG_TRY_HIP(launch_convert_from_f64(X->beta64, o.dtype, X->p, beta_out, st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  return status;
+}
+
+int ppcg_solve_backward(const ppcg_matrix* Xc, const void* omega, const void* lambda,
+                        double tau, const void* beta, const void* grad_beta,
+                        const ppcg_options* opt, void* grad_b, void* grad_loglambda,
+                        double* grad_logtau, ppcg_info* info, hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !omega || !lambda || !beta || !grad_beta || !grad_b || !grad_loglambda ||
+      !grad_logtau || bad_tau(tau))
+    return PPCG_EINVAL;
+  const ppcg_options o = resolve(opt, X->p);
+  if (check_opts(o)) return PPCG_EINVAL;
+  int rc = prepare(X, omega, lambda, tau, o.dtype, st);
+  if (rc) return rc;
+  PPCG_TRY_HIP(launch_convert_to_f64(grad_beta, o.dtype, X->p, X->b64, st));
+  const int status = dispatch_solve(X, omega, o.dtype, false, o, info, st);
+  if (status == PPCG_EINVAL || status == PPCG_ENOMEM || status == PPCG_EHIP) return status;
+  PPCG_TRY_HIP(launch_adjoint_epilogue(vw(X), X->beta64, beta, o.dtype, X->d, X->p, grad_b,
+                                       grad_loglambda, grad_logtau, st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  return status;
+}
+
+}  // extern "C"
