@@ -45,10 +45,10 @@ def parse():
 
 
 def pass_bytes(P, sv):
-    """Algorithmic bytes of one launch of each X pass (what the index-only
-    CSR/CSC format moves): the int32 index stream, the segment offsets and ids
-    of the non-empty segments, the per-chunk tables, the gathered vector read
-    once, the row scale (omega, row pass only) and the output."""
+    """Bytes one launch of each X pass would move in a plain int32 CSR / CSC
+    format (index stream, offsets, gathered vector once, scale, output); the
+    int32-equivalent rate of the 16-bit panel format is reported beside its
+    own."""
     nnz, n, p = P.nnz, P.n, P.p
     chunk = 2048
     nch = (nnz + chunk - 1) // chunk
@@ -153,7 +153,8 @@ def main():
     el, infos, st = run_form(pk, torch, X, P, pk.F32, args.steps, args.warmup, args.tol, True)
     iters = np.array([i["iters"] + i["refine_iters"] for i in infos], dtype=np.float64)
     K = float(iters.mean())
-    csr_b, csc_b = pass_bytes(P, 4)
+    csr_b, csc_b = X.pass_bytes(pk.F32)
+    csr_i32, csc_i32 = pass_bytes(P, 4)
     t_pass = (st["csr_ms"] + st["csc_ms"]) / max(st["csr_launches"] + st["csc_launches"], 1)
     bytes_per_launch = 0.5 * (csr_b + csc_b)
     achieved = bytes_per_launch / (t_pass * 1e-3) / 1e9
@@ -186,13 +187,14 @@ def main():
         "refined_draws": int(sum(i["refined"] for i in infos)),
         "max_true_resid_over_tol": float(max(i["resid_true"] for i in infos)),
         "roofline": {
-            "kernel": "k_segsum<float,8> (row pass u = omega.*(X s) and column pass q = X^T u)",
+            "kernel": "k_panel<float> (row pass X s and column pass X^T u)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
             "avg_launch_us": 1e3 * t_pass,
             "row_pass_us": 1e3 * st["csr_ms"] / max(st["csr_launches"], 1),
             "col_pass_us": 1e3 * st["csc_ms"] / max(st["csc_launches"], 1),
             "bytes_per_launch": bytes_per_launch,
+            "int32_csr_csc_equiv_gbps": 0.5 * (csr_i32 + csc_i32) / (t_pass * 1e-3) / 1e9,
         },
     }
     if not args.no_f64:
@@ -200,7 +202,7 @@ def main():
         print(f"[bench] timing FP64 form (1+{steps64} draws)", file=sys.stderr, flush=True)
         el64, inf64, st64 = run_form(pk, torch, X, P, pk.F64, steps64, 1, args.tol, True)
         it64 = np.array([i["iters"] + i["refine_iters"] for i in inf64], dtype=np.float64)
-        c64, s64 = pass_bytes(P, 8)
+        c64, s64 = X.pass_bytes(pk.F64)
         t64 = (st64["csr_ms"] + st64["csc_ms"]) / max(st64["csr_launches"] + st64["csc_launches"], 1)
         out["plain_f64"] = {
             "draws_per_s": steps64 / el64, "cg_iters_mean": float(it64.mean()),

@@ -87,7 +87,9 @@ typedef struct ppcg_options {
   double tol;         /* tolerance of the stopping rule (default 1e-6)           */
   int32_t true_resid; /* 1 (default): recompute b - Phi beta in FP64 at the end     */
   int32_t check_every;/* host convergence check period in iterations (0: default) */
-  int32_t reserved[6];
+  double loop_factor; /* the recursion runs to loop_factor * tol before the FP64
+                         check (0: default, 0.5 for F32 and 1 for F64)         */
+  int32_t reserved[4];
 } ppcg_options;
 
 typedef struct ppcg_info {
@@ -101,6 +103,8 @@ typedef struct ppcg_info {
                            not computed)                                            */
   double rms_precond;   /* p^-1/2 ||tau lambda (b - Phi beta)|| (the paper's measure) */
   double bnorm_precond; /* ||tau lambda b||                                         */
+  double resid_true_first; /* resid_true after the first phase, before any
+                              refinement (-1 when not computed)                   */
 } ppcg_info;
 
 /* Fills `opt` with the defaults listed above for the given dtype. */
@@ -218,6 +222,15 @@ int ppcg_matrix_profile(ppcg_matrix* X, int32_t enable);
  */
 int ppcg_matrix_stats(const ppcg_matrix* X, double* csr_ms, int64_t* csr_launches,
                       double* csc_ms, int64_t* csc_launches);
+
+/*
+ * Algorithmic bytes of one launch of each X pass in the handle's format for
+ * vectors of `dtype`: the 16-bit index stream with its chunk padding, the
+ * per-chunk tables, segment boundaries and output slots, the gathered
+ * vector read once, and the per-panel partial outputs.  Host-only.
+ */
+int ppcg_matrix_pass_bytes(const ppcg_matrix* X, int32_t dtype, int64_t* row_pass_bytes,
+                           int64_t* col_pass_bytes);
 
 #ifdef __cplusplus
 }

@@ -37,6 +37,7 @@ EXPORTED_SYMBOLS = (
     "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
     "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
     "ppcg_solve_backward", "ppcg_matrix_profile", "ppcg_matrix_stats",
+    "ppcg_matrix_pass_bytes",
 )
 
 
@@ -55,7 +56,8 @@ class Options(ctypes.Structure):
         ("dtype", ctypes.c_int32), ("criterion", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("refine", ctypes.c_int32),
         ("tol", ctypes.c_double), ("true_resid", ctypes.c_int32),
-        ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+        ("check_every", ctypes.c_int32), ("loop_factor", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -65,6 +67,7 @@ class Info(ctypes.Structure):
         ("refine_iters", ctypes.c_int32), ("refined", ctypes.c_int32),
         ("resid_rec", ctypes.c_double), ("resid_true", ctypes.c_double),
         ("rms_precond", ctypes.c_double), ("bnorm_precond", ctypes.c_double),
+        ("resid_true_first", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -97,7 +100,8 @@ def _declare(L):
     L.ppcg_matrix_profile.argtypes = [_vp, _i32]
     L.ppcg_matrix_stats.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64),
                                     ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]
-    for name in ("ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
+    L.ppcg_matrix_pass_bytes.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+    for name in ("ppcg_matrix_pass_bytes", "ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
                  "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
                  "ppcg_solve_backward"):
         getattr(L, name).restype = ctypes.c_int
@@ -227,13 +231,20 @@ class Matrix:
         return {"csr_ms": a.value, "csr_launches": na.value, "csc_ms": b.value,
                 "csc_launches": nb.value}
 
+    def pass_bytes(self, dtype):
+        """(row pass, column pass) algorithmic bytes of one launch for `dtype`."""
+        a, b = _i64(), _i64()
+        _check(lib().ppcg_matrix_pass_bytes(self.handle, int(dtype), ctypes.byref(a),
+                                            ctypes.byref(b)), "ppcg_matrix_pass_bytes")
+        return a.value, b.value
+
     @classmethod
     def from_problem(cls, P):
         return cls(P.n, P.p, P.row_ptr, P.col_idx)
 
 
 def make_options(dtype=F64, tol=1e-6, criterion=REL_PRECOND, max_iter=0, refine=-1,
-                 true_resid=1, check_every=0):
+                 true_resid=1, check_every=0, loop_factor=0.0):
     o = Options()
     lib().ppcg_options_default(ctypes.byref(o), int(dtype))
     o.tol = float(tol)
@@ -242,6 +253,7 @@ def make_options(dtype=F64, tol=1e-6, criterion=REL_PRECOND, max_iter=0, refine=
     o.refine = int(refine)
     o.true_resid = int(true_resid)
     o.check_every = int(check_every)
+    o.loop_factor = float(loop_factor)
     return o
 
 

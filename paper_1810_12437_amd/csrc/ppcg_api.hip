@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -13,6 +14,7 @@
 
 #include "../../include/ppcg.h"
 #include "ppcg_kernels.h"
+#include "ppcg_panels.h"
 
 using namespace ppcg;
 
@@ -36,28 +38,33 @@ struct DevBuf {
   }
 };
 
-struct HostTable {
-  std::vector<int64_t> ptr;     // non-empty segment offsets
-  std::vector<int32_t> sid;     // segment ids
-  std::vector<int64_t> cstart;  // chunk starts (+ nnz)
-  std::vector<int32_t> cseg, cnseg;
-  std::vector<int32_t> split_seg, split_c0, split_c1;
-  int32_t nchunks = 0;
-};
-
 }  // namespace
+
+// One orientation of X at one precision on the device.
+struct Orient {
+  PanelPass pass{};
+  void* part = nullptr;   // [npanels][out_dim] segment sums (zero where absent)
+  void* piece = nullptr;  // [nchunks] piece sums
+  const int32_t* sp_off = nullptr;
+  const int32_t* sp_c0 = nullptr;
+  const int32_t* sp_c1 = nullptr;
+  int32_t npanels = 0;
+  int64_t out_dim = 0;
+  int64_t dev_bytes = 0;
+  int64_t pass_bytes = 0;  // algorithmic bytes of one launch (inputs counted once)
+};
 
 struct ppcg_matrix {
   int64_t n = 0, p = 0, nnz = 0;
   int device = 0;
-  int chunk = 2048;
+  int ncu = 256;
   DevBuf mem;
-  SegTable csr{}, csc{};
+  Orient rows[2], cols[2];  // [0]: FP64 tables, [1]: FP32 tables
   // workspace
-  double *u64 = nullptr, *qx64 = nullptr, *y64 = nullptr, *omega64 = nullptr;
+  double *qx64 = nullptr, *y64 = nullptr, *omega64 = nullptr;
   double *d = nullptr, *m = nullptr, *b64 = nullptr, *beta64 = nullptr, *r64 = nullptr,
          *s64 = nullptr;
-  float *u32 = nullptr, *qx32 = nullptr, *s32 = nullptr;
+  float *qx32 = nullptr, *s32 = nullptr;
   double* part = nullptr;
   DevScal* sc = nullptr;
   DevScal* h_sc = nullptr;  // pinned host mirror
@@ -68,15 +75,15 @@ struct ppcg_matrix {
   int64_t pass_cnt[2] = {0, 0};
 };
 
-#define PPCG_TRY_HIP(expr)                    \
+#define PPCG_TRY_HIP(...)                     \
   do {                                        \
-    hipError_t _e = (expr);                   \
+    hipError_t _e = (__VA_ARGS__);            \
     if (_e != hipSuccess) return PPCG_EHIP;   \
   } while (0)
 
-#define PPCG_TRY_ALLOC(expr)                                               \
+#define PPCG_TRY_ALLOC(...)                                                \
   do {                                                                     \
-    hipError_t _e = (expr);                                                \
+    hipError_t _e = (__VA_ARGS__);                                         \
     if (_e == hipErrorOutOfMemory || _e == hipErrorMemoryAllocation)       \
       return PPCG_ENOMEM;                                                  \
     if (_e != hipSuccess) return PPCG_EHIP;                                \
@@ -87,83 +94,60 @@ namespace {
 // Non-empty segments and chunk table of one orientation given its offsets:
 // greedy packing of whole segments into chunks of at most C - 3 elements;
 // a segment longer than that becomes consecutive piece chunks.
-void build_table(const std::vector<int64_t>& off, int64_t nnz, int chunk, HostTable& t) {
-  const int64_t cap = chunk - 3;
-  const int64_t nseg_all = (int64_t)off.size() - 1;
-  t = HostTable();
-  for (int64_t s = 0; s < nseg_all; ++s) {
-    if (off[s + 1] > off[s]) {
-      t.ptr.push_back(off[s]);
-      t.sid.push_back((int32_t)s);
-    }
-  }
-  t.ptr.push_back(nnz);
-  const int64_t nseg = (int64_t)t.sid.size();
-  int64_t g = 0;
-  while (g < nseg) {
-    const int64_t len = t.ptr[g + 1] - t.ptr[g];
-    if (len > cap) {
-      const int32_t c0 = (int32_t)t.cstart.size();
-      for (int64_t o = t.ptr[g]; o < t.ptr[g + 1]; o += cap) {
-        t.cstart.push_back(o);
-        t.cseg.push_back((int32_t)g);
-        t.cnseg.push_back(0);
-      }
-      t.split_seg.push_back((int32_t)g);
-      t.split_c0.push_back(c0);
-      t.split_c1.push_back((int32_t)t.cstart.size() - 1);
-      ++g;
-    } else {
-      const int64_t start = t.ptr[g];
-      const int64_t first = g;
-      while (g < nseg && t.ptr[g + 1] - start <= cap) ++g;
-      t.cstart.push_back(start);
-      t.cseg.push_back((int32_t)first);
-      t.cnseg.push_back((int32_t)(g - first));
-    }
-  }
-  t.nchunks = (int32_t)t.cseg.size();
-  t.cstart.push_back(nnz);
-}
-
 template <typename V>
-int upload_vec(ppcg_matrix* X, const std::vector<V>& h, const V** out) {
+int upload_vec(ppcg_matrix* X, const std::vector<V>& h, const V** out, int64_t* bytes) {
   V* d = nullptr;
   PPCG_TRY_ALLOC(X->mem.alloc(&d, h.size()));
   if (!h.empty())
     PPCG_TRY_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
   *out = d;
+  *bytes += (int64_t)(h.size() * sizeof(V));
   return PPCG_OK;
 }
 
-int upload_table(ppcg_matrix* X, const HostTable& h, const int32_t* idx_dev, int64_t nnz,
-                 SegTable& t) {
+int upload_orient(ppcg_matrix* X, const PanelBuild& B, int elem, Orient& o) {
   int rc;
-  if ((rc = upload_vec(X, h.ptr, &t.ptr))) return rc;
-  if ((rc = upload_vec(X, h.sid, &t.sid))) return rc;
-  if ((rc = upload_vec(X, h.cstart, &t.cstart))) return rc;
-  if ((rc = upload_vec(X, h.cseg, &t.cseg))) return rc;
-  if ((rc = upload_vec(X, h.cnseg, &t.cnseg))) return rc;
-  if ((rc = upload_vec(X, h.split_seg, &t.split_seg))) return rc;
-  if ((rc = upload_vec(X, h.split_c0, &t.split_c0))) return rc;
-  if ((rc = upload_vec(X, h.split_c1, &t.split_c1))) return rc;
-  double* part = nullptr;
-  PPCG_TRY_ALLOC(X->mem.alloc(&part, h.nchunks));
-  t.part = part;
-  t.idx = idx_dev;
-  t.nnz = nnz;
-  t.nseg = (int32_t)h.sid.size();
-  t.nchunks = h.nchunks;
-  t.nsplit = (int32_t)h.split_seg.size();
-  t.chunk = X->chunk;
+  int64_t by = 0;
+  PanelPass& t = o.pass;
+  if ((rc = upload_vec(X, B.idx, &t.idx, &by))) return rc;
+  if ((rc = upload_vec(X, B.cstart, &t.cstart, &by))) return rc;
+  if ((rc = upload_vec(X, B.cseg, &t.cseg, &by))) return rc;
+  if ((rc = upload_vec(X, B.cnseg, &t.cnseg, &by))) return rc;
+  if ((rc = upload_vec(X, B.cboff, &t.cboff, &by))) return rc;
+  if ((rc = upload_vec(X, B.bound16, &t.bound16, &by))) return rc;
+  if ((rc = upload_vec(X, B.seg_out, &t.seg_out, &by))) return rc;
+  if ((rc = upload_vec(X, B.wg_panel, &t.wg_panel, &by))) return rc;
+  if ((rc = upload_vec(X, B.wg_c0, &t.wg_c0, &by))) return rc;
+  if ((rc = upload_vec(X, B.wg_c1, &t.wg_c1, &by))) return rc;
+  if (!B.sp_off.empty()) {
+    if ((rc = upload_vec(X, B.sp_off, &o.sp_off, &by))) return rc;
+    if ((rc = upload_vec(X, B.sp_c0, &o.sp_c0, &by))) return rc;
+    if ((rc = upload_vec(X, B.sp_c1, &o.sp_c1, &by))) return rc;
+  }
+  t.gdim = B.gdim;
+  t.W = B.W;
+  t.nwg = (int32_t)B.wg_panel.size();
+  t.nchunks = (int32_t)B.cseg.size();
+  o.npanels = B.npanels;
+  o.out_dim = B.out_dim;
+  const size_t part_bytes = (size_t)B.npanels * (size_t)B.out_dim * (size_t)elem;
+  unsigned char* part = nullptr;
+  unsigned char* piece = nullptr;
+  PPCG_TRY_ALLOC(X->mem.alloc(&part, part_bytes));
+  PPCG_TRY_ALLOC(X->mem.alloc(&piece, (size_t)std::max<int32_t>(t.nchunks, 1) * elem));
+  // (segment, panel) pairs with no elements are never written: they stay zero.
+  PPCG_TRY_HIP(hipMemset(part, 0, std::max<size_t>(part_bytes, 1)));
+  o.part = part;
+  o.piece = piece;
+  o.dev_bytes = by + (int64_t)part_bytes + (int64_t)t.nchunks * elem;
+  // Per launch: index stream, chunk tables (cstart, cseg, cnseg, cboff),
+  // boundaries, output slots, one segment sum per (segment, panel), and the
+  // gathered vector once (its panel copies come from cache).
+  const int64_t nseg = (int64_t)B.seg_out.size();
+  o.pass_bytes = 2 * (int64_t)B.idx.size() + 20 * (int64_t)t.nchunks +
+                 2 * (int64_t)B.bound16.size() + 4 * nseg + (int64_t)elem * nseg +
+                 (int64_t)elem * B.gdim;
   return PPCG_OK;
-}
-
-int chunk_from_env() {
-  const char* s = std::getenv("PPCG_CHUNK_V");
-  if (!s) return 8;
-  const int v = std::atoi(s);
-  return (v == 4 || v == 8 || v == 16) ? v : 8;
 }
 
 bool valid_dtype(int32_t d) { return d == PPCG_F64 || d == PPCG_F32; }
@@ -185,15 +169,65 @@ int check_opts(const ppcg_options& o) {
   if (!valid_dtype(o.dtype)) return PPCG_EINVAL;
   if (o.criterion < 0 || o.criterion > 2) return PPCG_EINVAL;
   if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return PPCG_EINVAL;
+  if (!(o.loop_factor >= 0.0) || !(o.loop_factor <= 1.0)) return PPCG_EINVAL;
   return PPCG_OK;
 }
 
 VecWork vw(ppcg_matrix* X) { return VecWork{X->part, X->sc}; }
 
-// FP64 product parts: u64 = omega .* (X x), qx64 = X^T u64.
+template <typename T>
+constexpr int prec_index() {
+  return sizeof(T) == 8 ? 0 : 1;
+}
+
+template <typename T>
+Combine<T> comb_vec(const T* v) {
+  Combine<T> c{};
+  c.part = v;
+  c.stride = 0;
+  c.nparts = 1;
+  return c;
+}
+
+// The consumer's view of an orientation's pass output (optionally scaled).
+template <typename T>
+Combine<T> comb_out(const Orient& o, const T* scale) {
+  Combine<T> c{};
+  c.part = reinterpret_cast<const T*>(o.part);
+  c.stride = o.out_dim;
+  c.nparts = o.npanels;
+  c.scale = scale;
+  c.sp_off = o.sp_off;
+  c.sp_c0 = o.sp_c0;
+  c.sp_c1 = o.sp_c1;
+  c.piece = reinterpret_cast<const T*>(o.piece);
+  return c;
+}
+
+// Row pass: segment sums of X x (omega is applied by the consumer).
+template <typename T>
+hipError_t row_pass(ppcg_matrix* X, const Combine<T>& x, const int32_t* done, hipStream_t st) {
+  Orient& o = X->rows[prec_index<T>()];
+  return launch_panel_pass<T>(o.pass, x, reinterpret_cast<T*>(o.part),
+                              reinterpret_cast<T*>(o.piece), done, st);
+}
+
+// Column pass: segment sums of X^T u with u = omega .* (X x) from the row pass.
+template <typename T>
+hipError_t col_pass(ppcg_matrix* X, const T* omega, const Combine<T>* y, const int32_t* done,
+                    hipStream_t st) {
+  Orient& o = X->cols[prec_index<T>()];
+  const Combine<T> u = y ? *y : comb_out<T>(X->rows[prec_index<T>()], omega);
+  return launch_panel_pass<T>(o.pass, u, reinterpret_cast<T*>(o.part),
+                              reinterpret_cast<T*>(o.piece), done, st);
+}
+
+// FP64 product part qx64 = X^T (omega .* (X x)).
 int fp64_phi_parts(ppcg_matrix* X, const double* x, const double* omega64, hipStream_t st) {
-  PPCG_TRY_HIP(launch_segsum<double>(X->csr, x, omega64, X->u64, nullptr, st));
-  PPCG_TRY_HIP(launch_segsum<double>(X->csc, X->u64, nullptr, X->qx64, nullptr, st));
+  PPCG_TRY_HIP(row_pass<double>(X, comb_vec<double>(x), nullptr, st));
+  PPCG_TRY_HIP(col_pass<double>(X, omega64, nullptr, nullptr, st));
+  PPCG_TRY_HIP(launch_combine<double, double>(comb_out<double>(X->cols[0], nullptr), X->p,
+                                              X->qx64, st));
   return PPCG_OK;
 }
 
@@ -202,13 +236,11 @@ struct Bufs;
 template <>
 struct Bufs<double> {
   static double* s(ppcg_matrix* X) { return X->s64; }
-  static double* u(ppcg_matrix* X) { return X->u64; }
   static double* qx(ppcg_matrix* X) { return X->qx64; }
 };
 template <>
 struct Bufs<float> {
   static float* s(ppcg_matrix* X) { return X->s32; }
-  static float* u(ppcg_matrix* X) { return X->u32; }
   static float* qx(ppcg_matrix* X) { return X->qx32; }
 };
 
@@ -222,10 +254,11 @@ int sync_scal(ppcg_matrix* X, hipStream_t st) {
 template <typename T>
 int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t st) {
   T* s = Bufs<T>::s(X);
-  T* u = Bufs<T>::u(X);
   T* qx = Bufs<T>::qx(X);
   const int32_t* done = &X->sc->done;
   const VecWork w = vw(X);
+  const Combine<T> svec = comb_vec<T>(s);
+  const Combine<T> qsrc = comb_out<T>(X->cols[prec_index<T>()], nullptr);
   const bool prof = X->profile != 0;
   if (prof && (int)X->ev.size() < 4 * o.check_every) {
     while ((int)X->ev.size() < 4 * o.check_every) {
@@ -239,11 +272,11 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
     if (prof) active_before = X->h_sc->done ? 0 : 1;
     for (int i = 0; i < o.check_every; ++i) {
       if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 0], st));
-      PPCG_TRY_HIP(launch_segsum<T>(X->csr, s, omegaT, u, done, st));
+      PPCG_TRY_HIP(row_pass<T>(X, svec, done, st));
       if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 1], st));
-      PPCG_TRY_HIP(launch_segsum<T>(X->csc, u, nullptr, qx, done, st));
+      PPCG_TRY_HIP(col_pass<T>(X, omegaT, nullptr, done, st));
       if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 2], st));
-      PPCG_TRY_HIP(launch_cg_dot<T>(w, s, qx, X->d, X->p, st));
+      PPCG_TRY_HIP(launch_cg_dot<T>(w, s, qsrc, qx, X->d, X->p, st));
       PPCG_TRY_HIP(launch_cg_update<T>(w, s, qx, X->d, X->m, X->beta64, X->r64, X->p, st));
       PPCG_TRY_HIP(launch_cg_direction<T>(w, X->m, X->r64, s, X->p, st));
     }
@@ -267,7 +300,6 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
   }
 }
 
-
 double ratio(double meas, double thresh2) {
   if (thresh2 > 0.0) return std::sqrt(meas / thresh2);
   return meas > 0.0 ? std::numeric_limits<double>::infinity() : 0.0;
@@ -286,8 +318,13 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
     if (rc) return rc;
     qx0 = X->qx64;
   }
+  // The FP32 form runs its recursion to half the tolerance: its recursive
+  // residual drifts from the true one by about the FP32 rounding of the
+  // products, and the margin lets the FP64 check pass without a replacement.
+  const double loop_factor =
+      o.loop_factor > 0.0 ? o.loop_factor : ((sizeof(T) == 4) ? 0.5 : 1.0);
   PPCG_TRY_HIP(launch_cg_start<T>(w, 0, X->b64, qx0, X->d, X->m, X->beta64, X->r64, s, X->p,
-                                  o.tol, o.criterion, o.max_iter, st));
+                                  o.tol, o.criterion, o.max_iter, loop_factor, st));
   if (X->profile) {
     int rc0 = sync_scal(X, st);
     if (rc0) return rc0;
@@ -299,22 +336,24 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
   inf.iters = X->h_sc->iters;
   inf.resid_rec = ratio(X->h_sc->meas, X->h_sc->thresh2);
   inf.resid_true = -1.0;
+  inf.resid_true_first = -1.0;
   inf.bnorm_precond = std::sqrt(X->h_sc->bm2);
   inf.rms_precond = -1.0;
   if (o.true_resid || o.refine) {
     rc = fp64_phi_parts(X, X->beta64, omega64, st);
     if (rc) return rc;
     PPCG_TRY_HIP(launch_cg_start<T>(w, 2, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
-                                    X->p, o.tol, o.criterion, o.max_iter, st));
+                                    X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
     rc = sync_scal(X, st);
     if (rc) return rc;
     inf.resid_true = ratio(X->h_sc->true_meas, X->h_sc->thresh2);
+    inf.resid_true_first = inf.resid_true;
     inf.rms_precond = std::sqrt(X->h_sc->true_rm / (double)X->p);
     if (o.refine && inf.status == PPCG_OK && X->h_sc->true_meas > X->h_sc->thresh2) {
-      // Restart once from the FP64 true residual r = b - Phi beta (qx64 holds
-      // the product parts of the current beta).
+      // One refinement: restart CG from the FP64 true residual
+      // b - Phi beta (qx64 holds the product part of the current beta).
       PPCG_TRY_HIP(launch_cg_start<T>(w, 1, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
-                                      X->p, o.tol, o.criterion, o.max_iter, st));
+                                      X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
       if (X->profile) {
         rc = sync_scal(X, st);
         if (rc) return rc;
@@ -328,7 +367,7 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
       rc = fp64_phi_parts(X, X->beta64, omega64, st);
       if (rc) return rc;
       PPCG_TRY_HIP(launch_cg_start<T>(w, 2, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
-                                      X->p, o.tol, o.criterion, o.max_iter, st));
+                                      X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
       rc = sync_scal(X, st);
       if (rc) return rc;
       inf.resid_true = ratio(X->h_sc->true_meas, X->h_sc->thresh2);
@@ -456,44 +495,40 @@ int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
     X->n = n;
     X->p = p;
     X->nnz = nnz;
-    (void)hipGetDevice(&X->device);
-    X->chunk = kWG * chunk_from_env();
+    if (hipGetDevice(&X->device) != hipSuccess) return fail(PPCG_EHIP);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, X->device) !=
+            hipSuccess || ncu < 1)
+      ncu = 256;
+    X->ncu = ncu;
+    if (setup_pass_kernels() != hipSuccess) return fail(PPCG_EHIP);
 
-    int32_t *dci = nullptr, *dri = nullptr;
-    hipError_t e;
-    if ((e = X->mem.alloc(&dci, nnz)) != hipSuccess) return fail(PPCG_ENOMEM);
-    if ((e = X->mem.alloc(&dri, nnz)) != hipSuccess) return fail(PPCG_ENOMEM);
-    if (nnz) {
-      if (hipMemcpy(dci, ci.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
-        return fail(PPCG_EHIP);
-      if (hipMemcpy(dri, ri.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
-        return fail(PPCG_EHIP);
+    // Panel-blocked index-only tables of both orientations, for FP64 and
+    // FP32 gathered values (the panel width depends on the value size).
+    {
+      PanelBuild B;
+      for (int pi = 0; pi < 2; ++pi) {
+        const int elem = pi == 0 ? 8 : 4;
+        build_panels(rp, ci, n, p, elem, ncu, B);
+        int rc = upload_orient(X, B, elem, X->rows[pi]);
+        if (rc) return fail(rc);
+        build_panels(cp, ri, p, n, elem, ncu, B);
+        rc = upload_orient(X, B, elem, X->cols[pi]);
+        if (rc) return fail(rc);
+      }
     }
-    HostTable hr, hc;
-    build_table(rp, nnz, X->chunk, hr);
-    build_table(cp, nnz, X->chunk, hc);
-    int rc = upload_table(X, hr, dci, nnz, X->csr);
-    if (rc) return fail(rc);
-    rc = upload_table(X, hc, dri, nnz, X->csc);
-    if (rc) return fail(rc);
 
     const size_t N = (size_t)n, P = (size_t)p;
-    bool ok = X->mem.alloc(&X->u64, N) == hipSuccess && X->mem.alloc(&X->qx64, P) == hipSuccess &&
-              X->mem.alloc(&X->y64, N) == hipSuccess && X->mem.alloc(&X->omega64, N) == hipSuccess &&
+    bool ok = X->mem.alloc(&X->qx64, P) == hipSuccess && X->mem.alloc(&X->y64, N) == hipSuccess &&
+              X->mem.alloc(&X->omega64, N) == hipSuccess &&
               X->mem.alloc(&X->d, P) == hipSuccess && X->mem.alloc(&X->m, P) == hipSuccess &&
               X->mem.alloc(&X->b64, P) == hipSuccess && X->mem.alloc(&X->beta64, P) == hipSuccess &&
               X->mem.alloc(&X->r64, P) == hipSuccess && X->mem.alloc(&X->s64, P) == hipSuccess &&
-              X->mem.alloc(&X->u32, N) == hipSuccess && X->mem.alloc(&X->qx32, P) == hipSuccess &&
-              X->mem.alloc(&X->s32, P) == hipSuccess &&
+              X->mem.alloc(&X->qx32, P) == hipSuccess && X->mem.alloc(&X->s32, P) == hipSuccess &&
               X->mem.alloc(&X->part, (size_t)kMaxRedBlocks * 4) == hipSuccess &&
               X->mem.alloc(&X->sc, 1) == hipSuccess;
     if (!ok) return fail(PPCG_ENOMEM);
-    // Empty rows / columns are never written by the passes: their outputs
-    // stay at the zero set here.
-    if (hipMemset(X->u64, 0, N * 8) != hipSuccess || hipMemset(X->qx64, 0, P * 8) != hipSuccess ||
-        hipMemset(X->u32, 0, N * 4) != hipSuccess || hipMemset(X->qx32, 0, P * 4) != hipSuccess ||
-        hipMemset(X->sc, 0, sizeof(DevScal)) != hipSuccess)
-      return fail(PPCG_EHIP);
+    if (hipMemset(X->sc, 0, sizeof(DevScal)) != hipSuccess) return fail(PPCG_EHIP);
     if (hipHostMalloc(reinterpret_cast<void**>(&X->h_sc), sizeof(DevScal), 0) != hipSuccess) {
       X->h_sc = nullptr;
       return fail(PPCG_ENOMEM);
@@ -529,6 +564,15 @@ int ppcg_matrix_stats(const ppcg_matrix* X, double* csr_ms, int64_t* csr_launche
   return PPCG_OK;
 }
 
+int ppcg_matrix_pass_bytes(const ppcg_matrix* X, int32_t dtype, int64_t* row_pass_bytes,
+                           int64_t* col_pass_bytes) {
+  if (!X || !valid_dtype(dtype)) return PPCG_EINVAL;
+  const int pi = dtype == PPCG_F64 ? 0 : 1;
+  if (row_pass_bytes) *row_pass_bytes = X->rows[pi].pass_bytes;
+  if (col_pass_bytes) *col_pass_bytes = X->cols[pi].pass_bytes;
+  return PPCG_OK;
+}
+
 int ppcg_matrix_destroy(ppcg_matrix* X) {
   if (!X) return PPCG_OK;
   (void)hipDeviceSynchronize();
@@ -557,15 +601,21 @@ int ppcg_phi_matvec(const ppcg_matrix* Xc, const void* omega, const void* lambda
   if (dtype == PPCG_F64) {
     const double* om = reinterpret_cast<const double*>(omega);
     const double* vv = reinterpret_cast<const double*>(v);
-    PPCG_TRY_HIP(launch_segsum<double>(X->csr, vv, om, X->u64, nullptr, st));
-    PPCG_TRY_HIP(launch_segsum<double>(X->csc, X->u64, nullptr, X->qx64, nullptr, st));
-    PPCG_TRY_HIP(launch_phi_finish<double>(X->qx64, X->d, vv, X->p, reinterpret_cast<double*>(out), st));
+    PPCG_TRY_HIP(row_pass<double>(X, comb_vec<double>(vv), nullptr, st));
+    PPCG_TRY_HIP(col_pass<double>(X, om, nullptr, nullptr, st));
+    PPCG_TRY_HIP(launch_combine<double, double>(comb_out<double>(X->cols[0], nullptr), X->p,
+                                                X->qx64, st));
+    PPCG_TRY_HIP(launch_phi_finish<double>(X->qx64, X->d, vv, X->p,
+                                           reinterpret_cast<double*>(out), st));
   } else {
     const float* om = reinterpret_cast<const float*>(omega);
     const float* vv = reinterpret_cast<const float*>(v);
-    PPCG_TRY_HIP(launch_segsum<float>(X->csr, vv, om, X->u32, nullptr, st));
-    PPCG_TRY_HIP(launch_segsum<float>(X->csc, X->u32, nullptr, X->qx32, nullptr, st));
-    PPCG_TRY_HIP(launch_phi_finish<float>(X->qx32, X->d, vv, X->p, reinterpret_cast<float*>(out), st));
+    PPCG_TRY_HIP(row_pass<float>(X, comb_vec<float>(vv), nullptr, st));
+    PPCG_TRY_HIP(col_pass<float>(X, om, nullptr, nullptr, st));
+    PPCG_TRY_HIP(launch_combine<float, float>(comb_out<float>(X->cols[1], nullptr), X->p,
+                                              X->qx32, st));
+    PPCG_TRY_HIP(launch_phi_finish<float>(X->qx32, X->d, vv, X->p,
+                                          reinterpret_cast<float*>(out), st));
   }
   return PPCG_OK;
 }
@@ -584,7 +634,10 @@ static int form_rhs(ppcg_matrix* X, const void* omega, const void* z, const void
   if (rc) return rc;
   const double* om64 = omega_f64(X, omega, dtype);
   PPCG_TRY_HIP(launch_y_draw(om64, z, dtype, seed, chain, draw, X->n, X->y64, st));
-  PPCG_TRY_HIP(launch_segsum<double>(X->csc, X->y64, nullptr, X->qx64, nullptr, st));
+  const Combine<double> y = comb_vec<double>(X->y64);
+  PPCG_TRY_HIP(col_pass<double>(X, nullptr, &y, nullptr, st));
+  PPCG_TRY_HIP(launch_combine<double, double>(comb_out<double>(X->cols[0], nullptr), X->p,
+                                              X->qx64, st));
   PPCG_TRY_HIP(launch_rhs_fin(X->qx64, lambda, dtype, tau, seed, chain, draw, X->p, b_out, st));
   return PPCG_OK;
 }

@@ -4,34 +4,56 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ppcg_layout.h"
+
 namespace ppcg {
 
 constexpr int kWG = 256;            // threads per workgroup (4 wavefronts of 64)
 constexpr int kMaxRedBlocks = 1024; // max workgroups of a p-vector phase
 
-// Chunked segment table: the non-empty segments (rows of CSR or columns of
-// CSC) of one orientation of X, cut into chunks of at most C - 3 elements
-// (C = kWG * V) along segment boundaries.  A chunk either packs whole
-// segments (cnseg > 0) or is one piece of a segment longer than a chunk
-// (cnseg == 0); the pieces of such a split segment are summed, in chunk
-// order, by a follow-up kernel.  A chunk is processed from the 16-byte
-// aligned element start & ~3, so its index loads are aligned.
-struct SegTable {
-  const int64_t* ptr;    // [nseg + 1] offsets of the non-empty segments
-  const int32_t* sid;    // [nseg] original row / column id of each segment
-  const int32_t* idx;    // [nnz] gathered index of each element
-  const int64_t* cstart; // [nchunks + 1] first element of each chunk; last = nnz
-  const int32_t* cseg;   // [nchunks] first (or split) segment of the chunk
-  const int32_t* cnseg;  // [nchunks] whole segments in the chunk; 0 for a piece
-  void* part;            // [nchunks] piece sums (T)
-  const int32_t* split_seg; // [nsplit] segments longer than a chunk
-  const int32_t* split_c0;  // [nsplit] their first piece chunk
-  const int32_t* split_c1;  // [nsplit] their last piece chunk
-  int64_t nnz;
-  int32_t nseg;
+// ---- X passes ----
+// One orientation of X (rows of CSR for v -> X v, columns of CSC for
+// w -> X^T w) in a panel-blocked, index-only layout.  The gathered
+// dimension is cut into panels of at most W entries so that a panel of the
+// gathered vector fits in LDS; within panel k the non-empty (segment, panel)
+// pairs are stored consecutively with 16-bit indices local to the panel.
+// The element stream is cut into chunks along segment boundaries, each
+// padded to a multiple of kPPad with the index W (an LDS zero): a packed
+// chunk (cnseg > 0) holds whole segments in one window of kPC elements, a
+// long chunk (cnseg == 0) is one segment summed whole, and a piece
+// (cnseg < 0) is part of a segment longer than kPLongMax whose piece sums
+// the consumer adds.  Workgroup w serves one panel and owns the chunk range
+// [wg_c0[w], wg_c1[w]).
+struct PanelPass {
+  const uint16_t* idx;     // [nnz] panel-local gathered index
+  const int64_t* cstart;   // [nchunks + 1] first element of each chunk; last = nnz
+  const int32_t* cseg;     // [nchunks] first segment (or the split segment)
+  const int32_t* cnseg;    // [nchunks] segments in a packed chunk; 0 for a piece
+  const int32_t* cboff;    // [nchunks] offset of the chunk's boundaries in bound16
+  const int16_t* bound16;  // segment boundaries relative to the chunk window
+  const int32_t* seg_out;  // [nseg] output slot = panel * out_dim + segment id
+  const int32_t* wg_panel; // [nwg]
+  const int32_t* wg_c0;    // [nwg]
+  const int32_t* wg_c1;    // [nwg]
+  int64_t gdim;            // gathered dimension (p for rows, n for columns)
+  int32_t W;               // panel width
+  int32_t nwg;
   int32_t nchunks;
-  int32_t nsplit;
-  int32_t chunk;         // C
+};
+
+// value(i) = scale[i] * (sum_k part[k * stride + i] + sum of the pieces of i):
+// the input a pass gathers, or the consumer's view of a pass output.
+template <typename T>
+struct Combine {
+  const T* part;
+  int64_t stride;
+  int32_t nparts;
+  int32_t pad;
+  const T* scale;         // may be null
+  const int32_t* sp_off;  // [dim + 1] pieces of element i (null: none)
+  const int32_t* sp_c0;   // piece chunk ranges [c0, c1]
+  const int32_t* sp_c1;
+  const T* piece;         // [nchunks] piece sums
 };
 
 // Scalars of one CG run, in device memory.
@@ -41,6 +63,8 @@ struct DevScal {
   double betacg;   // direction update ratio
   double sq;       // <s, Phi s>
   double thresh2;  // squared threshold of the stopping rule
+  double loop2;    // squared threshold the recursive residual is run to
+  double rho_prev; // rho of the previous iteration
   double bm2;      // <b, M^-1 b>
   double bb;       // <b, b>
   double rr;       // <r, r>
@@ -63,10 +87,18 @@ struct VecWork {
 };
 
 // ---- launchers (all asynchronous on `st`) ----
-// out = scale .* (X-orientation sum of x): a segmented gather-sum pass.
+// One X pass: gathers value(x, .) panel by panel and writes the segment sums
+// of panel k to part_out[k * out_dim + id], piece sums to piece_out.
 template <typename T>
-hipError_t launch_segsum(const SegTable& t, const T* x, const T* scale, T* out,
-                         const int32_t* done, hipStream_t st);
+hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
+                             T* piece_out, const int32_t* done, hipStream_t st);
+
+// out[i] = value(c, i) for i < dim.
+template <typename T, typename U>
+hipError_t launch_combine(const Combine<T>& c, int64_t dim, U* out, hipStream_t st);
+
+// Maximum dynamic LDS the pass kernels may use (call once per device).
+hipError_t setup_pass_kernels();
 
 hipError_t launch_prep(const void* lambda, const void* omega, int dtype, double tau,
                        int64_t n, int64_t p, double* d, double* m, double* omega64,
@@ -92,20 +124,24 @@ template <typename T>
 hipError_t launch_phi_finish(const T* qx, const double* d, const T* v, int64_t p, T* out,
                              hipStream_t st);
 
-// CG start / restart.  If qx64 != NULL, r = b - qx64 - d .* beta, else r = b
-// (beta must then be zero).  z = m .* r, s = z.  mode 0: fresh start (computes
-// <b,Mb>, <b,b>, threshold); mode 1: restart (keeps the threshold); mode 2:
-// true-residual check only (no state change, writes true_meas / true_rm).
+// CG start and restart.  If qx64 != NULL, r = b - qx64 - d .* beta, else
+// r = b (beta must then be zero).  z = M^-1 r, s = z.
+// mode 0: fresh start: also computes <b,Mb>, <b,b> and the thresholds (the
+//         recursion runs to loop_factor * tol);
+// mode 1: restart from the FP64 true residual of the current beta (keeps the
+//         thresholds);
+// mode 2: true-residual check only (no state change; writes true_meas, true_rm).
 template <typename T>
 hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
                            const double* d, const double* m, double* beta, double* r,
                            T* s, int64_t p, double tol, int criterion, int max_iter,
-                           hipStream_t st);
+                           double loop_factor, hipStream_t st);
 
-// One CG iteration's vector phases after the matvec q = qx + d .* s.
+// One CG iteration's vector phases after the matvec q = qx + d .* s.  The
+// dot phase assembles qx from the column pass's panel partials and writes it.
 template <typename T>
-hipError_t launch_cg_dot(VecWork w, const T* s, const T* qx, const double* d, int64_t p,
-                         hipStream_t st);
+hipError_t launch_cg_dot(VecWork w, const T* s, const Combine<T>& qsrc, T* qx,
+                         const double* d, int64_t p, hipStream_t st);
 template <typename T>
 hipError_t launch_cg_update(VecWork w, const T* s, const T* qx, const double* d,
                             const double* m, double* beta, double* r, int64_t p,

@@ -98,116 +98,183 @@ __device__ __forceinline__ void gather_totals(const double* part, uint32_t* ctr,
 }
 
 // ------------------------------------------------------------------------
-// segmented gather-sum pass: out[sid[g]] = scale[sid[g]] * sum_{e in g} x[idx[e]]
+// X pass: panel-resident gathers, one wavefront per chunk
 // ------------------------------------------------------------------------
-template <typename T, int V>
-__global__ __launch_bounds__(kWG) void k_segsum(SegTable t, const T* __restrict__ x,
-                                                const T* __restrict__ scale,
-                                                T* __restrict__ out,
-                                                const int32_t* __restrict__ done) {
-  if (done != nullptr && *done) return;
-  constexpr int C = kWG * V;
-  __shared__ int32_t lptr[C + 2];
-  __shared__ int32_t wkey[kWG / 64];
-  __shared__ T wval[kWG / 64];
-
-  const int c = blockIdx.x;
-  const int64_t cs = t.cstart[c], ce = t.cstart[c + 1];
-  const int64_t base = cs & ~(int64_t)3;  // aligned start; [base, cs) is masked
-  const int lo = (int)(cs - base);
-  const int len = (int)(ce - base);  // <= C
-  const int sf = t.cseg[c];
-  const int nsg = t.cnseg[c];
-
-  for (int k = threadIdx.x; k <= nsg; k += kWG) lptr[k] = (int32_t)(t.ptr[sf + k] - base);
-
-  // Stream this thread's V indices (non-temporal: read once per pass) and
-  // gather x; the gathered vector stays in cache.
-  const int e0 = threadIdx.x * V;
-  T xv[V];
-  if (e0 + V <= len) {
-    const int4v* ip = reinterpret_cast<const int4v*>(t.idx + base + e0);
-    int32_t ix[V];
+template <typename T>
+__device__ __forceinline__ T combine_at(const Combine<T>& c, int64_t i) {
+  // Issue up to eight partial loads before adding them (fixed order).
+  T pv[8];
 #pragma unroll
-    for (int q = 0; q < V / 4; ++q) {
-      int4v w4 = __builtin_nontemporal_load(ip + q);
-      ix[4 * q + 0] = w4.x;
-      ix[4 * q + 1] = w4.y;
-      ix[4 * q + 2] = w4.z;
-      ix[4 * q + 3] = w4.w;
+  for (int k = 0; k < 8; ++k) pv[k] = (k < c.nparts) ? c.part[(int64_t)k * c.stride + i] : T(0);
+  T v = pv[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (k < c.nparts) v += pv[k];
+  for (int k = 8; k < c.nparts; ++k) v += c.part[(int64_t)k * c.stride + i];
+  if (c.sp_off != nullptr) {
+    const int q1 = c.sp_off[i + 1];
+    for (int q = c.sp_off[i]; q < q1; ++q) {
+      const int c1 = c.sp_c1[q];
+      for (int cc = c.sp_c0[q]; cc <= c1; ++cc) v += c.piece[cc];
+    }
+  }
+  return c.scale ? v * c.scale[i] : v;
+}
+
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// Registers of one chunk in flight: its bounds, this lane's kPV indices of
+// the chunk's first window, and the segment boundaries / output slots of a
+// packed chunk spread over the lanes (entry k at lane k % 64, slot k / 64).
+struct ChunkRegs {
+  int64_t base;
+  int len, sf, nsg;
+  bool valid;
+  u16x8 a, b;
+  int16_t bnd[5];
+  int32_t so[4];
+};
+
+__device__ __forceinline__ void load_window(const PanelPass& t, int64_t at, u16x8& a,
+                                            u16x8& b) {
+  // Read once per pass: non-temporal.
+  const u16x8* ip = reinterpret_cast<const u16x8*>(t.idx + at);
+  a = __builtin_nontemporal_load(ip);
+  b = __builtin_nontemporal_load(ip + 1);
+}
+
+__device__ __forceinline__ void load_chunk(const PanelPass& t, int c, int c_end, int lane,
+                                           ChunkRegs& R) {
+  R.valid = c < c_end;
+  if (!R.valid) return;
+  R.base = t.cstart[c];
+  R.len = (int)(t.cstart[c + 1] - R.base);  // a multiple of kPPad
+  R.sf = t.cseg[c];
+  R.nsg = t.cnseg[c];
+  const int e0 = lane * kPV;
+  if (e0 < R.len) load_window(t, R.base + e0, R.a, R.b);
+  if (R.nsg > 0) {
+    const int16_t* src = t.bound16 + t.cboff[c];
+    const int32_t* so = t.seg_out + R.sf;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const int k = lane + 64 * q;
+      R.bnd[q] = (k <= R.nsg) ? src[k] : (int16_t)0;
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) xv[j] = x[ix[j]];
-  } else {
-#pragma unroll
-    for (int j = 0; j < V; ++j) xv[j] = (e0 + j < len) ? x[t.idx[base + e0 + j]] : T(0);
+    for (int q = 0; q < 4; ++q) {
+      const int k = lane + 64 * q;
+      R.so[q] = (k < R.nsg) ? so[k] : 0;
+    }
   }
-#pragma unroll
-  for (int j = 0; j < V; ++j)
-    if (e0 + j < lo) xv[j] = T(0);  // elements of the previous chunk
+}
 
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (nsg == 0) {
-    // One piece of a long segment: fixed-order sum over the workgroup.
-    T acc = T(0);
+template <typename T>
+__device__ __forceinline__ T gather_sum16(const T* xl, const u16x8& a, const u16x8& b) {
+  T v[kPV];
 #pragma unroll
-    for (int j = 0; j < V; ++j) acc += xv[j];
+  for (int j = 0; j < 8; ++j) {
+    v[j] = xl[a[j]];
+    v[8 + j] = xl[b[j]];
+  }
+  T s = v[0];
+#pragma unroll
+  for (int j = 1; j < kPV; ++j) s += v[j];
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void process_chunk(const PanelPass& t, const ChunkRegs& R, int c,
+                                              int lane, const T* xl, int16_t* lb, int32_t* lso,
+                                              T* __restrict__ part_out,
+                                              T* __restrict__ piece_out) {
+  const int e0 = lane * kPV;
+  const int len = R.len, nsg = R.nsg;
+  if (nsg <= 0) {
+    // One long segment (or a piece of one): this lane sums its share of
+    // every window, the next window's indices in flight, then a fixed-order
+    // wavefront sum.
+    const int32_t slot = (nsg == 0) ? t.seg_out[R.sf] : 0;
+    T acc = T(0);
+    u16x8 a = R.a, b = R.b;
+    for (int w0 = 0; w0 < len; w0 += kPC) {
+      const bool have = e0 + w0 < len;
+      u16x8 na, nb;
+      const bool next = e0 + w0 + kPC < len;
+      if (next) load_window(t, R.base + e0 + w0 + kPC, na, nb);
+      if (have) acc += gather_sum16(xl, a, b);
+      if (next) {
+        a = na;
+        b = nb;
+      }
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) wval[wid] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      T tot = wval[0];
-      for (int w = 1; w < kWG / 64; ++w) tot += wval[w];
-      reinterpret_cast<T*>(t.part)[c] = tot;
+    if (lane == 0) {
+      if (nsg == 0)
+        part_out[slot] = acc;
+      else
+        piece_out[c] = acc;
     }
     return;
   }
-  __syncthreads();
 
-  auto emit = [&](int k, T v) {
-    const int o = t.sid[sf + k];
-    out[o] = scale ? v * scale[o] : v;
-  };
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const int k = lane + 64 * q;
+    if (k <= nsg) lb[k] = R.bnd[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = lane + 64 * q;
+    if (k < nsg) lso[k] = R.so[q];
+  }
+  __builtin_amdgcn_wave_barrier();
 
-  // Walk this thread's elements; every segment of a packed chunk ends inside
-  // the chunk, so each is finished by the thread holding its last element.
+  // Each active lane holds kPV consecutive elements; every segment of a
+  // packed chunk ends inside the chunk, so each is finished by the lane
+  // holding its last element.  Most lanes see no boundary: a plain sum.
+  const bool active = e0 < len;
   int k = nsg, first_k = nsg;
   T acc = T(0), first_val = T(0);
   bool first_closed = false, closes_at_end = false;
-  const int eb = max(e0, lo);
-  const int eend = min(e0 + V, len);
-  if (eb < eend) {
-    int a = 0, b = nsg - 1;
-    while (a < b) {
-      const int mid = (a + b + 1) >> 1;
-      if (lptr[mid] <= eb) a = mid; else b = mid - 1;
+  if (active) {
+    int lo = 0, hi = nsg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (lb[mid] <= e0) lo = mid; else hi = mid - 1;
     }
-    k = first_k = a;
-    int nxt = lptr[k + 1];
+    k = first_k = lo;
+    int nxt = lb[k + 1];
+    if (nxt >= e0 + kPV) {
+      acc = gather_sum16(xl, R.a, R.b);
+    } else {
+      T xv[kPV];
 #pragma unroll
-    for (int j = 0; j < V; ++j) {
-      const int e = e0 + j;
-      if (e >= eb && e < eend) {
+      for (int j = 0; j < 8; ++j) {
+        xv[j] = xl[R.a[j]];
+        xv[8 + j] = xl[R.b[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < kPV; ++j) {
+        const int e = e0 + j;
         while (e >= nxt) {  // segment k ended before element e
           if (!first_closed) {
             first_val = acc;
             first_closed = true;
           } else {
-            emit(k, acc);  // started and ended inside this thread
+            part_out[lso[k]] = acc;  // inside this lane
           }
           acc = T(0);
           ++k;
-          nxt = lptr[k + 1];
+          nxt = lb[k + 1];
         }
         acc += xv[j];
       }
     }
-    closes_at_end = (nxt == eend);
+    closes_at_end = (nxt == e0 + kPV);
   }
-
-  // Segmented inclusive scan of (segment, partial) over the workgroup gives
-  // each thread the sum of the earlier threads' share of its first segment.
+  // Segmented inclusive scan of (segment, partial) across the wavefront.
   int key = k;
   T val = acc;
 #pragma unroll
@@ -216,80 +283,110 @@ __global__ __launch_bounds__(kWG) void k_segsum(SegTable t, const T* __restrict_
     const T vu = __shfl_up(val, d, 64);
     if (lane >= d && ku == key) val += vu;
   }
-  if (lane == 63) {
-    wkey[wid] = key;
-    wval[wid] = val;
-  }
-  __syncthreads();
-  int pk = -1;
-  T pv = T(0);
-  for (int w = 0; w < wid; ++w) {
-    pv = wval[w] + (wkey[w] == pk ? pv : T(0));
-    pk = wkey[w];
-  }
-  const T incl = val + (pk == key ? pv : T(0));
   int ek = __shfl_up(key, 1, 64);
-  T ev = __shfl_up(incl, 1, 64);
-  if (lane == 0) {
-    ek = pk;
-    ev = pv;
-  }
+  T ev = __shfl_up(val, 1, 64);
+  if (lane == 0) ek = -1;
   const T carry_in = (ek == first_k) ? ev : T(0);
-
-  if (eb < eend) {
+  if (active) {
     if (first_closed) {
-      emit(first_k, carry_in + first_val);
-      if (closes_at_end) emit(k, acc);
+      part_out[lso[first_k]] = carry_in + first_val;
+      if (closes_at_end) part_out[lso[k]] = acc;
     } else if (closes_at_end) {
-      emit(k, carry_in + acc);
+      part_out[lso[k]] = carry_in + acc;
     }
   }
+  __builtin_amdgcn_wave_barrier();
 }
 
-// Sums the pieces of each split segment in chunk order.
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_split_sum(SegTable t, const T* __restrict__ scale,
-                                                   T* __restrict__ out,
-                                                   const int32_t* __restrict__ done) {
+__global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin,
+                                                     T* __restrict__ part_out,
+                                                     T* __restrict__ piece_out,
+                                                     const int32_t* __restrict__ done) {
   if (done != nullptr && *done) return;
-  const int i = blockIdx.x * kWG + threadIdx.x;
-  if (i >= t.nsplit) return;
-  const T* part = reinterpret_cast<const T*>(t.part);
-  const int c0 = t.split_c0[i], c1 = t.split_c1[i];
-  T tot = part[c0];
-  for (int cc = c0 + 1; cc <= c1; ++cc) tot += part[cc];
-  const int o = t.sid[t.split_seg[i]];
-  out[o] = scale ? tot * scale[o] : tot;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xl = reinterpret_cast<T*>(smem);
+  int16_t* lb_all = reinterpret_cast<int16_t*>(smem + kPanelBytes);
+  int32_t* lso_all = reinterpret_cast<int32_t*>(smem + kPanelBytes +
+                                                kPWaves * (kPSegMax + 2) * sizeof(int16_t));
+
+  const int w = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c_end = t.wg_c1[w];
+  int c = t.wg_c0[w] + wave;
+  // Start the first chunk's loads before assembling the panel.
+  ChunkRegs R0, R1;
+  load_chunk(t, c, c_end, lane, R0);
+
+  const int panel = t.wg_panel[w];
+  const int64_t g0 = (int64_t)panel * t.W;
+  const int64_t rem = t.gdim - g0;
+  const int wlen = (int)(rem < t.W ? rem : t.W);
+  // The panel of the gathered vector, assembled once per workgroup; slot W
+  // holds the zero the padding indices point to.
+  for (int j = threadIdx.x; j < wlen; j += kPThreads) xl[j] = combine_at(xin, g0 + j);
+  if (threadIdx.x == 0) xl[t.W] = T(0);
+  __syncthreads();
+
+  int16_t* lb = lb_all + wave * (kPSegMax + 2);
+  int32_t* lso = lso_all + wave * kPSegMax;
+  // Two-stage pipeline: the next chunk's loads are in flight while the
+  // current one is processed.
+  while (R0.valid) {
+    load_chunk(t, c + kPWaves, c_end, lane, R1);
+    process_chunk<T>(t, R0, c, lane, xl, lb, lso, part_out, piece_out);
+    if (!R1.valid) break;
+    load_chunk(t, c + 2 * kPWaves, c_end, lane, R0);
+    process_chunk<T>(t, R1, c + kPWaves, lane, xl, lb, lso, part_out, piece_out);
+    c += 2 * kPWaves;
+  }
+}
+
+static size_t pass_lds_bytes() {
+  return (size_t)kPanelBytes + (size_t)kPWaves * (kPSegMax + 2) * sizeof(int16_t) +
+         (size_t)kPWaves * kPSegMax * sizeof(int32_t);
+}
+
+hipError_t setup_pass_kernels() {
+  const int bytes = (int)pass_lds_bytes();
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel<float>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel<double>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <typename T>
-hipError_t launch_segsum(const SegTable& t, const T* x, const T* scale, T* out,
-                         const int32_t* done, hipStream_t st) {
-  if (t.nchunks == 0) return hipSuccess;
-  const dim3 grid(t.nchunks), block(kWG);
-  switch (t.chunk / kWG) {
-    case 4:
-      hipLaunchKernelGGL((k_segsum<T, 4>), grid, block, 0, st, t, x, scale, out, done);
-      break;
-    case 8:
-      hipLaunchKernelGGL((k_segsum<T, 8>), grid, block, 0, st, t, x, scale, out, done);
-      break;
-    case 16:
-      hipLaunchKernelGGL((k_segsum<T, 16>), grid, block, 0, st, t, x, scale, out, done);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  if (t.nsplit > 0)
-    hipLaunchKernelGGL((k_split_sum<T>), dim3((t.nsplit + kWG - 1) / kWG), block, 0, st, t,
-                       scale, out, done);
+hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
+                             T* piece_out, const int32_t* done, hipStream_t st) {
+  if (t.nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_panel<T>), dim3(t.nwg), dim3(kPThreads), pass_lds_bytes(), st, t, x,
+                     part_out, piece_out, done);
   return hipGetLastError();
 }
 
-template hipError_t launch_segsum<float>(const SegTable&, const float*, const float*, float*,
-                                         const int32_t*, hipStream_t);
-template hipError_t launch_segsum<double>(const SegTable&, const double*, const double*,
-                                          double*, const int32_t*, hipStream_t);
+template <typename T, typename U>
+__global__ __launch_bounds__(kWG) void k_combine(Combine<T> c, int64_t dim, U* out) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < dim) out[i] = (U)combine_at(c, i);
+}
+
+template <typename T, typename U>
+hipError_t launch_combine(const Combine<T>& c, int64_t dim, U* out, hipStream_t st) {
+  if (dim <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_combine<T, U>), dim3((unsigned)((dim + kWG - 1) / kWG)), dim3(kWG), 0,
+                     st, c, dim, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_panel_pass<float>(const PanelPass&, const Combine<float>&, float*,
+                                             float*, const int32_t*, hipStream_t);
+template hipError_t launch_panel_pass<double>(const PanelPass&, const Combine<double>&, double*,
+                                              double*, const int32_t*, hipStream_t);
+template hipError_t launch_combine<float, float>(const Combine<float>&, int64_t, float*,
+                                                 hipStream_t);
+template hipError_t launch_combine<double, double>(const Combine<double>&, int64_t, double*,
+                                                   hipStream_t);
 
 // ------------------------------------------------------------------------
 // Philox4x64-10 and Box-Muller normals
@@ -485,7 +582,7 @@ template hipError_t launch_phi_finish<double>(const double*, const double*, cons
 // CG vector phases (p-vectors; FP64 state and reductions)
 // ------------------------------------------------------------------------
 static inline unsigned red_grid(int64_t p) {
-  int64_t g = (p + kWG * 4 - 1) / (kWG * 4);
+  int64_t g = (p + kWG - 1) / kWG;
   if (g < 1) g = 1;
   if (g > kMaxRedBlocks) g = kMaxRedBlocks;
   return (unsigned)g;
@@ -499,7 +596,7 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
                                                   const double* qx64, const double* d,
                                                   const double* m, double* beta, double* r,
                                                   T* s, int64_t p, double tol, int criterion,
-                                                  int max_iter) {
+                                                  int max_iter, double loop_factor) {
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // <r,Mr>, <r,r>, <b,Mb>, <b,b>
   for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < p;
        j += (int64_t)gridDim.x * kWG) {
@@ -511,11 +608,11 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
     if (mode == 0) {
       v[2] += bj * m[j] * bj;
       v[3] += bj * bj;
+      if (qx64 == nullptr) beta[j] = 0.0;
     }
     if (mode != 2) {
       r[j] = rj;
       s[j] = (T)zj;
-      if (mode == 0 && qx64 == nullptr) beta[j] = 0.0;
     }
   }
   block_sum<4>(v);
@@ -540,15 +637,17 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
       sc->thresh2 = criterion == kCritRelPrecond ? t2 * tot[2]
                   : criterion == kCritRmsAbs     ? t2 * (double)p
                                                  : t2 * tot[3];
+      sc->loop2 = sc->thresh2 * loop_factor * loop_factor;
     }
+    sc->betacg = 0.0;
+    sc->rho_prev = tot[0];
     sc->rho = tot[0];
     sc->rr = tot[1];
     sc->meas = meas;
     sc->iters = 0;
     sc->status = kStatOK;
     sc->alpha = 0.0;
-    sc->betacg = 0.0;
-    sc->done = (meas <= sc->thresh2) ? 1 : 0;
+    sc->done = (meas <= sc->loop2) ? 1 : 0;
     if (!isfinite(tot[0]) || !isfinite(tot[1])) {
       sc->status = kStatBreakdown;
       sc->done = 1;
@@ -559,21 +658,24 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
 template <typename T>
 hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
                            const double* d, const double* m, double* beta, double* r, T* s,
-                           int64_t p, double tol, int criterion, int max_iter, hipStream_t st) {
+                           int64_t p, double tol, int criterion, int max_iter,
+                           double loop_factor, hipStream_t st) {
   hipLaunchKernelGGL((k_cg_start<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, mode, b, qx64, d,
-                     m, beta, r, s, p, tol, criterion, max_iter);
+                     m, beta, r, s, p, tol, criterion, max_iter, loop_factor);
   return hipGetLastError();
 }
 
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_dot(VecWork w, const T* s, const T* qx,
+__global__ __launch_bounds__(kWG) void k_cg_dot(VecWork w, const T* s, Combine<T> qsrc, T* qx,
                                                 const double* d, int64_t p) {
   if (w.sc->done) return;
   double v[1] = {0.0};
   for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < p;
        j += (int64_t)gridDim.x * kWG) {
+    const T qj = combine_at(qsrc, j);
+    qx[j] = qj;
     const double sj = (double)s[j];
-    v[0] += sj * ((double)qx[j] + d[j] * sj);
+    v[0] += sj * ((double)qj + d[j] * sj);
   }
   block_sum<1>(v);
   if (!publish_and_arrive<1>(v, w.part, &w.sc->arrive[2])) return;
@@ -621,11 +723,12 @@ __global__ __launch_bounds__(kWG) void k_cg_update(VecWork w, const T* s, const 
     const double meas = (sc->criterion == kCritRelPlain) ? tot[1] : rho_new;
     sc->meas = meas;
     sc->betacg = rho_new / sc->rho;
+    sc->rho_prev = sc->rho;
     sc->rho = rho_new;
     if (!isfinite(rho_new)) {
       sc->status = kStatBreakdown;
       sc->done = 1;
-    } else if (meas <= sc->thresh2) {
+    } else if (meas <= sc->loop2) {
       sc->done = 1;
     } else if (sc->iters >= sc->max_iter) {
       sc->status = kStatNotConv;
@@ -645,9 +748,9 @@ __global__ __launch_bounds__(kWG) void k_cg_direction(VecWork w, const double* m
 }
 
 template <typename T>
-hipError_t launch_cg_dot(VecWork w, const T* s, const T* qx, const double* d, int64_t p,
-                         hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_dot<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, s, qx, d, p);
+hipError_t launch_cg_dot(VecWork w, const T* s, const Combine<T>& qsrc, T* qx, const double* d,
+                         int64_t p, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_dot<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, s, qsrc, qx, d, p);
   return hipGetLastError();
 }
 template <typename T>
@@ -668,9 +771,9 @@ hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s
 #define PPCG_INST(T)                                                                         \
   template hipError_t launch_cg_start<T>(VecWork, int, const double*, const double*,         \
                                          const double*, const double*, double*, double*, T*, \
-                                         int64_t, double, int, int, hipStream_t);            \
-  template hipError_t launch_cg_dot<T>(VecWork, const T*, const T*, const double*, int64_t,  \
-                                       hipStream_t);                                         \
+                                         int64_t, double, int, int, double, hipStream_t);    \
+  template hipError_t launch_cg_dot<T>(VecWork, const T*, const Combine<T>&, T*,            \
+                                       const double*, int64_t, hipStream_t);                 \
   template hipError_t launch_cg_update<T>(VecWork, const T*, const T*, const double*,        \
                                           const double*, double*, double*, int64_t,          \
                                           hipStream_t);                                      \

@@ -45,11 +45,12 @@ def test_struct_layout_matches_header(tmp_path):
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "ppcg.h"\n'
         "int main(void){\n"
-        ' printf("%zu %zu %zu %zu %zu\\n", sizeof(ppcg_options), offsetof(ppcg_options, tol),'
+        ' printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ppcg_options), offsetof(ppcg_options, tol),'
         " offsetof(ppcg_options, true_resid), offsetof(ppcg_options, check_every),"
-        " offsetof(ppcg_options, reserved));\n"
-        ' printf("%zu %zu %zu\\n", sizeof(ppcg_info), offsetof(ppcg_info, resid_rec),'
-        " offsetof(ppcg_info, bnorm_precond));\n return 0; }\n")
+        " offsetof(ppcg_options, loop_factor), offsetof(ppcg_options, reserved));\n"
+        ' printf("%zu %zu %zu %zu\\n", sizeof(ppcg_info), offsetof(ppcg_info, resid_rec),'
+        " offsetof(ppcg_info, bnorm_precond), offsetof(ppcg_info, resid_true_first));\n"
+        " return 0; }\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
                     "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
@@ -57,8 +58,10 @@ def test_struct_layout_matches_header(tmp_path):
     o = [int(x) for x in lines[0].split()]
     i = [int(x) for x in lines[1].split()]
     assert o == [ctypes.sizeof(pk.Options), pk.Options.tol.offset, pk.Options.true_resid.offset,
-                 pk.Options.check_every.offset, pk.Options.reserved.offset]
-    assert i == [ctypes.sizeof(pk.Info), pk.Info.resid_rec.offset, pk.Info.bnorm_precond.offset]
+                 pk.Options.check_every.offset, pk.Options.loop_factor.offset,
+                 pk.Options.reserved.offset]
+    assert i == [ctypes.sizeof(pk.Info), pk.Info.resid_rec.offset, pk.Info.bnorm_precond.offset,
+                 pk.Info.resid_true_first.offset]
 
 
 @needs_lib

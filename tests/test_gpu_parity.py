@@ -35,6 +35,13 @@ def t32(a):
     return torch.as_tensor(np.asarray(a, dtype=np.float32), device=DEV)
 
 
+def iters_close(a, b):
+    """Stopping iterations of two CG runs on the same system under different
+    summation orders: the residual can plateau near the threshold for a few
+    steps, so they may differ by a few iterations."""
+    return abs(a - b) <= max(3, 0.05 * b)
+
+
 def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -129,7 +136,7 @@ def test_solve_f64_c0_matches_oracle_pcg_and_cholesky(problem_cache):
     b = np.random.default_rng(3).standard_normal(P.p) / (P.tau * P.lam)
     beta, info = pk.solve(X, t64(P.omega), t64(P.lam), P.tau, t64(b), tol=1e-10)
     ref = R.pcg_solve(Xs, P.omega, P.lam, P.tau, b, tol=1e-10)
-    assert info["status"] == 0 and abs(info["iters"] - ref.iters) <= 3
+    assert info["status"] == 0 and iters_close(info["iters"], ref.iters)
     assert info["resid_true"] <= 1.0 + 1e-6
     exact = R.solve_chol(R.phi_dense(Xs, P.omega, P.lam, P.tau), b)
     e_ = rel(beta.cpu().numpy(), exact)
@@ -171,7 +178,7 @@ def test_draw_f64_c0_matches_oracle(problem_cache):
         ref = R.pcg_solve(Xs, P.omega, P.lam, P.tau, b, tol=1e-10)
         # The residual stagnates for a few steps near the threshold, so the
         # stopping iteration may differ by a few steps under rounding.
-        assert info["status"] == 0 and abs(info["iters"] - ref.iters) <= 3
+        assert info["status"] == 0 and iters_close(info["iters"], ref.iters)
         assert info["resid_true"] <= 1.0 + 1e-6
         rt = R.true_residual(Xs, P.omega, P.lam, P.tau, b, got)
         assert R.criterion_value(R.REL_PRECOND, rt, b, m) <= 1e-10 * (1 + 1e-6)
@@ -257,7 +264,7 @@ def test_criteria(problem_cache):
         got = beta.cpu().numpy()
         ref = R.pcg_solve(Xs, P.omega, P.lam, P.tau, b, tol=tol, criterion=crit)
         its, its_ref = info["iters"], ref.iters
-        assert abs(its - its_ref) <= 3, crit
+        assert iters_close(its, its_ref), crit
         r = R.true_residual(Xs, P.omega, P.lam, P.tau, b, got)
         value = R.criterion_value(crit, r, b, m)
         assert value <= tol * (1 + 1e-6), crit
