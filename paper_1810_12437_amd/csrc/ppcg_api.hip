@@ -113,8 +113,7 @@ int upload_orient(ppcg_matrix* X, const PanelBuild& B, int elem, Orient& o) {
   if ((rc = upload_vec(X, B.cstart, &t.cstart, &by))) return rc;
   if ((rc = upload_vec(X, B.cseg, &t.cseg, &by))) return rc;
   if ((rc = upload_vec(X, B.cnseg, &t.cnseg, &by))) return rc;
-  if ((rc = upload_vec(X, B.cboff, &t.cboff, &by))) return rc;
-  if ((rc = upload_vec(X, B.bound16, &t.bound16, &by))) return rc;
+  if ((rc = upload_vec(X, B.cmask, &t.cmask, &by))) return rc;
   if ((rc = upload_vec(X, B.seg_out, &t.seg_out, &by))) return rc;
   if ((rc = upload_vec(X, B.wg_panel, &t.wg_panel, &by))) return rc;
   if ((rc = upload_vec(X, B.wg_c0, &t.wg_c0, &by))) return rc;
@@ -140,13 +139,12 @@ int upload_orient(ppcg_matrix* X, const PanelBuild& B, int elem, Orient& o) {
   o.part = part;
   o.piece = piece;
   o.dev_bytes = by + (int64_t)part_bytes + (int64_t)t.nchunks * elem;
-  // Per launch: index stream, chunk tables (cstart, cseg, cnseg, cboff),
-  // boundaries, output slots, one segment sum per (segment, panel), and the
-  // gathered vector once (its panel copies come from cache).
+  // Per launch: the padded index stream, the chunk tables (cstart, cseg,
+  // cnseg, cmask), output slots, one segment sum per (segment, panel), and
+  // the gathered vector once (its panel copies come from cache).
   const int64_t nseg = (int64_t)B.seg_out.size();
-  o.pass_bytes = 2 * (int64_t)B.idx.size() + 20 * (int64_t)t.nchunks +
-                 2 * (int64_t)B.bound16.size() + 4 * nseg + (int64_t)elem * nseg +
-                 (int64_t)elem * B.gdim;
+  o.pass_bytes = 2 * (int64_t)B.idx.size() + (16 + 8 * kPNW) * (int64_t)t.nchunks + 4 * nseg +
+                 (int64_t)elem * nseg + (int64_t)elem * B.gdim;
   return PPCG_OK;
 }
 
@@ -204,27 +202,41 @@ Combine<T> comb_out(const Orient& o, const T* scale) {
   return c;
 }
 
-// Row pass: segment sums of X x (omega is applied by the consumer).
+// Whether the row pass can apply omega itself: one panel and no pieces, so
+// each row's sum is complete when the pass writes it.
+inline bool rows_direct(const Orient& o) { return o.npanels == 1 && o.sp_off == nullptr; }
+
+// Row pass: u = omega .* (X x), as panel partials (omega applied by the pass
+// when the rows fit one panel, else by the consumer).
 template <typename T>
-hipError_t row_pass(ppcg_matrix* X, const Combine<T>& x, const int32_t* done, hipStream_t st) {
+hipError_t row_pass(ppcg_matrix* X, const Combine<T>& x, const T* omega, const int32_t* done,
+                    hipStream_t st) {
   Orient& o = X->rows[prec_index<T>()];
   return launch_panel_pass<T>(o.pass, x, reinterpret_cast<T*>(o.part),
-                              reinterpret_cast<T*>(o.piece), done, st);
+                              reinterpret_cast<T*>(o.piece), rows_direct(o) ? omega : nullptr,
+                              done, st);
 }
 
-// Column pass: segment sums of X^T u with u = omega .* (X x) from the row pass.
+// The column pass's view of u.
+template <typename T>
+Combine<T> u_view(ppcg_matrix* X, const T* omega) {
+  const Orient& o = X->rows[prec_index<T>()];
+  return comb_out<T>(o, rows_direct(o) ? nullptr : omega);
+}
+
+// Column pass: segment sums of X^T u, u from the row pass (or y if given).
 template <typename T>
 hipError_t col_pass(ppcg_matrix* X, const T* omega, const Combine<T>* y, const int32_t* done,
                     hipStream_t st) {
   Orient& o = X->cols[prec_index<T>()];
-  const Combine<T> u = y ? *y : comb_out<T>(X->rows[prec_index<T>()], omega);
+  const Combine<T> u = y ? *y : u_view<T>(X, omega);
   return launch_panel_pass<T>(o.pass, u, reinterpret_cast<T*>(o.part),
-                              reinterpret_cast<T*>(o.piece), done, st);
+                              reinterpret_cast<T*>(o.piece), nullptr, done, st);
 }
 
 // FP64 product part qx64 = X^T (omega .* (X x)).
 int fp64_phi_parts(ppcg_matrix* X, const double* x, const double* omega64, hipStream_t st) {
-  PPCG_TRY_HIP(row_pass<double>(X, comb_vec<double>(x), nullptr, st));
+  PPCG_TRY_HIP(row_pass<double>(X, comb_vec<double>(x), omega64, nullptr, st));
   PPCG_TRY_HIP(col_pass<double>(X, omega64, nullptr, nullptr, st));
   PPCG_TRY_HIP(launch_combine<double, double>(comb_out<double>(X->cols[0], nullptr), X->p,
                                               X->qx64, st));
@@ -272,7 +284,7 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
     if (prof) active_before = X->h_sc->done ? 0 : 1;
     for (int i = 0; i < o.check_every; ++i) {
       if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 0], st));
-      PPCG_TRY_HIP(row_pass<T>(X, svec, done, st));
+      PPCG_TRY_HIP(row_pass<T>(X, svec, omegaT, done, st));
       if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 1], st));
       PPCG_TRY_HIP(col_pass<T>(X, omegaT, nullptr, done, st));
       if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 2], st));
@@ -601,7 +613,7 @@ int ppcg_phi_matvec(const ppcg_matrix* Xc, const void* omega, const void* lambda
   if (dtype == PPCG_F64) {
     const double* om = reinterpret_cast<const double*>(omega);
     const double* vv = reinterpret_cast<const double*>(v);
-    PPCG_TRY_HIP(row_pass<double>(X, comb_vec<double>(vv), nullptr, st));
+    PPCG_TRY_HIP(row_pass<double>(X, comb_vec<double>(vv), om, nullptr, st));
     PPCG_TRY_HIP(col_pass<double>(X, om, nullptr, nullptr, st));
     PPCG_TRY_HIP(launch_combine<double, double>(comb_out<double>(X->cols[0], nullptr), X->p,
                                                 X->qx64, st));
@@ -610,7 +622,7 @@ int ppcg_phi_matvec(const ppcg_matrix* Xc, const void* omega, const void* lambda
   } else {
     const float* om = reinterpret_cast<const float*>(omega);
     const float* vv = reinterpret_cast<const float*>(v);
-    PPCG_TRY_HIP(row_pass<float>(X, comb_vec<float>(vv), nullptr, st));
+    PPCG_TRY_HIP(row_pass<float>(X, comb_vec<float>(vv), om, nullptr, st));
     PPCG_TRY_HIP(col_pass<float>(X, om, nullptr, nullptr, st));
     PPCG_TRY_HIP(launch_combine<float, float>(comb_out<float>(X->cols[1], nullptr), X->p,
                                               X->qx32, st));

@@ -16,21 +16,21 @@ constexpr int kMaxRedBlocks = 1024; // max workgroups of a p-vector phase
 // w -> X^T w) in a panel-blocked, index-only layout.  The gathered
 // dimension is cut into panels of at most W entries so that a panel of the
 // gathered vector fits in LDS; within panel k the non-empty (segment, panel)
-// pairs are stored consecutively with 16-bit indices local to the panel.
-// The element stream is cut into chunks along segment boundaries, each
-// padded to a multiple of kPPad with the index W (an LDS zero): a packed
-// chunk (cnseg > 0) holds whole segments in one window of kPC elements, a
-// long chunk (cnseg == 0) is one segment summed whole, and a piece
-// (cnseg < 0) is part of a segment longer than kPLongMax whose piece sums
-// the consumer adds.  Workgroup w serves one panel and owns the chunk range
-// [wg_c0[w], wg_c1[w]).
+// pairs are stored consecutively with 16-bit indices local to the panel,
+// each padded with the index W (an LDS zero) to a multiple of kPV, so one
+// lane's kPV elements always belong to one segment.  Chunks: a packed chunk
+// (cnseg > 0) holds whole padded segments in up to kPNW windows of kPC
+// elements, bit g of its kPNW mask words marking the kPV-element groups that
+// start a segment; a long chunk (cnseg == 0) is one segment summed whole; a
+// piece (cnseg < 0) is part of a segment longer than kPLongMax whose piece
+// sums the consumer adds.
+// Workgroup w serves one panel and owns the chunk range [wg_c0[w], wg_c1[w]).
 struct PanelPass {
-  const uint16_t* idx;     // [nnz] panel-local gathered index
-  const int64_t* cstart;   // [nchunks + 1] first element of each chunk; last = nnz
-  const int32_t* cseg;     // [nchunks] first segment (or the split segment)
-  const int32_t* cnseg;    // [nchunks] segments in a packed chunk; 0 for a piece
-  const int32_t* cboff;    // [nchunks] offset of the chunk's boundaries in bound16
-  const int16_t* bound16;  // segment boundaries relative to the chunk window
+  const uint16_t* idx;     // [stream] panel-local gathered index (padded)
+  const int64_t* cstart;   // [nchunks + 1] first element of each chunk; last = stream end
+  const int32_t* cseg;     // [nchunks] first (or the long) segment
+  const int32_t* cnseg;    // [nchunks] segments of a packed chunk; 0 long; < 0 piece
+  const uint64_t* cmask;   // [nchunks * kPNW] groups that start a segment (packed chunks)
   const int32_t* seg_out;  // [nseg] output slot = panel * out_dim + segment id
   const int32_t* wg_panel; // [nwg]
   const int32_t* wg_c0;    // [nwg]
@@ -88,10 +88,12 @@ struct VecWork {
 
 // ---- launchers (all asynchronous on `st`) ----
 // One X pass: gathers value(x, .) panel by panel and writes the segment sums
-// of panel k to part_out[k * out_dim + id], piece sums to piece_out.
+// of panel k to part_out[k * out_dim + id] (times out_scale[id] when given:
+// only for a single-panel table without pieces), piece sums to piece_out.
 template <typename T>
 hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
-                             T* piece_out, const int32_t* done, hipStream_t st);
+                             T* piece_out, const T* out_scale, const int32_t* done,
+                             hipStream_t st);
 
 // out[i] = value(c, i) for i < dim.
 template <typename T, typename U>

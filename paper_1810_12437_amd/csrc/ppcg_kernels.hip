@@ -123,16 +123,22 @@ __device__ __forceinline__ T combine_at(const Combine<T>& c, int64_t i) {
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-// Registers of one chunk in flight: its bounds, this lane's kPV indices of
-// the chunk's first window, and the segment boundaries / output slots of a
-// packed chunk spread over the lanes (entry k at lane k % 64, slot k / 64).
+// One chunk in flight: its bounds and segment-start masks (wave-uniform),
+// this lane's kPV indices in each window, and for a packed chunk the output
+// slot of segment kfirst(q) + lane of each window q.
 struct ChunkRegs {
   int64_t base;
+  uint64_t mask[kPNW];
   int len, sf, nsg;
-  bool valid;
-  u16x8 a, b;
-  int16_t bnd[5];
-  int32_t so[4];
+  u16x8 a[kPNW], b[kPNW];
+  int32_t so[kPNW];
+};
+
+// Metadata of up to 64 chunks of one wavefront, one chunk per lane.
+struct ChunkMeta {
+  int64_t cs, ce;
+  uint64_t mask[kPNW];
+  int sf, nsg;
 };
 
 __device__ __forceinline__ void load_window(const PanelPass& t, int64_t at, u16x8& a,
@@ -143,28 +149,48 @@ __device__ __forceinline__ void load_window(const PanelPass& t, int64_t at, u16x
   b = __builtin_nontemporal_load(ip + 1);
 }
 
-__device__ __forceinline__ void load_chunk(const PanelPass& t, int c, int c_end, int lane,
-                                           ChunkRegs& R) {
-  R.valid = c < c_end;
-  if (!R.valid) return;
-  R.base = t.cstart[c];
-  R.len = (int)(t.cstart[c + 1] - R.base);  // a multiple of kPPad
-  R.sf = t.cseg[c];
-  R.nsg = t.cnseg[c];
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float readlane_t(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_t(double v, int l) {
+  return __longlong_as_double(readlane64(__double_as_longlong(v), l));
+}
+
+// First segment (chunk-relative) of window q: the one continuing into it,
+// or the first one starting in it.
+__device__ __forceinline__ int window_first_key(const uint64_t* mask, int q) {
+  int pre = 0;
+#pragma unroll
+  for (int i = 0; i < kPNW; ++i)
+    if (i < q) pre += __popcll(mask[i]);
+  return (mask[q] & 1ull) ? pre : pre - 1;
+}
+
+// Issues the loads of chunk number k of the metadata block held in M.
+__device__ __forceinline__ void issue_chunk(const PanelPass& t, const ChunkMeta& M, int k,
+                                            int lane, ChunkRegs& R) {
+  R.base = readlane64(M.cs, k);
+  R.len = (int)(readlane64(M.ce, k) - R.base);  // a multiple of kPV
+  R.sf = __builtin_amdgcn_readlane(M.sf, k);
+  R.nsg = __builtin_amdgcn_readlane(M.nsg, k);
+#pragma unroll
+  for (int q = 0; q < kPNW; ++q) R.mask[q] = (uint64_t)readlane64((int64_t)M.mask[q], k);
   const int e0 = lane * kPV;
-  if (e0 < R.len) load_window(t, R.base + e0, R.a, R.b);
+  const int nw = R.nsg > 0 ? (R.len + kPC - 1) / kPC : 1;
+#pragma unroll
+  for (int q = 0; q < kPNW; ++q)
+    if (q < nw && q * kPC + e0 < R.len) load_window(t, R.base + q * kPC + e0, R.a[q], R.b[q]);
   if (R.nsg > 0) {
-    const int16_t* src = t.bound16 + t.cboff[c];
-    const int32_t* so = t.seg_out + R.sf;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const int k = lane + 64 * q;
-      R.bnd[q] = (k <= R.nsg) ? src[k] : (int16_t)0;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = lane + 64 * q;
-      R.so[q] = (k < R.nsg) ? so[k] : 0;
+    for (int q = 0; q < kPNW; ++q) {
+      const int kk = window_first_key(R.mask, q) + lane;
+      R.so[q] = (q < nw && kk < R.nsg) ? t.seg_out[R.sf + kk] : 0;
     }
   }
 }
@@ -183,24 +209,32 @@ __device__ __forceinline__ T gather_sum16(const T* xl, const u16x8& a, const u16
   return s;
 }
 
+// Output of one segment sum: the panel-partial slot, scaled by out_scale of
+// the segment (row pass with a single panel) when given.
+template <typename T>
+__device__ __forceinline__ void put(T* __restrict__ part_out, const T* __restrict__ out_scale,
+                                    int32_t slot, T v) {
+  part_out[slot] = out_scale ? v * out_scale[slot] : v;
+}
+
 template <typename T>
 __device__ __forceinline__ void process_chunk(const PanelPass& t, const ChunkRegs& R, int c,
-                                              int lane, const T* xl, int16_t* lb, int32_t* lso,
-                                              T* __restrict__ part_out,
-                                              T* __restrict__ piece_out) {
+                                              int lane, const T* xl, T* __restrict__ part_out,
+                                              T* __restrict__ piece_out,
+                                              const T* __restrict__ out_scale) {
   const int e0 = lane * kPV;
   const int len = R.len, nsg = R.nsg;
   if (nsg <= 0) {
-    // One long segment (or a piece of one): this lane sums its share of
+    // One long segment (or a piece of one): each lane sums its share of
     // every window, the next window's indices in flight, then a fixed-order
     // wavefront sum.
     const int32_t slot = (nsg == 0) ? t.seg_out[R.sf] : 0;
     T acc = T(0);
-    u16x8 a = R.a, b = R.b;
+    u16x8 a = R.a[0], b = R.b[0];
     for (int w0 = 0; w0 < len; w0 += kPC) {
       const bool have = e0 + w0 < len;
-      u16x8 na, nb;
       const bool next = e0 + w0 + kPC < len;
+      u16x8 na, nb;
       if (next) load_window(t, R.base + e0 + w0 + kPC, na, nb);
       if (have) acc += gather_sum16(xl, a, b);
       if (next) {
@@ -212,140 +246,150 @@ __device__ __forceinline__ void process_chunk(const PanelPass& t, const ChunkReg
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if (lane == 0) {
       if (nsg == 0)
-        part_out[slot] = acc;
+        put(part_out, out_scale, slot, acc);
       else
         piece_out[c] = acc;
     }
     return;
   }
-
+  // Packed chunk, window by window: a lane sums its group; lanes of one
+  // segment are contiguous; a lane's segment (chunk-relative) is the number
+  // of segment starts at or before its group, minus one.  The running sum of
+  // a segment that crosses into the next window is carried by lane 63.
+  const int nw = (len + kPC - 1) / kPC;
+  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  int carry_key = -1;
+  T carry_val = T(0);
+  int pre = 0;
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    const int k = lane + 64 * q;
-    if (k <= nsg) lb[k] = R.bnd[q];
-  }
+  for (int q = 0; q < kPNW; ++q) {
+    if (q < nw) {
+      const bool active = q * kPC + e0 < len;
+      T val = active ? gather_sum16(xl, R.a[q], R.b[q]) : T(0);
+      const int kfirst = (R.mask[q] & 1ull) ? pre : pre - 1;
+      const int key = active ? (pre + __popcll(R.mask[q] & upto) - 1) : nsg;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int k = lane + 64 * q;
-    if (k < nsg) lso[k] = R.so[q];
-  }
-  __builtin_amdgcn_wave_barrier();
-
-  // Each active lane holds kPV consecutive elements; every segment of a
-  // packed chunk ends inside the chunk, so each is finished by the lane
-  // holding its last element.  Most lanes see no boundary: a plain sum.
-  const bool active = e0 < len;
-  int k = nsg, first_k = nsg;
-  T acc = T(0), first_val = T(0);
-  bool first_closed = false, closes_at_end = false;
-  if (active) {
-    int lo = 0, hi = nsg - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (lb[mid] <= e0) lo = mid; else hi = mid - 1;
-    }
-    k = first_k = lo;
-    int nxt = lb[k + 1];
-    if (nxt >= e0 + kPV) {
-      acc = gather_sum16(xl, R.a, R.b);
-    } else {
-      T xv[kPV];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        xv[j] = xl[R.a[j]];
-        xv[8 + j] = xl[R.b[j]];
+      for (int d = 1; d < 64; d <<= 1) {
+        const int ku = __shfl_up(key, d, 64);
+        const T vu = __shfl_up(val, d, 64);
+        if (lane >= d && ku == key) val += vu;
       }
-#pragma unroll
-      for (int j = 0; j < kPV; ++j) {
-        const int e = e0 + j;
-        while (e >= nxt) {  // segment k ended before element e
-          if (!first_closed) {
-            first_val = acc;
-            first_closed = true;
-          } else {
-            part_out[lso[k]] = acc;  // inside this lane
-          }
-          acc = T(0);
-          ++k;
-          nxt = lb[k + 1];
-        }
-        acc += xv[j];
-      }
-    }
-    closes_at_end = (nxt == e0 + kPV);
-  }
-  // Segmented inclusive scan of (segment, partial) across the wavefront.
-  int key = k;
-  T val = acc;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int ku = __shfl_up(key, d, 64);
-    const T vu = __shfl_up(val, d, 64);
-    if (lane >= d && ku == key) val += vu;
-  }
-  int ek = __shfl_up(key, 1, 64);
-  T ev = __shfl_up(val, 1, 64);
-  if (lane == 0) ek = -1;
-  const T carry_in = (ek == first_k) ? ev : T(0);
-  if (active) {
-    if (first_closed) {
-      part_out[lso[first_k]] = carry_in + first_val;
-      if (closes_at_end) part_out[lso[k]] = acc;
-    } else if (closes_at_end) {
-      part_out[lso[k]] = carry_in + acc;
+      if (key == carry_key) val += carry_val;
+      const bool cont = (q + 1 < nw) && !(R.mask[q + 1 < kPNW ? q + 1 : q] & 1ull);
+      const int knext = __shfl_down(key, 1, 64);
+      const int rel = key - kfirst;
+      const int32_t slot = __shfl(R.so[q], (rel >= 0 && rel < 64) ? rel : 0, 64);
+      const bool last = active && (lane == 63 ? !cont : knext != key);
+      if (last) put(part_out, out_scale, slot, val);
+      carry_key = __builtin_amdgcn_readlane(key, 63);
+      carry_val = readlane_t(val, 63);
+      pre += __popcll(R.mask[q]);
     }
   }
-  __builtin_amdgcn_wave_barrier();
 }
 
 template <typename T>
 __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin,
                                                      T* __restrict__ part_out,
                                                      T* __restrict__ piece_out,
+                                                     const T* __restrict__ out_scale,
                                                      const int32_t* __restrict__ done) {
   if (done != nullptr && *done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* xl = reinterpret_cast<T*>(smem);
-  int16_t* lb_all = reinterpret_cast<int16_t*>(smem + kPanelBytes);
-  int32_t* lso_all = reinterpret_cast<int32_t*>(smem + kPanelBytes +
-                                                kPWaves * (kPSegMax + 2) * sizeof(int16_t));
 
   const int w = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c_end = t.wg_c1[w];
-  int c = t.wg_c0[w] + wave;
-  // Start the first chunk's loads before assembling the panel.
+  const int c_beg = t.wg_c0[w] + wave, c_end = t.wg_c1[w];
+  // This wavefront's chunks: c_beg, c_beg + kPWaves, ...
+  const int K = c_beg < c_end ? (c_end - c_beg + kPWaves - 1) / kPWaves : 0;
+
+  ChunkMeta M;
   ChunkRegs R0, R1;
-  load_chunk(t, c, c_end, lane, R0);
+  auto load_meta = [&](int kb) {
+    const int c = c_beg + kPWaves * (kb + lane);
+    if (kb + lane < K) {
+      M.cs = t.cstart[c];
+      M.ce = t.cstart[c + 1];
+#pragma unroll
+      for (int q = 0; q < kPNW; ++q) M.mask[q] = t.cmask[(int64_t)c * kPNW + q];
+      M.sf = t.cseg[c];
+      M.nsg = t.cnseg[c];
+    } else {
+      M.cs = M.ce = 0;
+#pragma unroll
+      for (int q = 0; q < kPNW; ++q) M.mask[q] = 0;
+      M.sf = M.nsg = 0;
+    }
+  };
+  // Start the first chunk's loads before assembling the panel.
+  int nb = K < 64 ? K : 64;
+  if (K > 0) {
+    load_meta(0);
+    issue_chunk(t, M, 0, lane, R0);
+  }
 
   const int panel = t.wg_panel[w];
   const int64_t g0 = (int64_t)panel * t.W;
   const int64_t rem = t.gdim - g0;
   const int wlen = (int)(rem < t.W ? rem : t.W);
   // The panel of the gathered vector, assembled once per workgroup; slot W
-  // holds the zero the padding indices point to.
-  for (int j = threadIdx.x; j < wlen; j += kPThreads) xl[j] = combine_at(xin, g0 + j);
+  // holds the zero the padding indices point to.  Eight loads in flight per
+  // thread before the LDS stores.
+  constexpr int U = 8;
+  if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr) {
+    const T* src = xin.part + g0;
+    for (int j0 = threadIdx.x; j0 < wlen; j0 += kPThreads * U) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * kPThreads;
+        v[u] = (j < wlen) ? src[j] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * kPThreads;
+        if (j < wlen) xl[j] = v[u];
+      }
+    }
+  } else {
+    for (int j0 = threadIdx.x; j0 < wlen; j0 += kPThreads * U) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * kPThreads;
+        v[u] = (j < wlen) ? combine_at(xin, g0 + j) : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * kPThreads;
+        if (j < wlen) xl[j] = v[u];
+      }
+    }
+  }
   if (threadIdx.x == 0) xl[t.W] = T(0);
   __syncthreads();
 
-  int16_t* lb = lb_all + wave * (kPSegMax + 2);
-  int32_t* lso = lso_all + wave * kPSegMax;
-  // Two-stage pipeline: the next chunk's loads are in flight while the
-  // current one is processed.
-  while (R0.valid) {
-    load_chunk(t, c + kPWaves, c_end, lane, R1);
-    process_chunk<T>(t, R0, c, lane, xl, lb, lso, part_out, piece_out);
-    if (!R1.valid) break;
-    load_chunk(t, c + 2 * kPWaves, c_end, lane, R0);
-    process_chunk<T>(t, R1, c + kPWaves, lane, xl, lb, lso, part_out, piece_out);
-    c += 2 * kPWaves;
+  // Two chunks in flight per wavefront: chunk k is processed while the loads
+  // of chunk k + 1 are outstanding.
+  for (int kb = 0; kb < K; kb += 64) {
+    if (kb > 0) {
+      nb = (K - kb) < 64 ? (K - kb) : 64;
+      load_meta(kb);
+      issue_chunk(t, M, 0, lane, R0);
+    }
+    const int cb = c_beg + kPWaves * kb;
+    for (int k = 0; k < nb; k += 2) {
+      if (k + 1 < nb) issue_chunk(t, M, k + 1, lane, R1);
+      process_chunk<T>(t, R0, cb + kPWaves * k, lane, xl, part_out, piece_out, out_scale);
+      if (k + 1 >= nb) break;
+      if (k + 2 < nb) issue_chunk(t, M, k + 2, lane, R0);
+      process_chunk<T>(t, R1, cb + kPWaves * (k + 1), lane, xl, part_out, piece_out, out_scale);
+    }
   }
 }
 
-static size_t pass_lds_bytes() {
-  return (size_t)kPanelBytes + (size_t)kPWaves * (kPSegMax + 2) * sizeof(int16_t) +
-         (size_t)kPWaves * kPSegMax * sizeof(int32_t);
-}
+static size_t pass_lds_bytes() { return (size_t)kPanelBytes; }
 
 hipError_t setup_pass_kernels() {
   const int bytes = (int)pass_lds_bytes();
@@ -358,10 +402,11 @@ hipError_t setup_pass_kernels() {
 
 template <typename T>
 hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
-                             T* piece_out, const int32_t* done, hipStream_t st) {
+                             T* piece_out, const T* out_scale, const int32_t* done,
+                             hipStream_t st) {
   if (t.nwg == 0) return hipSuccess;
   hipLaunchKernelGGL((k_panel<T>), dim3(t.nwg), dim3(kPThreads), pass_lds_bytes(), st, t, x,
-                     part_out, piece_out, done);
+                     part_out, piece_out, out_scale, done);
   return hipGetLastError();
 }
 
@@ -380,9 +425,10 @@ hipError_t launch_combine(const Combine<T>& c, int64_t dim, U* out, hipStream_t 
 }
 
 template hipError_t launch_panel_pass<float>(const PanelPass&, const Combine<float>&, float*,
-                                             float*, const int32_t*, hipStream_t);
+                                             float*, const float*, const int32_t*, hipStream_t);
 template hipError_t launch_panel_pass<double>(const PanelPass&, const Combine<double>&, double*,
-                                              double*, const int32_t*, hipStream_t);
+                                              double*, const double*, const int32_t*,
+                                              hipStream_t);
 template hipError_t launch_combine<float, float>(const Combine<float>&, int64_t, float*,
                                                  hipStream_t);
 template hipError_t launch_combine<double, double>(const Combine<double>&, int64_t, double*,

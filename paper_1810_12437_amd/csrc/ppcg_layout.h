@@ -6,11 +6,11 @@ namespace ppcg {
 
 constexpr int kPWaves = 16;            // wavefronts per pass workgroup
 constexpr int kPThreads = kPWaves * 64;
-constexpr int kPV = 16;                // elements per lane per chunk
-constexpr int kPC = 64 * kPV;          // window: elements one wavefront reads at once
-constexpr int kPPad = 16;              // chunks start and end on multiples of this
-constexpr int kPSegMax = 256;          // segments per packed chunk
+constexpr int kPV = 16;                // elements per lane (one group)
+constexpr int kPC = 64 * kPV;          // window: the elements one wavefront reads at once
+constexpr int kPNW = 2;                // windows of a packed chunk
+constexpr int kPGroups = 64 * kPNW;    // lane groups of a packed chunk
 constexpr int kPLongMax = 16 * kPC;    // longest segment a single wavefront sums whole
-constexpr int kPanelBytes = 128 * 1024;  // LDS for the gathered panel
+constexpr int kPanelBytes = 160 * 1024 - 64;  // LDS for the gathered panel (+ zero slot)
 
 }  // namespace ppcg

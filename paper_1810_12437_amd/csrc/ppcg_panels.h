@@ -17,8 +17,8 @@ namespace ppcg {
 struct PanelBuild {
   std::vector<uint16_t> idx;
   std::vector<int64_t> cstart;
-  std::vector<int32_t> cseg, cnseg, cboff;
-  std::vector<int16_t> bound16;
+  std::vector<int32_t> cseg, cnseg;
+  std::vector<uint64_t> cmask;
   std::vector<int32_t> seg_out;
   std::vector<int32_t> wg_panel, wg_c0, wg_c1;
   std::vector<int32_t> sp_off, sp_c0, sp_c1;
@@ -30,12 +30,14 @@ struct PanelBuild {
 // (increasing within a segment), gdim: gathered dimension, elem: bytes of
 // one gathered value, ncu: compute units to spread the workgroups over.
 //
-// Chunk kinds (cnseg): > 0 packs whole segments into one window of kPC
-// elements; 0 is one segment longer than a window, summed whole by one
-// wavefront; < 0 is a piece of a segment longer than kPLongMax (its sum goes
-// to the piece array and the consumer adds the pieces).  Every chunk is
-// padded with the sentinel index W (a zero in the LDS panel) to a multiple
-// of kPPad elements, so chunk windows are aligned and need no masking.
+// Every (segment, panel) is padded with the sentinel index W (a zero in the
+// LDS panel) to a multiple of kPV elements, so each lane's kPV elements
+// belong to one segment.  Chunk kinds (cnseg): > 0 packs whole padded
+// segments into up to kPNW windows (kPGroups groups of kPV elements), with
+// bit g of the chunk's kPNW mask words set when group g starts a segment; 0
+// is one segment longer than that, summed whole by one wavefront; < 0 is a
+// piece of a segment longer than kPLongMax (its sum goes to the piece array
+// and the consumer adds the pieces).
 void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& gidx,
                   int64_t out_dim, int64_t gdim, int elem, int ncu, PanelBuild& B) {
   B = PanelBuild();
@@ -50,12 +52,10 @@ void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& g
   std::vector<int32_t> pc0(B.npanels + 1, 0);
   std::vector<std::array<int32_t, 3>> splits;  // (segment id, c0, c1)
   std::vector<int64_t> seg_a, seg_e;           // element range of each (segment, panel)
-  auto pad_to = [&](int64_t len) { return (len + kPPad - 1) / kPPad * kPPad; };
+  auto groups = [&](int64_t len) { return (len + kPV - 1) / kPV; };
   auto append = [&](int64_t a, int64_t e, int64_t glo) {
     for (int64_t q = a; q < e; ++q) B.idx.push_back((uint16_t)(gidx[q] - glo));
-  };
-  auto pad_stream = [&]() {
-    while (B.idx.size() % kPPad) B.idx.push_back(sentinel);
+    while (B.idx.size() % kPV) B.idx.push_back(sentinel);
   };
   for (int32_t k = 0; k < B.npanels; ++k) {
     const int64_t hi = (int64_t)(k + 1) * B.W;
@@ -78,47 +78,39 @@ void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& g
     int64_t g = seg_first;
     while (g < seg_end) {
       const int64_t len = seg_e[g] - seg_a[g];
-      if (len > kPC) {
+      if (groups(len) > kPGroups) {
         if (len <= kPLongMax) {
           B.cstart.push_back((int64_t)B.idx.size());
           B.cseg.push_back((int32_t)g);
           B.cnseg.push_back(0);
-          B.cboff.push_back(0);
+          for (int q = 0; q < kPNW; ++q) B.cmask.push_back(0);
           append(seg_a[g], seg_e[g], glo);
-          pad_stream();
         } else {
           const int32_t c0 = (int32_t)B.cseg.size();
           for (int64_t o = seg_a[g]; o < seg_e[g]; o += kPLongMax) {
             B.cstart.push_back((int64_t)B.idx.size());
             B.cseg.push_back((int32_t)g);
             B.cnseg.push_back(-1);
-            B.cboff.push_back(0);
+            for (int q = 0; q < kPNW; ++q) B.cmask.push_back(0);
             append(o, std::min<int64_t>(o + kPLongMax, seg_e[g]), glo);
-            pad_stream();
           }
           splits.push_back({(int32_t)(B.seg_out[g] % out_dim), c0, (int32_t)B.cseg.size() - 1});
         }
         ++g;
       } else {
         const int64_t first = g;
-        int64_t total = 0;
-        while (g < seg_end && g - first < kPSegMax &&
-               pad_to(total + (seg_e[g] - seg_a[g])) <= kPC) {
-          total += seg_e[g] - seg_a[g];
+        int64_t used = 0;  // groups
+        uint64_t mask[kPNW] = {};
+        B.cstart.push_back((int64_t)B.idx.size());
+        while (g < seg_end && used + groups(seg_e[g] - seg_a[g]) <= kPGroups) {
+          mask[used / 64] |= 1ull << (used % 64);
+          used += groups(seg_e[g] - seg_a[g]);
+          append(seg_a[g], seg_e[g], glo);
           ++g;
         }
-        B.cstart.push_back((int64_t)B.idx.size());
         B.cseg.push_back((int32_t)first);
         B.cnseg.push_back((int32_t)(g - first));
-        B.cboff.push_back((int32_t)B.bound16.size());
-        int64_t o = 0;
-        for (int64_t x = first; x < g; ++x) {
-          B.bound16.push_back((int16_t)o);
-          append(seg_a[x], seg_e[x], glo);
-          o += seg_e[x] - seg_a[x];
-        }
-        pad_stream();
-        B.bound16.push_back((int16_t)pad_to(o));  // the last segment absorbs the padding
+        for (int q = 0; q < kPNW; ++q) B.cmask.push_back(mask[q]);
       }
     }
   }
