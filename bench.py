@@ -2,16 +2,19 @@
 """Throughput of the prior-preconditioned CG sampler on one MI355X.
 
 A step is one Gibbs beta-draw (Prop 2.1): counter-based eta and delta, the
-right-hand side b, prior-preconditioned CG to the stopping rule, the FP64 true
-residual and, in the FP32 form, the refinement restart when the true residual
-misses the rule.  The workload is n = 1e5 observations, p = 2e4 binary
-features with log-uniform column densities in [1e-4, 0.2], tau = 1e-3 and
-50 signal columns, relative preconditioned residual 1e-6.
+right-hand side b, prior-preconditioned CG to the stopping rule and the FP64
+true residual of the result.  The workload is n = 1e5 observations, p = 2e4
+binary features with log-uniform column densities in [1e-4, 0.2], tau = 1e-3
+and 50 signal columns, relative preconditioned residual 1e-6.
 
-Prints one JSON line (rank 0): draws/s of the chosen form (FP32 vectors,
-FP64 scalars), with the plain FP64 form, the HBM roofline of the dominant
-kernel (the X pass, timed with HIP events on the solver's stream during the
-timed draws) and the CPU oracle timed on this host as a baseline.
+Prints one JSON line: draws/s of the headline form (FP64 vectors and
+scalars, the faster form at the 1e-5 accuracy bar), the FP32-vector form with
+its FP64 refinement beside it, the HBM roofline of the dominant kernel (the X
+pass, timed with HIP events on the solver's stream during the timed draws)
+and the CPU oracle timed on this host as a baseline.
+
+``--copy-calibration`` instead times a plain 512 MiB device copy: its
+FETCH_SIZE / WRITE_SIZE counters calibrate the pass kernel's counters.
 """
 from __future__ import annotations
 
@@ -29,6 +32,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "Gibbs beta-draws/sec + SpMV-CG HBM GB/s (% peak), n=1e5 p=2e4, rel err<=1e-5"
 SEED = 12437
+COPY_BYTES = 512 << 20
+
+# HBM traffic of one k_panel<double> launch on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean
+# over the launches of the timed draws) scaled by the same counters of a
+# plain 512 MiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for
+# the kernel sources it was measured on (SHA-256 over the files below); any
+# change to them reports null until the counters are taken again.
+PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
+                "paper_1810_12437_amd/csrc/ppcg_layout.h",
+                "paper_1810_12437_amd/csrc/ppcg_panels.h")
+TRAFFIC = {
+    "sources_sha256": "bdab65202b2239311cbef5c2fa457adc149b54863c3980800355cca9377a0879",
+    # (55,864.6 KiB FETCH_SIZE x 2.0 + 787.3 KiB WRITE_SIZE x 1.0) x 1024
+    "bytes_per_launch": 115216966,
+}
 
 
 def parse():
@@ -38,24 +57,35 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 form")
+    ap.add_argument("--no-f32", action="store_true", help="skip the FP32-vector form")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the accuracy check of the timed configuration")
     ap.add_argument("--cpu-iters", type=int, default=40,
                     help="oracle CG iterations in the bounded CPU sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only time a plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
-def pass_bytes(P, sv):
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in PASS_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def int32_pass_bytes(P, sv):
     """Bytes one launch of each X pass would move in a plain int32 CSR / CSC
     format (index stream, offsets, gathered vector once, scale, output); the
     int32-equivalent rate of the 16-bit panel format is reported beside its
     own."""
     nnz, n, p = P.nnz, P.n, P.p
-    chunk = 2048
-    nch = (nnz + chunk - 1) // chunk
     rows = int(np.count_nonzero(np.diff(P.row_ptr)))
     cols = int(np.count_nonzero(np.bincount(P.col_idx, minlength=p)))
-    csr = 4 * nnz + 8 * (rows + 1) + 4 * rows + 8 * nch + sv * p + sv * n + sv * rows
-    csc = 4 * nnz + 8 * (cols + 1) + 4 * cols + 8 * nch + sv * n + sv * cols
+    csr = 4 * nnz + 8 * (rows + 1) + sv * p + sv * n + sv * rows
+    csc = 4 * nnz + 8 * (cols + 1) + sv * n + sv * cols
     return csr, csc
 
 
@@ -68,7 +98,7 @@ def vec_bytes(p, sv):
     return dot + upd + direc
 
 
-def run_form(pk, torch, X, P, dtype, steps, warmup, tol, profile):
+def run_form(pk, torch, X, P, dtype, steps, warmup, tol):
     dt = torch.float32 if dtype == pk.F32 else torch.float64
     om = torch.as_tensor(P.omega, device="cuda").to(dt)
     z = torch.as_tensor(P.z, device="cuda").to(dt)
@@ -76,8 +106,7 @@ def run_form(pk, torch, X, P, dtype, steps, warmup, tol, profile):
     for w in range(warmup):
         pk.draw(X, om, z, lam, P.tau, SEED, 0, 1000 + w, tol=tol)
     torch.cuda.synchronize()
-    if profile:
-        X.profile(True)
+    X.profile(True)
     infos = []
     t0 = time.perf_counter()
     for k in range(steps):
@@ -85,10 +114,34 @@ def run_form(pk, torch, X, P, dtype, steps, warmup, tol, profile):
         infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stats = X.stats() if profile else None
-    if profile:
-        X.profile(False)
-    return t1 - t0, infos, stats
+    stats = X.stats()
+    X.profile(False)
+    iters = np.array([i["iters"] + i["refine_iters"] for i in infos], dtype=np.float64)
+    return {"elapsed": t1 - t0, "infos": infos, "stats": stats, "iters": iters}
+
+
+def pass_time_ms(st):
+    return (st["csr_ms"] + st["csc_ms"]) / max(st["csr_launches"] + st["csc_launches"], 1)
+
+
+def check_accuracy(pk, torch, X, P, tol):
+    """Relative error of draw (SEED, 0, 0) of each form against the oracle's
+    solution of the same draw (stored by the oracle-only script
+    tests/golden/make_c1_reference.py)."""
+    gold = os.path.join(ROOT, "tests", "golden", "c1_draw0_reference.npz")
+    if not os.path.exists(gold):
+        return {}
+    g = np.load(gold)
+    out = {}
+    for name, dt, key in (("f64", torch.float64, "beta_f64"), ("f32", torch.float32, "beta_f32")):
+        om = torch.as_tensor(P.omega, device="cuda").to(dt)
+        zz = torch.as_tensor(P.z, device="cuda").to(dt)
+        la = torch.as_tensor(P.lam, device="cuda").to(dt)
+        b0, _ = pk.draw(X, om, zz, la, P.tau, int(g["seed"]), int(g["chain"]), int(g["draw"]),
+                        tol=tol)
+        ref = g[key]
+        out[name] = float(np.linalg.norm(b0.double().cpu().numpy() - ref) / np.linalg.norm(ref))
+    return out
 
 
 def cpu_baseline(P, K_mean, tol, iters):
@@ -118,13 +171,38 @@ def cpu_baseline(P, K_mean, tol, iters):
     }
 
 
+def copy_calibration():
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    best = min(ms)
+    print(json.dumps({"copy_calibration": {"bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES,
+                                           "best_ms": best,
+                                           "gbps": 2 * COPY_BYTES / (best * 1e-3) / 1e9}}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the sampler's "
-              "data-parallel path is measured on a single MI355X; see DESIGN.md for how it "
-              "would shard.", file=sys.stderr)
+              "data-parallel path is measured on a single MI355X (a multi-GPU run would "
+              "row-partition X and all-reduce one p-vector per CG iteration).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     import paper_1810_12437_amd as pk
@@ -134,32 +212,22 @@ def main():
     print("[bench] generating workload n=1e5 p=2e4 ...", file=sys.stderr, flush=True)
     P = synth.make_problem("c1")
     X = pk.Matrix.from_problem(P)
-    print(f"[bench] nnz={P.nnz}; timing FP32 form ({args.warmup}+{args.steps} draws)",
-          file=sys.stderr, flush=True)
-    rel_err = None
-    gold = os.path.join(ROOT, "tests", "golden", "c1_draw0_reference.npz")
-    if os.path.exists(gold):
-        # Accuracy of the timed configuration: draw (SEED, 0, 0) against the
-        # oracle's solution of the same draw (stored by the oracle-only script
-        # tests/golden/make_c1_reference.py).
-        g = np.load(gold)
-        om = torch.as_tensor(P.omega, device="cuda").float()
-        zz = torch.as_tensor(P.z, device="cuda").float()
-        la = torch.as_tensor(P.lam, device="cuda").float()
-        b0, _ = pk.draw(X, om, zz, la, P.tau, int(g["seed"]), int(g["chain"]), int(g["draw"]),
-                        tol=args.tol)
-        ref = g["beta_f32"]
-        rel_err = float(np.linalg.norm(b0.double().cpu().numpy() - ref) / np.linalg.norm(ref))
-    el, infos, st = run_form(pk, torch, X, P, pk.F32, args.steps, args.warmup, args.tol, True)
-    iters = np.array([i["iters"] + i["refine_iters"] for i in infos], dtype=np.float64)
+    rel = {} if args.no_check else check_accuracy(pk, torch, X, P, args.tol)
+    print(f"[bench] nnz={P.nnz}; rel err vs oracle {rel}; timing FP64 form "
+          f"({args.warmup}+{args.steps} draws)", file=sys.stderr, flush=True)
+    r64 = run_form(pk, torch, X, P, pk.F64, args.steps, args.warmup, args.tol)
+    el, st, iters = r64["elapsed"], r64["stats"], r64["iters"]
     K = float(iters.mean())
-    csr_b, csc_b = X.pass_bytes(pk.F32)
-    csr_i32, csc_i32 = pass_bytes(P, 4)
-    t_pass = (st["csr_ms"] + st["csc_ms"]) / max(st["csr_launches"] + st["csc_launches"], 1)
+    csr_b, csc_b = X.pass_bytes(pk.F64)
+    csr_i32, csc_i32 = int32_pass_bytes(P, 8)
+    t_pass = pass_time_ms(st)
     bytes_per_launch = 0.5 * (csr_b + csc_b)
     achieved = bytes_per_launch / (t_pass * 1e-3) / 1e9
-    iter_bytes = csr_b + csc_b + vec_bytes(P.p, 4)
+    iter_bytes = csr_b + csc_b + vec_bytes(P.p, 8)
     cg_gbps = iter_bytes * iters.sum() / el / 1e9
+    traffic = None
+    if TRAFFIC["bytes_per_launch"] is not None and TRAFFIC["sources_sha256"] == sources_sha256():
+        traffic = TRAFFIC["bytes_per_launch"]
     out = {
         "metric": METRIC,
         "value": args.steps / el,
@@ -171,44 +239,45 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": ("n=1e5 p=2e4 binary X, column densities log-uniform [1e-4, 0.2], "
-                         "tau=1e-3, 50 signal columns; FP32 vectors + FP64 scalars; "
+                         "tau=1e-3, 50 signal columns; FP64 vectors and scalars; "
                          f"relative preconditioned residual {args.tol:g}"),
             "nnz": P.nnz, "n": P.n, "p": P.p, "tol": args.tol, "seed": SEED,
         },
-        "rel_err_vs_oracle": rel_err,
+        "rel_err_vs_oracle": rel.get("f64"),
         "cg_iters_mean": K,
         "cg_iters_per_s": float(iters.sum() / el),
         "cg_hbm_gbps": cg_gbps,
         "cg_hbm_frac": cg_gbps / HBM_PEAK_GBPS,
-        "refined_draws": int(sum(i["refined"] for i in infos)),
-        "max_true_resid_over_tol": float(max(i["resid_true"] for i in infos)),
+        "max_true_resid_over_tol": float(max(i["resid_true"] for i in r64["infos"])),
         "roofline": {
-            "kernel": "k_panel<float> (row pass X s and column pass X^T u)",
+            "kernel": "k_panel<double> (row pass X s and column pass X^T u)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
             "avg_launch_us": 1e3 * t_pass,
             "row_pass_us": 1e3 * st["csr_ms"] / max(st["csr_launches"], 1),
             "col_pass_us": 1e3 * st["csc_ms"] / max(st["csc_launches"], 1),
+            "launches": st["csr_launches"] + st["csc_launches"],
             "bytes_per_launch": bytes_per_launch,
             "int32_csr_csc_equiv_gbps": 0.5 * (csr_i32 + csc_i32) / (t_pass * 1e-3) / 1e9,
         },
     }
-    if not args.no_f64:
-        steps64 = max(3, args.steps // 4)
-        print(f"[bench] timing FP64 form (1+{steps64} draws)", file=sys.stderr, flush=True)
-        el64, inf64, st64 = run_form(pk, torch, X, P, pk.F64, steps64, 1, args.tol, True)
-        it64 = np.array([i["iters"] + i["refine_iters"] for i in inf64], dtype=np.float64)
-        c64, s64 = X.pass_bytes(pk.F64)
-        t64 = (st64["csr_ms"] + st64["csc_ms"]) / max(st64["csr_launches"] + st64["csc_launches"], 1)
-        out["plain_f64"] = {
-            "draws_per_s": steps64 / el64, "cg_iters_mean": float(it64.mean()),
-            "cg_iters_per_s": float(it64.sum() / el64),
-            "cg_hbm_gbps": (c64 + s64 + vec_bytes(P.p, 8)) * it64.sum() / el64 / 1e9,
-            "pass_gbps": 0.5 * (c64 + s64) / (t64 * 1e-3) / 1e9,
+    if not args.no_f32:
+        steps32 = max(3, args.steps // 2)
+        print(f"[bench] timing FP32-vector form (1+{steps32} draws)", file=sys.stderr, flush=True)
+        r32 = run_form(pk, torch, X, P, pk.F32, steps32, 1, args.tol)
+        c32, s32 = X.pass_bytes(pk.F32)
+        it32 = r32["iters"]
+        out["f32_form"] = {
+            "draws_per_s": steps32 / r32["elapsed"], "cg_iters_mean": float(it32.mean()),
+            "cg_iters_per_s": float(it32.sum() / r32["elapsed"]),
+            "cg_hbm_gbps": (c32 + s32 + vec_bytes(P.p, 4)) * it32.sum() / r32["elapsed"] / 1e9,
+            "pass_gbps": 0.5 * (c32 + s32) / (pass_time_ms(r32["stats"]) * 1e-3) / 1e9,
+            "refined_draws": int(sum(i["refined"] for i in r32["infos"])),
+            "rel_err_vs_oracle": rel.get("f32"),
         }
     if not args.no_cpu:
         print(f"[bench] CPU oracle sample ({args.cpu_iters} iterations)", file=sys.stderr,

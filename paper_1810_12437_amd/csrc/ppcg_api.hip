@@ -44,7 +44,7 @@ struct DevBuf {
 struct Orient {
   PanelPass pass{};
   void* part = nullptr;   // [npanels][out_dim] segment sums (zero where absent)
-  void* piece = nullptr;  // [nchunks] piece sums
+  void* piece = nullptr;  // [npieces] piece sums
   const int32_t* sp_off = nullptr;
   const int32_t* sp_c0 = nullptr;
   const int32_t* sp_c1 = nullptr;
@@ -110,14 +110,10 @@ int upload_orient(ppcg_matrix* X, const PanelBuild& B, int elem, Orient& o) {
   int64_t by = 0;
   PanelPass& t = o.pass;
   if ((rc = upload_vec(X, B.idx, &t.idx, &by))) return rc;
-  if ((rc = upload_vec(X, B.cstart, &t.cstart, &by))) return rc;
-  if ((rc = upload_vec(X, B.cseg, &t.cseg, &by))) return rc;
-  if ((rc = upload_vec(X, B.cnseg, &t.cnseg, &by))) return rc;
-  if ((rc = upload_vec(X, B.cmask, &t.cmask, &by))) return rc;
+  if ((rc = upload_vec(X, B.chunks, &t.chunks, &by))) return rc;
   if ((rc = upload_vec(X, B.seg_out, &t.seg_out, &by))) return rc;
   if ((rc = upload_vec(X, B.wg_panel, &t.wg_panel, &by))) return rc;
-  if ((rc = upload_vec(X, B.wg_c0, &t.wg_c0, &by))) return rc;
-  if ((rc = upload_vec(X, B.wg_c1, &t.wg_c1, &by))) return rc;
+  if ((rc = upload_vec(X, B.wave_c, &t.wave_c, &by))) return rc;
   if (!B.sp_off.empty()) {
     if ((rc = upload_vec(X, B.sp_off, &o.sp_off, &by))) return rc;
     if ((rc = upload_vec(X, B.sp_c0, &o.sp_c0, &by))) return rc;
@@ -126,25 +122,26 @@ int upload_orient(ppcg_matrix* X, const PanelBuild& B, int elem, Orient& o) {
   t.gdim = B.gdim;
   t.W = B.W;
   t.nwg = (int32_t)B.wg_panel.size();
-  t.nchunks = (int32_t)B.cseg.size();
+  t.nchunks = (int32_t)B.chunks.size();
+  t.npieces = B.npieces;
   o.npanels = B.npanels;
   o.out_dim = B.out_dim;
   const size_t part_bytes = (size_t)B.npanels * (size_t)B.out_dim * (size_t)elem;
   unsigned char* part = nullptr;
   unsigned char* piece = nullptr;
   PPCG_TRY_ALLOC(X->mem.alloc(&part, part_bytes));
-  PPCG_TRY_ALLOC(X->mem.alloc(&piece, (size_t)std::max<int32_t>(t.nchunks, 1) * elem));
+  PPCG_TRY_ALLOC(X->mem.alloc(&piece, (size_t)std::max<int32_t>(t.npieces, 1) * elem));
   // (segment, panel) pairs with no elements are never written: they stay zero.
   PPCG_TRY_HIP(hipMemset(part, 0, std::max<size_t>(part_bytes, 1)));
   o.part = part;
   o.piece = piece;
-  o.dev_bytes = by + (int64_t)part_bytes + (int64_t)t.nchunks * elem;
-  // Per launch: the padded index stream, the chunk tables (cstart, cseg,
-  // cnseg, cmask), output slots, one segment sum per (segment, panel), and
-  // the gathered vector once (its panel copies come from cache).
-  const int64_t nseg = (int64_t)B.seg_out.size();
-  o.pass_bytes = 2 * (int64_t)B.idx.size() + (16 + 8 * kPNW) * (int64_t)t.nchunks + 4 * nseg +
-                 (int64_t)elem * nseg + (int64_t)elem * B.gdim;
+  o.dev_bytes = by + (int64_t)part_bytes + (int64_t)t.npieces * elem;
+  // Per launch: the padded index stream, the chunk descriptors, the output
+  // slots, one sum per (segment, panel) pair, and the gathered vector once
+  // (its panel copies come from cache).
+  o.pass_bytes = 2 * (int64_t)B.idx.size() + (int64_t)sizeof(ChunkDesc) * t.nchunks +
+                 4 * (int64_t)B.seg_out.size() + (int64_t)elem * B.nseg +
+                 (int64_t)elem * B.gdim;
   return PPCG_OK;
 }
 

@@ -15,30 +15,25 @@ constexpr int kMaxRedBlocks = 1024; // max workgroups of a p-vector phase
 // One orientation of X (rows of CSR for v -> X v, columns of CSC for
 // w -> X^T w) in a panel-blocked, index-only layout.  The gathered
 // dimension is cut into panels of at most W entries so that a panel of the
-// gathered vector fits in LDS; within panel k the non-empty (segment, panel)
-// pairs are stored consecutively with 16-bit indices local to the panel,
-// each padded with the index W (an LDS zero) to a multiple of kPV, so one
-// lane's kPV elements always belong to one segment.  Chunks: a packed chunk
-// (cnseg > 0) holds whole padded segments in up to kPNW windows of kPC
-// elements, bit g of its kPNW mask words marking the kPV-element groups that
-// start a segment; a long chunk (cnseg == 0) is one segment summed whole; a
-// piece (cnseg < 0) is part of a segment longer than kPLongMax whose piece
-// sums the consumer adds.
-// Workgroup w serves one panel and owns the chunk range [wg_c0[w], wg_c1[w]).
+// gathered vector fits in LDS; the elements of each (segment, panel) pair are
+// stored as 16-bit indices local to the panel, in groups of kPV padded with
+// the index W (an LDS zero).  Chunks (ChunkDesc, ppcg_layout.h) are the units
+// a wavefront reads: packed chunks give each of their segments a lane range
+// for up to kPR windows, long chunks run one segment over up to kPLongWin
+// windows, and pieces are parts of a longer segment whose sums the consumer
+// adds.  Workgroup w serves panel wg_panel[w]; its wavefront q runs the
+// chunks [wave_c[kPWaves w + q], wave_c[kPWaves w + q + 1]) in order.
 struct PanelPass {
-  const uint16_t* idx;     // [stream] panel-local gathered index (padded)
-  const int64_t* cstart;   // [nchunks + 1] first element of each chunk; last = stream end
-  const int32_t* cseg;     // [nchunks] first (or the long) segment
-  const int32_t* cnseg;    // [nchunks] segments of a packed chunk; 0 long; < 0 piece
-  const uint64_t* cmask;   // [nchunks * kPNW] groups that start a segment (packed chunks)
-  const int32_t* seg_out;  // [nseg] output slot = panel * out_dim + segment id
-  const int32_t* wg_panel; // [nwg]
-  const int32_t* wg_c0;    // [nwg]
-  const int32_t* wg_c1;    // [nwg]
-  int64_t gdim;            // gathered dimension (p for rows, n for columns)
-  int32_t W;               // panel width
+  const uint16_t* idx;      // [stream] panel-local gathered index (padded)
+  const ChunkDesc* chunks;  // [nchunks]
+  const int32_t* seg_out;   // [entries] output slot = panel * out_dim + segment id
+  const int32_t* wg_panel;  // [nwg]
+  const int32_t* wave_c;    // [kPWaves * nwg + 1]
+  int64_t gdim;             // gathered dimension (p for rows, n for columns)
+  int32_t W;                // panel width
   int32_t nwg;
   int32_t nchunks;
+  int32_t npieces;
 };
 
 // value(i) = scale[i] * (sum_k part[k * stride + i] + sum of the pieces of i):
@@ -51,9 +46,9 @@ struct Combine {
   int32_t pad;
   const T* scale;         // may be null
   const int32_t* sp_off;  // [dim + 1] pieces of element i (null: none)
-  const int32_t* sp_c0;   // piece chunk ranges [c0, c1]
+  const int32_t* sp_c0;   // piece id ranges [c0, c1]
   const int32_t* sp_c1;
-  const T* piece;         // [nchunks] piece sums
+  const T* piece;         // [npieces] piece sums
 };
 
 // Scalars of one CG run, in device memory.

@@ -2,19 +2,19 @@
 //
 // Hot path of one CG iteration (Supplement S2 with the prior preconditioner
 // of Section 2.4):
-//   pass 1 (CSR): u = omega .* (X s)        -- v -> X v, then Omega
-//   pass 2 (CSC): q = X^T u                  -- w -> X^T w
-//   phase A     : <s, q + d .* s>  ->  alpha
-//   phase B     : beta += alpha s, r -= alpha (q + d s), z = M^-1 r, rho'
-//   phase C     : s = z + (rho'/rho) s
-// X is binary, so both passes are segmented gather-sums over int32 index
-// streams with no value array.  The passes split the index stream into
-// equal chunks of C = 256 * V elements per workgroup, so column lengths that
-// span three orders of magnitude stay load balanced; segments (rows or
-// columns) that cross a chunk boundary are finished by the last chunk to
-// arrive, summing the chunk partials in chunk order, so every result is
-// bitwise reproducible.  Reductions of the p-vector phases are fixed-order
-// too.
+//   row pass    : u = omega .* (X s)        -- v -> X v, then Omega
+//   column pass : q = X^T u                  -- w -> X^T w
+//   dot phase   : <s, q + d .* s>  ->  alpha
+//   update      : beta += alpha s, r -= alpha (q + d s), rho' = <r, M^-1 r>
+//   direction   : s = M^-1 r + (rho'/rho) s
+// X is binary, so both passes are segmented gather-sums over 16-bit
+// panel-local index streams with no value array: a workgroup holds one panel
+// of the gathered vector in LDS, each wavefront runs its own list of chunks,
+// every lane of a chunk sums groups of one segment across the chunk's
+// windows, and one DPP segmented scan per chunk combines the lanes of each
+// segment.  Every output has one writer and every sum has a fixed order, so
+// results are bitwise reproducible.  Reductions of the p-vector phases are
+// fixed-order too.
 #include "ppcg_kernels.h"
 
 #include <math.h>
@@ -123,23 +123,59 @@ __device__ __forceinline__ T combine_at(const Combine<T>& c, int64_t i) {
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-// One chunk in flight: its bounds and segment-start masks (wave-uniform),
-// this lane's kPV indices in each window, and for a packed chunk the output
-// slot of segment kfirst(q) + lane of each window q.
-struct ChunkRegs {
-  int64_t base;
-  uint64_t mask[kPNW];
-  int len, sf, nsg;
-  u16x8 a[kPNW], b[kPNW];
-  int32_t so[kPNW];
+__device__ __forceinline__ int ck_windows(int32_t info) { return info & 0xff; }
+__device__ __forceinline__ int ck_kind(int32_t info) { return (info >> 8) & 3; }
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ int bits_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// DPP move of x from another lane (0 where the source is outside the row or
+// the row is not selected by RM).
+template <int CTRL, int RM>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, RM, 0xf, true));
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, RM, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, RM, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
+constexpr int kDppRowShr = 0x110;   // row_shr:n = 0x110 + n (within 16-lane rows)
+constexpr int kDppBcast15 = 0x142;  // lane 15 of each row to the next row
+constexpr int kDppBcast31 = 0x143;  // lane 31 to rows 2 and 3
+
+// This lane's groups in the first kPR windows of a chunk: bit s of `has` is
+// set when the lane has a group in window s, at element base + rel[s].
+struct LaneWindows {
+  int32_t rel[kPR];
+  uint32_t has;
 };
 
-// Metadata of up to 64 chunks of one wavefront, one chunk per lane.
-struct ChunkMeta {
-  int64_t cs, ce;
-  uint64_t mask[kPNW];
-  int sf, nsg;
-};
+__device__ __forceinline__ void lane_windows(const ChunkDesc& D, int lane, LaneWindows& L) {
+  L.has = 0;
+  if (ck_kind(D.info) == kChunkPacked) {
+    int pre = 0;
+#pragma unroll
+    for (int s = 0; s < kPR; ++s) {
+      const uint64_t m = D.vm[s];
+      L.rel[s] = (pre + bits_below(m)) * kPV;
+      if ((m >> lane) & 1ull) L.has |= 1u << s;
+      pre += __popcll(m);
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < kPR; ++s) {
+      L.rel[s] = s * kPC + lane * kPV;
+      if ((int64_t)L.rel[s] < (int64_t)D.vm[0]) L.has |= 1u << s;
+    }
+  }
+}
 
 __device__ __forceinline__ void load_window(const PanelPass& t, int64_t at, u16x8& a,
                                             u16x8& b) {
@@ -149,50 +185,16 @@ __device__ __forceinline__ void load_window(const PanelPass& t, int64_t at, u16x
   b = __builtin_nontemporal_load(ip + 1);
 }
 
-__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ float readlane_t(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double readlane_t(double v, int l) {
-  return __longlong_as_double(readlane64(__double_as_longlong(v), l));
-}
-
-// First segment (chunk-relative) of window q: the one continuing into it,
-// or the first one starting in it.
-__device__ __forceinline__ int window_first_key(const uint64_t* mask, int q) {
-  int pre = 0;
-#pragma unroll
-  for (int i = 0; i < kPNW; ++i)
-    if (i < q) pre += __popcll(mask[i]);
-  return (mask[q] & 1ull) ? pre : pre - 1;
-}
-
-// Issues the loads of chunk number k of the metadata block held in M.
-__device__ __forceinline__ void issue_chunk(const PanelPass& t, const ChunkMeta& M, int k,
-                                            int lane, ChunkRegs& R) {
-  R.base = readlane64(M.cs, k);
-  R.len = (int)(readlane64(M.ce, k) - R.base);  // a multiple of kPV
-  R.sf = __builtin_amdgcn_readlane(M.sf, k);
-  R.nsg = __builtin_amdgcn_readlane(M.nsg, k);
-#pragma unroll
-  for (int q = 0; q < kPNW; ++q) R.mask[q] = (uint64_t)readlane64((int64_t)M.mask[q], k);
-  const int e0 = lane * kPV;
-  const int nw = R.nsg > 0 ? (R.len + kPC - 1) / kPC : 1;
-#pragma unroll
-  for (int q = 0; q < kPNW; ++q)
-    if (q < nw && q * kPC + e0 < R.len) load_window(t, R.base + q * kPC + e0, R.a[q], R.b[q]);
-  if (R.nsg > 0) {
-#pragma unroll
-    for (int q = 0; q < kPNW; ++q) {
-      const int kk = window_first_key(R.mask, q) + lane;
-      R.so[q] = (q < nw && kk < R.nsg) ? t.seg_out[R.sf + kk] : 0;
-    }
-  }
+// Output slot of this lane for chunk D: packed chunks write from the last
+// lane of each segment's slice, long chunks from lane 63; -1: no write.
+__device__ __forceinline__ int32_t out_slot(const PanelPass& t, const ChunkDesc& D, int lane) {
+  const int kind = ck_kind(D.info);
+  if (kind == kChunkLong) return t.seg_out[D.first];
+  if (kind == kChunkPiece) return -1;
+  const uint64_t sm = D.sm;
+  const bool last = lane == 63 || ((sm >> (lane + 1)) & 1ull);
+  const int si = bits_below(sm) + (int)((sm >> lane) & 1ull) - 1;
+  return (last && si < (D.info >> 24)) ? t.seg_out[D.first + si] : -1;
 }
 
 template <typename T>
@@ -209,82 +211,59 @@ __device__ __forceinline__ T gather_sum16(const T* xl, const u16x8& a, const u16
   return s;
 }
 
-// Output of one segment sum: the panel-partial slot, scaled by out_scale of
-// the segment (row pass with a single panel) when given.
+// Sum of each slice of chunk D at the slice's last lane (packed), or of the
+// whole wavefront at lane 63 (long), then the write.  Fixed order.
 template <typename T>
-__device__ __forceinline__ void put(T* __restrict__ part_out, const T* __restrict__ out_scale,
-                                    int32_t slot, T v) {
-  part_out[slot] = out_scale ? v * out_scale[slot] : v;
-}
-
-template <typename T>
-__device__ __forceinline__ void process_chunk(const PanelPass& t, const ChunkRegs& R, int c,
-                                              int lane, const T* xl, T* __restrict__ part_out,
-                                              T* __restrict__ piece_out,
-                                              const T* __restrict__ out_scale) {
-  const int e0 = lane * kPV;
-  const int len = R.len, nsg = R.nsg;
-  if (nsg <= 0) {
-    // One long segment (or a piece of one): each lane sums its share of
-    // every window, the next window's indices in flight, then a fixed-order
-    // wavefront sum.
-    const int32_t slot = (nsg == 0) ? t.seg_out[R.sf] : 0;
-    T acc = T(0);
-    u16x8 a = R.a[0], b = R.b[0];
-    for (int w0 = 0; w0 < len; w0 += kPC) {
-      const bool have = e0 + w0 < len;
-      const bool next = e0 + w0 + kPC < len;
-      u16x8 na, nb;
-      if (next) load_window(t, R.base + e0 + w0 + kPC, na, nb);
-      if (have) acc += gather_sum16(xl, a, b);
-      if (next) {
-        a = na;
-        b = nb;
-      }
+__device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T acc, int32_t slot,
+                                             T scl, int32_t piece, int lane,
+                                             T* __restrict__ part_out,
+                                             T* __restrict__ piece_out,
+                                             const T* __restrict__ out_scale) {
+  const int kind = ck_kind(info);
+  if (kind == kChunkPacked) {
+    // Segmented inclusive scan over the slices: row-local shifts, then the
+    // row-to-row broadcasts, each taken only from lanes of the same slice.
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int off = lane - (63 - __clzll(sm & upto));
+    const int nrow = (info >> 12) & 7;
+    if (nrow > 0) {
+      const T v = dpp_move<kDppRowShr + 1, 0xf>(acc);
+      if (off >= 1) acc += v;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) {
-      if (nsg == 0)
-        put(part_out, out_scale, slot, acc);
-      else
-        piece_out[c] = acc;
+    if (nrow > 1) {
+      const T v = dpp_move<kDppRowShr + 2, 0xf>(acc);
+      if (off >= 2) acc += v;
     }
+    if (nrow > 2) {
+      const T v = dpp_move<kDppRowShr + 4, 0xf>(acc);
+      if (off >= 4) acc += v;
+    }
+    if (nrow > 3) {
+      const T v = dpp_move<kDppRowShr + 8, 0xf>(acc);
+      if (off >= 8) acc += v;
+    }
+    if ((info >> 16) & 1) {
+      const T v = dpp_move<kDppBcast15, 0xa>(acc);
+      if (off > (lane & 15)) acc += v;
+    }
+    if ((info >> 17) & 1) {
+      const T v = dpp_move<kDppBcast31, 0xc>(acc);
+      if (off >= lane - 31) acc += v;
+    }
+    if (slot >= 0) part_out[slot] = out_scale ? acc * scl : acc;
     return;
   }
-  // Packed chunk, window by window: a lane sums its group; lanes of one
-  // segment are contiguous; a lane's segment (chunk-relative) is the number
-  // of segment starts at or before its group, minus one.  The running sum of
-  // a segment that crosses into the next window is carried by lane 63.
-  const int nw = (len + kPC - 1) / kPC;
-  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-  int carry_key = -1;
-  T carry_val = T(0);
-  int pre = 0;
-#pragma unroll
-  for (int q = 0; q < kPNW; ++q) {
-    if (q < nw) {
-      const bool active = q * kPC + e0 < len;
-      T val = active ? gather_sum16(xl, R.a[q], R.b[q]) : T(0);
-      const int kfirst = (R.mask[q] & 1ull) ? pre : pre - 1;
-      const int key = active ? (pre + __popcll(R.mask[q] & upto) - 1) : nsg;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int ku = __shfl_up(key, d, 64);
-        const T vu = __shfl_up(val, d, 64);
-        if (lane >= d && ku == key) val += vu;
-      }
-      if (key == carry_key) val += carry_val;
-      const bool cont = (q + 1 < nw) && !(R.mask[q + 1 < kPNW ? q + 1 : q] & 1ull);
-      const int knext = __shfl_down(key, 1, 64);
-      const int rel = key - kfirst;
-      const int32_t slot = __shfl(R.so[q], (rel >= 0 && rel < 64) ? rel : 0, 64);
-      const bool last = active && (lane == 63 ? !cont : knext != key);
-      if (last) put(part_out, out_scale, slot, val);
-      carry_key = __builtin_amdgcn_readlane(key, 63);
-      carry_val = readlane_t(val, 63);
-      pre += __popcll(R.mask[q]);
-    }
+  acc += dpp_move<kDppRowShr + 1, 0xf>(acc);
+  acc += dpp_move<kDppRowShr + 2, 0xf>(acc);
+  acc += dpp_move<kDppRowShr + 4, 0xf>(acc);
+  acc += dpp_move<kDppRowShr + 8, 0xf>(acc);
+  acc += dpp_move<kDppBcast15, 0xa>(acc);
+  acc += dpp_move<kDppBcast31, 0xc>(acc);
+  if (lane == 63) {
+    if (kind == kChunkLong)
+      part_out[slot] = out_scale ? acc * scl : acc;
+    else
+      piece_out[piece] = acc;
   }
 }
 
@@ -299,34 +278,34 @@ __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin
   T* xl = reinterpret_cast<T*>(smem);
 
   const int w = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c_beg = t.wg_c0[w] + wave, c_end = t.wg_c1[w];
-  // This wavefront's chunks: c_beg, c_beg + kPWaves, ...
-  const int K = c_beg < c_end ? (c_end - c_beg + kPWaves - 1) / kPWaves : 0;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  // This wavefront's chunks, in order.
+  int c = t.wave_c[kPWaves * w + wave];
+  const int c_end = t.wave_c[kPWaves * w + wave + 1];
 
-  ChunkMeta M;
-  ChunkRegs R0, R1;
-  auto load_meta = [&](int kb) {
-    const int c = c_beg + kPWaves * (kb + lane);
-    if (kb + lane < K) {
-      M.cs = t.cstart[c];
-      M.ce = t.cstart[c + 1];
+  // Each window of a chunk has a register slot (window k in slot k % kPR);
+  // a slot is refilled as soon as its window has been summed, with the
+  // chunk's window k + kPR or else the next chunk's window in that slot.
+  u16x8 sa[kPR], sb[kPR];
+  int32_t cinfo = 0, cfirst = 0, slot = -1;
+  int64_t cbase = 0, clen = 0;
+  uint64_t csm = 0;
+  uint32_t chas = 0;
+  if (c < c_end) {
+    const ChunkDesc D = t.chunks[c];
+    LaneWindows L;
+    lane_windows(D, lane, L);
 #pragma unroll
-      for (int q = 0; q < kPNW; ++q) M.mask[q] = t.cmask[(int64_t)c * kPNW + q];
-      M.sf = t.cseg[c];
-      M.nsg = t.cnseg[c];
-    } else {
-      M.cs = M.ce = 0;
-#pragma unroll
-      for (int q = 0; q < kPNW; ++q) M.mask[q] = 0;
-      M.sf = M.nsg = 0;
-    }
-  };
-  // Start the first chunk's loads before assembling the panel.
-  int nb = K < 64 ? K : 64;
-  if (K > 0) {
-    load_meta(0);
-    issue_chunk(t, M, 0, lane, R0);
+    for (int s = 0; s < kPR; ++s)
+      if ((L.has >> s) & 1u) load_window(t, D.base + L.rel[s], sa[s], sb[s]);
+    cinfo = D.info;
+    cfirst = D.first;
+    cbase = D.base;
+    clen = (int64_t)D.vm[0];
+    csm = D.sm;
+    chas = L.has;
+    slot = out_slot(t, D, lane);
   }
 
   const int panel = t.wg_panel[w];
@@ -370,22 +349,56 @@ __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin
   if (threadIdx.x == 0) xl[t.W] = T(0);
   __syncthreads();
 
-  // Two chunks in flight per wavefront: chunk k is processed while the loads
-  // of chunk k + 1 are outstanding.
-  for (int kb = 0; kb < K; kb += 64) {
-    if (kb > 0) {
-      nb = (K - kb) < 64 ? (K - kb) : 64;
-      load_meta(kb);
-      issue_chunk(t, M, 0, lane, R0);
+  while (c < c_end) {
+    const int cn = c + 1;
+    int32_t ninfo = 0, nfirst = 0, slot_n = -1;
+    int64_t nbase = 0, nlen = 0;
+    uint64_t nsm = 0;
+    LaneWindows LN;
+    LN.has = 0;
+    if (cn < c_end) {
+      const ChunkDesc N = t.chunks[cn];
+      lane_windows(N, lane, LN);
+      ninfo = N.info;
+      nfirst = N.first;
+      nbase = N.base;
+      nlen = (int64_t)N.vm[0];
+      nsm = N.sm;
+      slot_n = out_slot(t, N, lane);
     }
-    const int cb = c_beg + kPWaves * kb;
-    for (int k = 0; k < nb; k += 2) {
-      if (k + 1 < nb) issue_chunk(t, M, k + 1, lane, R1);
-      process_chunk<T>(t, R0, cb + kPWaves * k, lane, xl, part_out, piece_out, out_scale);
-      if (k + 1 >= nb) break;
-      if (k + 2 < nb) issue_chunk(t, M, k + 2, lane, R0);
-      process_chunk<T>(t, R1, cb + kPWaves * (k + 1), lane, xl, part_out, piece_out, out_scale);
+    const int R = ck_windows(cinfo);
+    const T scl = (out_scale != nullptr && slot >= 0) ? out_scale[slot] : T(1);
+    // Slots this chunk leaves unused take the next chunk's windows now.
+#pragma unroll
+    for (int s = 0; s < kPR; ++s)
+      if (s >= R && ((LN.has >> s) & 1u)) load_window(t, nbase + LN.rel[s], sa[s], sb[s]);
+    T acc = T(0);
+    for (int kb = 0; kb < R; kb += kPR) {
+#pragma unroll
+      for (int s = 0; s < kPR; ++s) {
+        const int k = kb + s;
+        if (k < R) {
+          const bool have = (k < kPR) ? ((chas >> s) & 1u) != 0
+                                      : (int64_t)k * kPC + lane * kPV < clen;
+          if (have) acc += gather_sum16(xl, sa[s], sb[s]);
+          if (k + kPR < R) {
+            const int64_t e = (int64_t)(k + kPR) * kPC + lane * kPV;
+            if (e < clen) load_window(t, cbase + e, sa[s], sb[s]);
+          } else if ((LN.has >> s) & 1u) {
+            load_window(t, nbase + LN.rel[s], sa[s], sb[s]);
+          }
+        }
+      }
     }
+    finish_chunk<T>(cinfo, csm, acc, slot, scl, cfirst, lane, part_out, piece_out, out_scale);
+    cinfo = ninfo;
+    cfirst = nfirst;
+    cbase = nbase;
+    clen = nlen;
+    csm = nsm;
+    chas = LN.has;
+    slot = slot_n;
+    c = cn;
   }
 }
 

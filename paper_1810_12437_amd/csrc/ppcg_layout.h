@@ -1,16 +1,47 @@
-// Layout constants of the panel-blocked X passes (shared by the kernels and
-// the host-side table builder; no HIP dependency).
+// Layout of the panel-blocked X passes, shared by the kernels and the
+// host-side table builder (plain C++, no HIP dependency).
 #pragma once
+
+#include <stdint.h>
 
 namespace ppcg {
 
 constexpr int kPWaves = 16;            // wavefronts per pass workgroup
 constexpr int kPThreads = kPWaves * 64;
-constexpr int kPV = 16;                // elements per lane (one group)
+constexpr int kPV = 16;                // elements per lane in one window (one group)
 constexpr int kPC = 64 * kPV;          // window: the elements one wavefront reads at once
-constexpr int kPNW = 2;                // windows of a packed chunk
-constexpr int kPGroups = 64 * kPNW;    // lane groups of a packed chunk
-constexpr int kPLongMax = 16 * kPC;    // longest segment a single wavefront sums whole
+constexpr int kPR = 4;                 // windows of a packed chunk
+constexpr int kPLongWin = 16;          // most windows of a long chunk
+constexpr int kPLongMax = kPLongWin * kPC;  // longest segment one wavefront sums whole
 constexpr int kPanelBytes = 160 * 1024 - 64;  // LDS for the gathered panel (+ zero slot)
+
+enum ChunkKind { kChunkPacked = 0, kChunkLong = 1, kChunkPiece = 2 };
+
+// One chunk of an orientation's index stream, read by one wavefront.
+//
+// Packed chunk: up to 64 lanes x kPR windows.  Each segment of the chunk owns
+// a contiguous lane range (a slice) for the whole chunk: its groups of kPV
+// elements go to its lanes kPR at a time (group j on lane l0 + j / kPR in
+// window j % kPR), so a lane only ever sums elements of one segment.  Bit l
+// of vm[k] is set when lane l has a group in window k; the groups of window k
+// are stored consecutively in lane order.  Bit l of sm is set when lane l
+// starts a slice (lanes after the last segment form one idle slice).
+//
+// Long chunk: one segment (or, for a piece, a part of one) laid out as
+// consecutive windows of 64 groups; vm[0] holds its padded element count.
+struct alignas(64) ChunkDesc {
+  int64_t base;      // first element of the chunk in the index stream
+  uint64_t vm[kPR];  // see above
+  uint64_t sm;
+  int32_t first;     // packed: first seg_out entry; long: its seg_out entry; piece: unused
+  int32_t info;      // windows | kind << 8 | row steps << 12 | bcast15 << 16 | bcast31 << 17
+                     //   | segments << 24
+  int64_t pad;
+};
+static_assert(sizeof(ChunkDesc) == 64, "chunk descriptor is one 64-byte scalar load");
+
+constexpr int32_t chunk_info(int windows, int kind, int nrow, int b15, int b31, int nseg) {
+  return windows | (kind << 8) | (nrow << 12) | (b15 << 16) | (b31 << 17) | (nseg << 24);
+}
 
 }  // namespace ppcg

@@ -1,122 +1,321 @@
 // Host-side builder of the panel-blocked, index-only layout of one
-// orientation of X (see PanelPass in ppcg_kernels.h).  Plain C++.
+// orientation of X (see PanelPass in ppcg_kernels.h and ChunkDesc in
+// ppcg_layout.h).  Plain C++.
 #pragma once
 
 #include <stdint.h>
 
 #include <algorithm>
 #include <array>
+#include <numeric>
 #include <vector>
 
 #include "ppcg_layout.h"
 
 namespace ppcg {
 
-// Host-side build of one orientation of X in the panel-blocked layout of
-// PanelPass (see ppcg_kernels.h).
 struct PanelBuild {
   std::vector<uint16_t> idx;
-  std::vector<int64_t> cstart;
-  std::vector<int32_t> cseg, cnseg;
-  std::vector<uint64_t> cmask;
+  std::vector<ChunkDesc> chunks;  // wave-major: the chunks of wave q of workgroup w are
+                                  // [wave_c[16 w + q], wave_c[16 w + q + 1])
   std::vector<int32_t> seg_out;
-  std::vector<int32_t> wg_panel, wg_c0, wg_c1;
-  std::vector<int32_t> sp_off, sp_c0, sp_c1;
+  std::vector<int32_t> wg_panel, wave_c;
+  std::vector<int32_t> sp_off, sp_c0, sp_c1;  // pieces of element i: ids sp_c0..sp_c1
   int64_t gdim = 0, out_dim = 0;
+  int64_t nseg = 0;    // (segment, panel) pairs with elements
+  int32_t npieces = 0;
   int32_t W = 1, npanels = 1;
 };
+
+namespace detail {
+
+inline int ceil_log2(int v) {
+  int s = 0;
+  while ((1 << s) < v) ++s;
+  return s;
+}
+
+// Whether the lane range [l0, l0 + w) contains both lane a and lane a + 1.
+inline bool crosses(int l0, int w, int a) { return l0 <= a && a + 1 < l0 + w; }
+
+struct Entry {
+  int64_t a, e, g;  // element range, groups
+  int32_t slot;     // panel * out_dim + segment
+};
+
+inline int chunk_cost(const ChunkDesc& d) {
+  if (((d.info >> 8) & 3) != kChunkPacked) return d.info & 0xff;
+  int c = 0;
+  for (int k = 0; k < kPR; ++k) c += d.vm[k] ? 1 : 0;
+  return c;
+}
+
+// Packed chunks of one panel from its entries sorted by decreasing length:
+// each chunk takes entries from the front (longest) while they fit, then
+// fills its leftover lanes from the back (shortest).  An entry of g groups
+// gets ceil(g / R) lanes, R being the chunk's windows.
+struct Packer {
+  const std::vector<Entry>* ent;
+  std::vector<int32_t> order;  // packed entries, longest first
+  size_t lo = 0, hi = 0;
+
+  bool empty() const { return lo >= hi; }
+  int lanes(int32_t i, int R) const { return (int)(((*ent)[i].g + R - 1) / R); }
+  int min_windows() const {  // windows the shortest entry needs to fit one chunk
+    return (int)(((*ent)[order[hi - 1]].g + 63) / 64);
+  }
+
+  // Takes the members of the next chunk of R windows (no stream output).
+  void take(int R, std::vector<int32_t>& members) {
+    members.clear();
+    int used = 0;
+    while (lo < hi && used + lanes(order[lo], R) <= 64) {
+      used += lanes(order[lo], R);
+      members.push_back(order[lo++]);
+    }
+    while (hi > lo && used + lanes(order[hi - 1], R) <= 64) {
+      used += lanes(order[hi - 1], R);
+      members.push_back(order[--hi]);
+    }
+  }
+};
+
+}  // namespace detail
 
 // off: segment offsets (out_dim + 1), gidx: gathered index of each element
 // (increasing within a segment), gdim: gathered dimension, elem: bytes of
 // one gathered value, ncu: compute units to spread the workgroups over.
 //
-// Every (segment, panel) is padded with the sentinel index W (a zero in the
-// LDS panel) to a multiple of kPV elements, so each lane's kPV elements
-// belong to one segment.  Chunk kinds (cnseg): > 0 packs whole padded
-// segments into up to kPNW windows (kPGroups groups of kPV elements), with
-// bit g of the chunk's kPNW mask words set when group g starts a segment; 0
-// is one segment longer than that, summed whole by one wavefront; < 0 is a
-// piece of a segment longer than kPLongMax (its sum goes to the piece array
-// and the consumer adds the pieces).
-void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& gidx,
-                  int64_t out_dim, int64_t gdim, int elem, int ncu, PanelBuild& B) {
+// The gathered dimension is cut into panels of W entries (W + 1 values fit
+// the LDS budget; slot W holds the zero the padding indices point to).  Each
+// non-empty (segment, panel) pair is a segment entry of g = ceil(len / kPV)
+// groups, padded with the index W.  Entries of at most 64 kPR groups go to
+// packed chunks; longer ones get long chunks of up to kPLongWin windows, and
+// one longer than that is cut into pieces whose sums the consumer adds.
+// Each panel gets workgroups in proportion to its windows; every wavefront
+// of them gets an explicit chunk list: long chunks first (least loaded
+// wavefront first), then packed chunks up to an equal share of windows, the
+// last chunk of a share built with fewer windows (from the shortest entries
+// when the longest do not fit in fewer) to end on the share.
+inline void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& gidx,
+                         int64_t out_dim, int64_t gdim, int elem, int ncu, PanelBuild& B) {
+  using detail::Entry;
   B = PanelBuild();
   B.gdim = gdim;
   B.out_dim = out_dim;
-  const int64_t wmax = kPanelBytes / elem - 1;  // one LDS slot holds the zero sentinel
+  const int64_t wmax = kPanelBytes / elem - 1;
   B.npanels = (int32_t)((gdim + wmax - 1) / wmax);
   if (B.npanels < 1) B.npanels = 1;
   B.W = (int32_t)((gdim + B.npanels - 1) / B.npanels);
   const uint16_t sentinel = (uint16_t)B.W;
-  std::vector<int64_t> cur(off.begin(), off.end() - 1);
-  std::vector<int32_t> pc0(B.npanels + 1, 0);
-  std::vector<std::array<int32_t, 3>> splits;  // (segment id, c0, c1)
-  std::vector<int64_t> seg_a, seg_e;           // element range of each (segment, panel)
-  auto groups = [&](int64_t len) { return (len + kPV - 1) / kPV; };
-  auto append = [&](int64_t a, int64_t e, int64_t glo) {
-    for (int64_t q = a; q < e; ++q) B.idx.push_back((uint16_t)(gidx[q] - glo));
-    while (B.idx.size() % kPV) B.idx.push_back(sentinel);
+  const int64_t packed_max = 64 * kPR;  // groups
+
+  auto append_group = [&](int64_t a, int64_t e, int64_t glo) {
+    // elements [a, e) (at most kPV) as one padded group
+    int64_t q = a;
+    for (; q < e; ++q) B.idx.push_back((uint16_t)(gidx[q] - glo));
+    for (; q < a + kPV; ++q) B.idx.push_back(sentinel);
   };
+
+  // 1. entries of every panel
+  std::vector<std::vector<Entry>> ent(B.npanels);
+  {
+    std::vector<int64_t> cur(off.begin(), off.end() - 1);
+    for (int32_t k = 0; k < B.npanels; ++k) {
+      const int64_t hi = (int64_t)(k + 1) * B.W;
+      for (int64_t sgm = 0; sgm < out_dim; ++sgm) {
+        const int64_t a = cur[sgm];
+        int64_t e = a;
+        const int64_t end = off[sgm + 1];
+        while (e < end && gidx[e] < hi) ++e;
+        if (e > a) {
+          ent[k].push_back({a, e, (e - a + kPV - 1) / kPV, (int32_t)((int64_t)k * out_dim + sgm)});
+          cur[sgm] = e;
+        }
+      }
+      B.nseg += (int64_t)ent[k].size();
+    }
+  }
+
+  // 2. estimated windows per panel (packed entries as chunks of kPR windows)
+  std::vector<detail::Packer> pk(B.npanels);
+  std::vector<int64_t> pwin(B.npanels, 0);
+  std::vector<int32_t> members;
   for (int32_t k = 0; k < B.npanels; ++k) {
-    const int64_t hi = (int64_t)(k + 1) * B.W;
-    const int64_t glo = (int64_t)k * B.W;
-    const int64_t seg_first = (int64_t)B.seg_out.size();
-    for (int64_t sgm = 0; sgm < out_dim; ++sgm) {
-      const int64_t a = cur[sgm];
-      int64_t e = a;
-      const int64_t end = off[sgm + 1];
-      while (e < end && gidx[e] < hi) ++e;
-      if (e > a) {
-        B.seg_out.push_back((int32_t)((int64_t)k * out_dim + sgm));
-        seg_a.push_back(a);
-        seg_e.push_back(e);
-        cur[sgm] = e;
+    detail::Packer& P = pk[k];
+    P.ent = &ent[k];
+    for (int32_t i = 0; i < (int32_t)ent[k].size(); ++i) {
+      const Entry& en = ent[k][i];
+      if (en.g > packed_max) {
+        const int64_t len = en.e - en.a;
+        for (int64_t o = 0; o < len; o += kPLongMax) {
+          const int64_t ng = (std::min<int64_t>(o + kPLongMax, len) - o + kPV - 1) / kPV;
+          pwin[k] += (ng + 63) / 64;
+        }
+      } else {
+        P.order.push_back(i);
       }
     }
-    const int64_t seg_end = (int64_t)B.seg_out.size();
-    pc0[k] = (int32_t)B.cseg.size();
-    int64_t g = seg_first;
-    while (g < seg_end) {
-      const int64_t len = seg_e[g] - seg_a[g];
-      if (groups(len) > kPGroups) {
-        if (len <= kPLongMax) {
-          B.cstart.push_back((int64_t)B.idx.size());
-          B.cseg.push_back((int32_t)g);
-          B.cnseg.push_back(0);
-          for (int q = 0; q < kPNW; ++q) B.cmask.push_back(0);
-          append(seg_a[g], seg_e[g], glo);
-        } else {
-          const int32_t c0 = (int32_t)B.cseg.size();
-          for (int64_t o = seg_a[g]; o < seg_e[g]; o += kPLongMax) {
-            B.cstart.push_back((int64_t)B.idx.size());
-            B.cseg.push_back((int32_t)g);
-            B.cnseg.push_back(-1);
-            for (int q = 0; q < kPNW; ++q) B.cmask.push_back(0);
-            append(o, std::min<int64_t>(o + kPLongMax, seg_e[g]), glo);
+    std::stable_sort(P.order.begin(), P.order.end(),
+                     [&](int32_t x, int32_t y) { return ent[k][x].g > ent[k][y].g; });
+    detail::Packer T = P;
+    T.hi = T.order.size();
+    while (!T.empty()) {
+      T.take(kPR, members);
+      int64_t last = 0;  // windows of the chunk: the longest lane's groups
+      for (int32_t i : members) last = std::max<int64_t>(last, std::min<int64_t>(ent[k][i].g, kPR));
+      pwin[k] += last;
+    }
+    P.hi = P.order.size();
+  }
+
+  // 3. workgroups per panel, in proportion to its windows
+  const int nwg_total = std::max<int>(ncu, B.npanels);
+  const int64_t tot = std::max<int64_t>(std::accumulate(pwin.begin(), pwin.end(), (int64_t)0), 1);
+  std::vector<int> g_k(B.npanels, 0);
+  int assigned = 0;
+  for (int32_t k = 0; k < B.npanels; ++k) {
+    if (pwin[k] == 0) continue;
+    g_k[k] = std::max(1, (int)((int64_t)nwg_total * pwin[k] / tot));
+    assigned += g_k[k];
+  }
+  while (assigned < nwg_total) {
+    int best = -1;
+    double best_load = 0.0;
+    for (int32_t k = 0; k < B.npanels; ++k) {
+      if (pwin[k] == 0) continue;
+      const double load = (double)pwin[k] / g_k[k];
+      if (load > best_load) {
+        best_load = load;
+        best = k;
+      }
+    }
+    if (best < 0) break;
+    g_k[best]++;
+    assigned++;
+  }
+
+  // 4. chunk lists, wavefront by wavefront
+  std::vector<std::array<int32_t, 3>> splits;  // (output element, first piece, last piece)
+  B.wave_c.push_back(0);
+  for (int32_t k = 0; k < B.npanels; ++k) {
+    if (g_k[k] == 0) continue;
+    const int64_t glo = (int64_t)k * B.W;
+    const int nwv = kPWaves * g_k[k];
+    std::vector<std::vector<ChunkDesc>> lists(nwv);
+    std::vector<int64_t> load(nwv, 0);
+    // long entries: least loaded wavefront first
+    for (const Entry& en : ent[k]) {
+      if (en.g <= packed_max) continue;
+      const int64_t len = en.e - en.a;
+      const bool pieces = len > kPLongMax;
+      if (!pieces) B.seg_out.push_back(en.slot);
+      const int32_t p_first = B.npieces;
+      for (int64_t o = en.a; o < en.e; o += kPLongMax) {
+        const int64_t oe = std::min<int64_t>(o + kPLongMax, en.e);
+        ChunkDesc d{};
+        d.base = (int64_t)B.idx.size();
+        const int64_t ng = (oe - o + kPV - 1) / kPV;
+        d.vm[0] = (uint64_t)(ng * kPV);
+        const int win = (int)((ng + 63) / 64);
+        d.first = pieces ? B.npieces++ : (int32_t)B.seg_out.size() - 1;
+        d.info = chunk_info(win, pieces ? kChunkPiece : kChunkLong, 0, 0, 0, 1);
+        for (int64_t q = o; q < oe; q += kPV) append_group(q, std::min<int64_t>(q + kPV, oe), glo);
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lists[q].push_back(d);
+        load[q] += win;
+      }
+      if (pieces) splits.push_back({(int32_t)(en.slot % out_dim), p_first, B.npieces - 1});
+    }
+    // packed entries: fill each wavefront to its share of the panel's
+    // windows; the share starts from the estimate and is rebuilt from the
+    // windows the first fill actually used when that fill ends unevenly.
+    detail::Packer& P = pk[k];
+    const size_t idx0 = B.idx.size(), seg0 = B.seg_out.size();
+    const std::vector<std::vector<ChunkDesc>> lists_long = lists;
+    const std::vector<int64_t> load_long = load;
+    auto make_packed = [&](int R) {
+      P.take(R, members);
+      ChunkDesc d{};
+      d.base = (int64_t)B.idx.size();
+      d.first = (int32_t)B.seg_out.size();
+      std::vector<int> l0s(members.size()), ws(members.size());
+      int l = 0, maxw = 1, b15 = 0, b31 = 0;
+      for (size_t s = 0; s < members.size(); ++s) {
+        const int w = P.lanes(members[s], R);
+        l0s[s] = l;
+        ws[s] = w;
+        d.sm |= 1ull << l;
+        maxw = std::max(maxw, w);
+        if (detail::crosses(l, w, 15) || detail::crosses(l, w, 47)) b15 = 1;
+        if (detail::crosses(l, w, 31)) b31 = 1;
+        l += w;
+        B.seg_out.push_back(ent[k][members[s]].slot);
+      }
+      if (l < 64) d.sm |= 1ull << l;  // idle tail slice
+      // window-major stream: window kw holds, lane by lane, group
+      // (lane - l0) * R + kw of the lane's entry when it exists
+      int nw = 0;
+      for (int kw = 0; kw < R; ++kw) {
+        for (size_t s = 0; s < members.size(); ++s) {
+          const Entry& en = ent[k][members[s]];
+          for (int i = 0; i < ws[s]; ++i) {
+            const int64_t j = (int64_t)i * R + kw;
+            if (j >= en.g) continue;
+            d.vm[kw] |= 1ull << (l0s[s] + i);
+            const int64_t q = en.a + j * kPV;
+            append_group(q, std::min<int64_t>(q + kPV, en.e), glo);
           }
-          splits.push_back({(int32_t)(B.seg_out[g] % out_dim), c0, (int32_t)B.cseg.size() - 1});
         }
-        ++g;
-      } else {
-        const int64_t first = g;
-        int64_t used = 0;  // groups
-        uint64_t mask[kPNW] = {};
-        B.cstart.push_back((int64_t)B.idx.size());
-        while (g < seg_end && used + groups(seg_e[g] - seg_a[g]) <= kPGroups) {
-          mask[used / 64] |= 1ull << (used % 64);
-          used += groups(seg_e[g] - seg_a[g]);
-          append(seg_a[g], seg_e[g], glo);
-          ++g;
+        if (d.vm[kw]) nw = kw + 1;
+      }
+      d.info = chunk_info(nw, kChunkPacked, detail::ceil_log2(std::min(maxw, 16)), b15, b31,
+                          (int)members.size());
+      return d;
+    };
+    int64_t total = pwin[k];
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      lists = lists_long;
+      load = load_long;
+      B.idx.resize(idx0);
+      B.seg_out.resize(seg0);
+      P.lo = 0;
+      P.hi = P.order.size();
+      const double share = (double)total / nwv;
+      for (int q = 0; q < nwv && !P.empty(); ++q) {
+        const int64_t target =
+            (int64_t)std::llround(share * (q + 1)) - (int64_t)std::llround(share * q);
+        while (!P.empty() && load[q] < target) {
+          int R = (int)std::min<int64_t>(kPR, target - load[q]);
+          R = std::max(R, P.min_windows());
+          const ChunkDesc d = make_packed(R);
+          lists[q].push_back(d);
+          load[q] += detail::chunk_cost(d);
         }
-        B.cseg.push_back((int32_t)first);
-        B.cnseg.push_back((int32_t)(g - first));
-        for (int q = 0; q < kPNW; ++q) B.cmask.push_back(mask[q]);
+      }
+      bool leftover = false;
+      while (!P.empty()) {  // what the share missed: least loaded wavefront
+        leftover = true;
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        const ChunkDesc d = make_packed(kPR);
+        lists[q].push_back(d);
+        load[q] += detail::chunk_cost(d);
+      }
+      const int64_t used = std::accumulate(load.begin(), load.end(), (int64_t)0);
+      const int64_t worst = *std::max_element(load.begin(), load.end());
+      if (!leftover && worst <= (used + nwv - 1) / nwv + 1) break;
+      total = used;
+    }
+    for (int g = 0; g < g_k[k]; ++g) {
+      B.wg_panel.push_back(k);
+      for (int q = 0; q < kPWaves; ++q) {
+        for (const ChunkDesc& d : lists[g * kPWaves + q]) B.chunks.push_back(d);
+        B.wave_c.push_back((int32_t)B.chunks.size());
       }
     }
   }
-  pc0[B.npanels] = (int32_t)B.cseg.size();
-  B.cstart.push_back((int64_t)B.idx.size());
-  // pieces of segments longer than kPLongMax, grouped by output element
+
+  // pieces of the longest entries, grouped by output element
   if (!splits.empty()) {
     std::stable_sort(splits.begin(), splits.end(),
                      [](const std::array<int32_t, 3>& a, const std::array<int32_t, 3>& b) {
@@ -128,56 +327,6 @@ void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& g
     for (auto& sp : splits) {
       B.sp_c0.push_back(sp[1]);
       B.sp_c1.push_back(sp[2]);
-    }
-  }
-  // workgroups: each serves one panel, in proportion to its elements
-  const int nwg_total = std::max<int>(ncu, B.npanels);
-  std::vector<int64_t> pe(B.npanels, 0);
-  for (int32_t k = 0; k < B.npanels; ++k) pe[k] = B.cstart[pc0[k + 1]] - B.cstart[pc0[k]];
-  const int64_t tot = std::max<int64_t>(B.cstart.back(), 1);
-  std::vector<int> g_k(B.npanels, 0);
-  int assigned = 0;
-  for (int32_t k = 0; k < B.npanels; ++k) {
-    const int64_t ck = pc0[k + 1] - pc0[k];
-    if (ck == 0) continue;
-    int gk = (int)((int64_t)nwg_total * pe[k] / tot);
-    gk = std::max(1, std::min<int>(gk, (int)ck));
-    g_k[k] = gk;
-    assigned += gk;
-  }
-  while (assigned < nwg_total) {
-    int best = -1;
-    double best_load = 0.0;
-    for (int32_t k = 0; k < B.npanels; ++k) {
-      const int64_t ck = pc0[k + 1] - pc0[k];
-      if (ck == 0 || g_k[k] >= ck) continue;
-      const double load = (double)pe[k] / g_k[k];
-      if (load > best_load) {
-        best_load = load;
-        best = k;
-      }
-    }
-    if (best < 0) break;
-    g_k[best]++;
-    assigned++;
-  }
-  // within a panel, split the chunks into equal-element ranges
-  for (int32_t k = 0; k < B.npanels; ++k) {
-    if (g_k[k] == 0) continue;
-    const int64_t e_lo = B.cstart[pc0[k]];
-    int32_t c = pc0[k];
-    for (int i = 0; i < g_k[k]; ++i) {
-      const int64_t target = e_lo + pe[k] * (i + 1) / g_k[k];
-      const int32_t c_begin = c;
-      if (i == g_k[k] - 1) {
-        c = pc0[k + 1];
-      } else {
-        while (c < pc0[k + 1] && B.cstart[c + 1] <= target) ++c;
-        if (c == c_begin && c < pc0[k + 1]) ++c;  // at least one chunk each
-      }
-      B.wg_panel.push_back(k);
-      B.wg_c0.push_back(c_begin);
-      B.wg_c1.push_back(c);
     }
   }
 }
