@@ -207,11 +207,11 @@ inline bool rows_direct(const Orient& o) { return o.npanels == 1 && o.sp_off == 
 // when the rows fit one panel, else by the consumer).
 template <typename T>
 hipError_t row_pass(ppcg_matrix* X, const Combine<T>& x, const T* omega, const int32_t* done,
-                    hipStream_t st) {
+                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   Orient& o = X->rows[prec_index<T>()];
   return launch_panel_pass<T>(o.pass, x, reinterpret_cast<T*>(o.part),
                               reinterpret_cast<T*>(o.piece), rows_direct(o) ? omega : nullptr,
-                              done, st);
+                              done, st, ev0, ev1);
 }
 
 // The column pass's view of u.
@@ -224,11 +224,11 @@ Combine<T> u_view(ppcg_matrix* X, const T* omega) {
 // Column pass: segment sums of X^T u, u from the row pass (or y if given).
 template <typename T>
 hipError_t col_pass(ppcg_matrix* X, const T* omega, const Combine<T>* y, const int32_t* done,
-                    hipStream_t st) {
+                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   Orient& o = X->cols[prec_index<T>()];
   const Combine<T> u = y ? *y : u_view<T>(X, omega);
   return launch_panel_pass<T>(o.pass, u, reinterpret_cast<T*>(o.part),
-                              reinterpret_cast<T*>(o.piece), nullptr, done, st);
+                              reinterpret_cast<T*>(o.piece), nullptr, done, st, ev0, ev1);
 }
 
 // FP64 product part qx64 = X^T (omega .* (X x)).
@@ -280,11 +280,11 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
     int32_t active_before = 0;
     if (prof) active_before = X->h_sc->done ? 0 : 1;
     for (int i = 0; i < o.check_every; ++i) {
-      if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 0], st));
-      PPCG_TRY_HIP(row_pass<T>(X, svec, omegaT, done, st));
-      if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 1], st));
-      PPCG_TRY_HIP(col_pass<T>(X, omegaT, nullptr, done, st));
-      if (prof) PPCG_TRY_HIP(hipEventRecord(X->ev[4 * i + 2], st));
+      hipEvent_t* e = prof ? &X->ev[4 * i] : nullptr;
+      PPCG_TRY_HIP(row_pass<T>(X, svec, omegaT, done, st, e ? e[0] : nullptr,
+                               e ? e[1] : nullptr));
+      PPCG_TRY_HIP(col_pass<T>(X, omegaT, nullptr, done, st, e ? e[2] : nullptr,
+                               e ? e[3] : nullptr));
       PPCG_TRY_HIP(launch_cg_dot<T>(w, s, qsrc, qx, X->d, X->p, st));
       PPCG_TRY_HIP(launch_cg_update<T>(w, s, qx, X->d, X->m, X->beta64, X->r64, X->p, st));
       PPCG_TRY_HIP(launch_cg_direction<T>(w, X->m, X->r64, s, X->p, st));
@@ -298,7 +298,7 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
       for (int i = 0; i < ran; ++i) {
         float a = 0.f, b = 0.f;
         PPCG_TRY_HIP(hipEventElapsedTime(&a, X->ev[4 * i + 0], X->ev[4 * i + 1]));
-        PPCG_TRY_HIP(hipEventElapsedTime(&b, X->ev[4 * i + 1], X->ev[4 * i + 2]));
+        PPCG_TRY_HIP(hipEventElapsedTime(&b, X->ev[4 * i + 2], X->ev[4 * i + 3]));
         X->pass_ms[0] += a;
         X->pass_ms[1] += b;
         X->pass_cnt[0] += 1;

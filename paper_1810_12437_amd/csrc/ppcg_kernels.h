@@ -85,10 +85,12 @@ struct VecWork {
 // One X pass: gathers value(x, .) panel by panel and writes the segment sums
 // of panel k to part_out[k * out_dim + id] (times out_scale[id] when given:
 // only for a single-panel table without pieces), piece sums to piece_out.
+// With ev0/ev1 the dispatch records the kernel's start and end in them.
 template <typename T>
 hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
                              T* piece_out, const T* out_scale, const int32_t* done,
-                             hipStream_t st);
+                             hipStream_t st, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
 
 // out[i] = value(c, i) for i < dim.
 template <typename T, typename U>
@@ -146,7 +148,6 @@ hipError_t launch_cg_update(VecWork w, const T* s, const T* qx, const double* d,
 template <typename T>
 hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s,
                                int64_t p, hipStream_t st);
-
 // Adjoint epilogue: grad_b = a, grad_loglambda = 2 d a beta, grad_logtau = sum.
 hipError_t launch_adjoint_epilogue(VecWork w, const double* a, const void* beta, int dtype,
                                    const double* d, int64_t p, void* grad_b,

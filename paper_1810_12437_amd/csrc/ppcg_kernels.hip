@@ -17,6 +17,8 @@
 // fixed-order too.
 #include "ppcg_kernels.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 namespace ppcg {
@@ -416,10 +418,16 @@ hipError_t setup_pass_kernels() {
 template <typename T>
 hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
                              T* piece_out, const T* out_scale, const int32_t* done,
-                             hipStream_t st) {
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (t.nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_panel<T>), dim3(t.nwg), dim3(kPThreads), pass_lds_bytes(), st, t, x,
-                     part_out, piece_out, out_scale, done);
+  if (ev0 != nullptr) {
+    // Events taken by the dispatch itself: the kernel's own duration.
+    hipExtLaunchKernelGGL((k_panel<T>), dim3(t.nwg), dim3(kPThreads), pass_lds_bytes(), st, ev0,
+                          ev1, 0u, t, x, part_out, piece_out, out_scale, done);
+  } else {
+    hipLaunchKernelGGL((k_panel<T>), dim3(t.nwg), dim3(kPThreads), pass_lds_bytes(), st, t, x,
+                       part_out, piece_out, out_scale, done);
+  }
   return hipGetLastError();
 }
 
@@ -438,10 +446,11 @@ hipError_t launch_combine(const Combine<T>& c, int64_t dim, U* out, hipStream_t 
 }
 
 template hipError_t launch_panel_pass<float>(const PanelPass&, const Combine<float>&, float*,
-                                             float*, const float*, const int32_t*, hipStream_t);
+                                             float*, const float*, const int32_t*, hipStream_t,
+                                             hipEvent_t, hipEvent_t);
 template hipError_t launch_panel_pass<double>(const PanelPass&, const Combine<double>&, double*,
                                               double*, const double*, const int32_t*,
-                                              hipStream_t);
+                                              hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_combine<float, float>(const Combine<float>&, int64_t, float*,
                                                  hipStream_t);
 template hipError_t launch_combine<double, double>(const Combine<double>&, int64_t, double*,
@@ -826,6 +835,7 @@ hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s
   hipLaunchKernelGGL((k_cg_direction<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, m, r, s, p);
   return hipGetLastError();
 }
+
 
 #define PPCG_INST(T)                                                                         \
   template hipError_t launch_cg_start<T>(VecWork, int, const double*, const double*,         \
