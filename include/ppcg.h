@@ -76,6 +76,7 @@ extern "C" {
 #define PPCG_STREAM_DELTA 1
 
 typedef struct ppcg_matrix ppcg_matrix;
+typedef struct ppcg_batch ppcg_batch;
 
 typedef struct ppcg_options {
   int32_t dtype;      /* PPCG_F64 or PPCG_F32                                        */
@@ -231,6 +232,56 @@ int ppcg_matrix_stats(const ppcg_matrix* X, double* csr_ms, int64_t* csr_launche
  */
 int ppcg_matrix_pass_bytes(const ppcg_matrix* X, int32_t dtype, int64_t* row_pass_bytes,
                            int64_t* col_pass_bytes);
+
+/*
+ * Many chains at once.  A batch binds C chains, chain c to the design X[c]
+ * (the same handle may serve several chains; sizes may differ between
+ * chains).  Each call runs every chain's CG with the per-iteration phases of
+ * all chains issued as one launch each (X passes, inner products, updates):
+ * a chain that has converged drops out of the launches at once, and the
+ * host waits until every chain has.  The result of each chain is the one
+ * ppcg_draw / ppcg_solve gives for it (bitwise: the same kernels, blocks and
+ * summation order).  `dtype` (PPCG_F64 or PPCG_F32) is fixed per batch; the
+ * options passed to the calls must have the same dtype.  The batch owns its
+ * workspace (one copy per chain) and keeps pointers to the X handles, which
+ * must outlive it.  PPCG_EINVAL for nchains < 1, a NULL handle or bad dtype.
+ */
+int ppcg_batch_create(ppcg_batch** out, int32_t nchains, const ppcg_matrix* const* X,
+                      int32_t dtype, hipStream_t stream);
+
+/* Releases a batch (not its X handles; NULL is allowed). */
+int ppcg_batch_destroy(ppcg_batch* B);
+
+/*
+ * One chain's arguments of a batched call (host array of C entries; the
+ * vectors are device pointers of the batch's dtype, lengths those of the
+ * chain's X: omega, z: n_c; lambda, b, beta_out: p_c).  Draws read z, seed,
+ * chain and draw_index (the draw is ppcg_draw's for these); solves read b.
+ */
+typedef struct ppcg_chain {
+  const void* omega;
+  const void* z;
+  const void* b;
+  const void* lambda;
+  void* beta_out;
+  double tau;
+  uint64_t seed;
+  uint64_t chain;
+  uint64_t draw_index;
+} ppcg_chain;
+
+/*
+ * One draw for every chain of the batch (Prop 2.1 per chain, as ppcg_draw).
+ * `infos` (host array of C entries, may be NULL) receives each chain's
+ * result.  Returns PPCG_OK when every chain converged, else the first
+ * chain's non-OK status; blocks until every beta_out is written.
+ */
+int ppcg_draw_batched(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options* opt,
+                      ppcg_info* infos, hipStream_t stream);
+
+/* Phi_c beta_c = b_c for every chain (as ppcg_solve from zero). */
+int ppcg_solve_batched(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options* opt,
+                       ppcg_info* infos, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "F64", "F32", "REL_PRECOND", "RMS_PRECOND_ABS", "REL_PLAIN",
-    "STREAM_ETA", "STREAM_DELTA", "Matrix", "Options", "Info",
+    "STREAM_ETA", "STREAM_DELTA", "Matrix", "Batch", "Options", "Info", "Chain",
     "phi_matvec", "normals", "rhs", "solve", "draw", "solve_backward",
     "PPCGSolve", "PPCGError", "PPCGUnavailable", "lib", "LIB_PATH", "EXPORTED_SYMBOLS",
 ]
@@ -37,7 +37,8 @@ EXPORTED_SYMBOLS = (
     "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
     "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
     "ppcg_solve_backward", "ppcg_matrix_profile", "ppcg_matrix_stats",
-    "ppcg_matrix_pass_bytes",
+    "ppcg_matrix_pass_bytes", "ppcg_batch_create", "ppcg_batch_destroy",
+    "ppcg_draw_batched", "ppcg_solve_batched",
 )
 
 
@@ -74,6 +75,14 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Chain(ctypes.Structure):
+    _fields_ = [
+        ("omega", ctypes.c_void_p), ("z", ctypes.c_void_p), ("b", ctypes.c_void_p),
+        ("lambda_", ctypes.c_void_p), ("beta_out", ctypes.c_void_p), ("tau", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("chain", ctypes.c_uint64), ("draw_index", ctypes.c_uint64),
+    ]
+
+
 _lib = None
 _vp, _i32, _i64, _u64, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
 
@@ -101,7 +110,14 @@ def _declare(L):
     L.ppcg_matrix_stats.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64),
                                     ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]
     L.ppcg_matrix_pass_bytes.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
-    for name in ("ppcg_matrix_pass_bytes", "ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
+    L.ppcg_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _i32, _vp]
+    L.ppcg_batch_destroy.argtypes = [_vp]
+    L.ppcg_draw_batched.argtypes = [_vp, ctypes.POINTER(Chain), ctypes.POINTER(Options),
+                                    ctypes.POINTER(Info), _vp]
+    L.ppcg_solve_batched.argtypes = [_vp, ctypes.POINTER(Chain), ctypes.POINTER(Options),
+                                     ctypes.POINTER(Info), _vp]
+    for name in ("ppcg_batch_create", "ppcg_batch_destroy", "ppcg_draw_batched",
+                 "ppcg_solve_batched", "ppcg_matrix_pass_bytes", "ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
                  "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
                  "ppcg_solve_backward"):
         getattr(L, name).restype = ctypes.c_int
@@ -241,6 +257,82 @@ class Matrix:
     @classmethod
     def from_problem(cls, P):
         return cls(P.n, P.p, P.row_ptr, P.col_idx)
+
+
+class Batch:
+    """Handle of C chains solved together (chain c on design matrices[c]; the
+    same Matrix may serve several chains).  Each CG phase of all chains is one
+    launch; a chain's result equals the single-chain call's."""
+
+    def __init__(self, matrices, dtype=F64):
+        L = lib()
+        self.matrices = list(matrices)  # keeps the X handles alive
+        if not self.matrices:
+            raise ValueError("a batch needs at least one chain")
+        self.dtype = int(dtype)
+        arr = (ctypes.c_void_p * len(self.matrices))(*[m.handle.value for m in self.matrices])
+        h = ctypes.c_void_p()
+        _check(L.ppcg_batch_create(ctypes.byref(h), len(self.matrices), arr, self.dtype,
+                                   _stream()), "ppcg_batch_create")
+        self._h = h
+
+    def __len__(self):
+        return len(self.matrices)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch handle is closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.ppcg_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _run(self, fn, what, omegas, lams, taus, zs=None, bs=None, seeds=None, chains=None,
+             draw_indices=None, **opts):
+        torch = _torch()
+        C = len(self.matrices)
+        arr = (Chain * C)()
+        outs = []
+        for c, X in enumerate(self.matrices):
+            dt = self.dtype
+            beta = torch.empty(X.p, dtype=_tdtype(dt), device=omegas[c].device)
+            outs.append(beta)
+            ch = arr[c]
+            ch.omega = _dev(omegas[c], dt, X.n, "omega")
+            ch.lambda_ = _dev(lams[c], dt, X.p, "lambda")
+            ch.beta_out = _dev(beta, dt, X.p, "beta")
+            ch.tau = float(taus[c])
+            if zs is not None:
+                ch.z = _dev(zs[c], dt, X.n, "z")
+                ch.seed = int(seeds[c])
+                ch.chain = int(chains[c])
+                ch.draw_index = int(draw_indices[c])
+            if bs is not None:
+                ch.b = _dev(bs[c], dt, X.p, "b")
+        o = make_options(dtype=self.dtype, **opts)
+        infos = (Info * C)()
+        rc = fn(self.handle, arr, ctypes.byref(o), infos, _stream())
+        _check(rc, what, solver=True)
+        return outs, [i.as_dict() for i in infos]
+
+    def draw(self, omegas, zs, lams, taus, seeds, chains, draw_indices, **opts):
+        """One draw per chain (ppcg_draw of each); returns (betas, infos)."""
+        return self._run(lib().ppcg_draw_batched, "ppcg_draw_batched", omegas, lams, taus, zs=zs,
+                         seeds=seeds, chains=chains, draw_indices=draw_indices, **opts)
+
+    def solve(self, omegas, lams, taus, bs, **opts):
+        """Phi_c beta_c = b_c for every chain from zero; returns (betas, infos)."""
+        return self._run(lib().ppcg_solve_batched, "ppcg_solve_batched", omegas, lams, taus,
+                         bs=bs, **opts)
 
 
 def make_options(dtype=F64, tol=1e-6, criterion=REL_PRECOND, max_iter=0, refine=-1,

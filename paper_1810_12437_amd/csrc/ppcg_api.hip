@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ppcg.h"
+#include "ppcg_handle.h"
 #include "ppcg_kernels.h"
 #include "ppcg_panels.h"
 
@@ -20,80 +21,7 @@ using namespace ppcg;
 
 namespace {
 
-struct DevBuf {
-  std::vector<void*> ptrs;
-  template <typename T>
-  hipError_t alloc(T** out, size_t count) {
-    void* p = nullptr;
-    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) return e;
-    ptrs.push_back(p);
-    *out = reinterpret_cast<T*>(p);
-    return hipSuccess;
-  }
-  void release() {
-    for (void* p : ptrs) (void)hipFree(p);
-    ptrs.clear();
-  }
-};
-
-}  // namespace
-
-// One orientation of X at one precision on the device.
-struct Orient {
-  PanelPass pass{};
-  void* part = nullptr;   // [npanels][out_dim] segment sums (zero where absent)
-  void* piece = nullptr;  // [npieces] piece sums
-  const int32_t* sp_off = nullptr;
-  const int32_t* sp_c0 = nullptr;
-  const int32_t* sp_c1 = nullptr;
-  int32_t npanels = 0;
-  int64_t out_dim = 0;
-  int64_t dev_bytes = 0;
-  int64_t pass_bytes = 0;  // algorithmic bytes of one launch (inputs counted once)
-};
-
-struct ppcg_matrix {
-  int64_t n = 0, p = 0, nnz = 0;
-  int device = 0;
-  int ncu = 256;
-  DevBuf mem;
-  Orient rows[2], cols[2];  // [0]: FP64 tables, [1]: FP32 tables
-  // workspace
-  double *qx64 = nullptr, *y64 = nullptr, *omega64 = nullptr;
-  double *d = nullptr, *m = nullptr, *b64 = nullptr, *beta64 = nullptr, *r64 = nullptr,
-         *s64 = nullptr;
-  float *qx32 = nullptr, *s32 = nullptr;
-  double* part = nullptr;
-  DevScal* sc = nullptr;
-  DevScal* h_sc = nullptr;  // pinned host mirror
-  // pass timing (ppcg_matrix_profile)
-  int profile = 0;
-  std::vector<hipEvent_t> ev;  // 4 per iteration of a check batch
-  double pass_ms[2] = {0.0, 0.0};
-  int64_t pass_cnt[2] = {0, 0};
-};
-
-#define PPCG_TRY_HIP(...)                     \
-  do {                                        \
-    hipError_t _e = (__VA_ARGS__);            \
-    if (_e != hipSuccess) return PPCG_EHIP;   \
-  } while (0)
-
-#define PPCG_TRY_ALLOC(...)                                                \
-  do {                                                                     \
-    hipError_t _e = (__VA_ARGS__);                                         \
-    if (_e == hipErrorOutOfMemory || _e == hipErrorMemoryAllocation)       \
-      return PPCG_ENOMEM;                                                  \
-    if (_e != hipSuccess) return PPCG_EHIP;                                \
-  } while (0)
-
-namespace {
-
-// Non-empty segments and chunk table of one orientation given its offsets:
-// greedy packing of whole segments into chunks of at most C - 3 elements;
-// a segment longer than that becomes consecutive piece chunks.
+// Uploads a host table to the handle's device memory.
 template <typename V>
 int upload_vec(ppcg_matrix* X, const std::vector<V>& h, const V** out, int64_t* bytes) {
   V* d = nullptr;
@@ -144,64 +72,6 @@ int upload_orient(ppcg_matrix* X, const PanelBuild& B, int elem, Orient& o) {
                  (int64_t)elem * B.gdim;
   return PPCG_OK;
 }
-
-bool valid_dtype(int32_t d) { return d == PPCG_F64 || d == PPCG_F32; }
-
-ppcg_options resolve(const ppcg_options* o, int64_t p) {
-  ppcg_options r;
-  if (o) {
-    r = *o;
-  } else {
-    ppcg_options_default(&r, PPCG_F64);
-  }
-  if (r.max_iter <= 0) r.max_iter = (int32_t)std::min<int64_t>(p, INT32_MAX);
-  if (r.refine < 0) r.refine = (r.dtype == PPCG_F32) ? 1 : 0;
-  if (r.check_every <= 0) r.check_every = 16;
-  return r;
-}
-
-int check_opts(const ppcg_options& o) {
-  if (!valid_dtype(o.dtype)) return PPCG_EINVAL;
-  if (o.criterion < 0 || o.criterion > 2) return PPCG_EINVAL;
-  if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return PPCG_EINVAL;
-  if (!(o.loop_factor >= 0.0) || !(o.loop_factor <= 1.0)) return PPCG_EINVAL;
-  return PPCG_OK;
-}
-
-VecWork vw(ppcg_matrix* X) { return VecWork{X->part, X->sc}; }
-
-template <typename T>
-constexpr int prec_index() {
-  return sizeof(T) == 8 ? 0 : 1;
-}
-
-template <typename T>
-Combine<T> comb_vec(const T* v) {
-  Combine<T> c{};
-  c.part = v;
-  c.stride = 0;
-  c.nparts = 1;
-  return c;
-}
-
-// The consumer's view of an orientation's pass output (optionally scaled).
-template <typename T>
-Combine<T> comb_out(const Orient& o, const T* scale) {
-  Combine<T> c{};
-  c.part = reinterpret_cast<const T*>(o.part);
-  c.stride = o.out_dim;
-  c.nparts = o.npanels;
-  c.scale = scale;
-  c.sp_off = o.sp_off;
-  c.sp_c0 = o.sp_c0;
-  c.sp_c1 = o.sp_c1;
-  c.piece = reinterpret_cast<const T*>(o.piece);
-  return c;
-}
-
-// Whether the row pass can apply omega itself: one panel and no pieces, so
-// each row's sum is complete when the pass writes it.
-inline bool rows_direct(const Orient& o) { return o.npanels == 1 && o.sp_off == nullptr; }
 
 // Row pass: u = omega .* (X x), as panel partials (omega applied by the pass
 // when the rows fit one panel, else by the consumer).
@@ -309,11 +179,6 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
   }
 }
 
-double ratio(double meas, double thresh2) {
-  if (thresh2 > 0.0) return std::sqrt(meas / thresh2);
-  return meas > 0.0 ? std::numeric_limits<double>::infinity() : 0.0;
-}
-
 // CG from the state prepared in b64 (and beta64 when have_beta0), then the
 // optional FP64 true residual and refinement restart.
 template <typename T>
@@ -409,8 +274,6 @@ int dispatch_solve(ppcg_matrix* X, const void* omega, int dtype, bool have_beta0
   return solve_core<float>(X, reinterpret_cast<const float*>(omega), om64, have_beta0, o, info,
                            st);
 }
-
-bool bad_tau(double tau) { return !(tau > 0.0) || !std::isfinite(tau); }
 
 }  // namespace
 

@@ -1,0 +1,462 @@
+// C-ABI batches: many chains, each with its own X handle and workspace, whose
+// per-iteration phases run as one launch per phase for all chains.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ppcg.h"
+#include "ppcg_handle.h"
+#include "ppcg_kernels.h"
+
+using namespace ppcg;
+
+namespace {
+
+// One chain's device workspace (allocated by the batch).
+struct ChainBufs {
+  const ppcg_matrix* X = nullptr;
+  int64_t n = 0, p = 0;
+  double *y64 = nullptr, *omega64 = nullptr, *d = nullptr, *m = nullptr, *b64 = nullptr,
+         *beta64 = nullptr, *r64 = nullptr, *qx64 = nullptr, *red = nullptr;
+  void *omegaT = nullptr, *s = nullptr, *qx = nullptr;  // the batch's dtype
+  void *rpart[2] = {}, *rpiece[2] = {}, *cpart[2] = {}, *cpiece[2] = {};  // per table precision
+};
+
+// The consumer's view of an orientation's pass output held in a chain's own
+// buffers (optionally scaled).
+template <typename T>
+Combine<T> comb_buf(const Orient& o, const void* part, const void* piece, const T* scale) {
+  Combine<T> c{};
+  c.part = reinterpret_cast<const T*>(part);
+  c.stride = o.out_dim;
+  c.nparts = o.npanels;
+  c.scale = scale;
+  c.sp_off = o.sp_off;
+  c.sp_c0 = o.sp_c0;
+  c.sp_c1 = o.sp_c1;
+  c.piece = reinterpret_cast<const T*>(piece);
+  return c;
+}
+
+enum { kJobRow = 0, kJobCol, kJobRow64, kJobCol64, kJobRhs64, kNumJobs };
+
+}  // namespace
+
+struct ppcg_batch {
+  int device = 0;
+  int32_t dtype = 0;
+  int32_t nch = 0;
+  std::vector<ChainBufs> ch;
+  ppcg::DevBuf mem;
+  ppcg::DevScal* sc = nullptr;    // [nch]
+  ppcg::DevScal* h_sc = nullptr;  // pinned mirror
+  void* jobs[kNumJobs] = {};
+  int32_t* wg_job[kNumJobs] = {};
+  int32_t* wg_local[kNumJobs] = {};
+  int32_t nwg[kNumJobs] = {};
+  void* vjobs = nullptr;  // VecJob<T>[nch]
+  int32_t* blk_job = nullptr;
+  int32_t nblk = 0;
+};
+
+namespace {
+
+template <typename V>
+int upload(ppcg_batch* B, const std::vector<V>& h, V** out) {
+  V* d = nullptr;
+  PPCG_TRY_ALLOC(B->mem.alloc(&d, h.size()));
+  if (!h.empty())
+    PPCG_TRY_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  *out = d;
+  return PPCG_OK;
+}
+
+// Pass job tables of one kind for every chain, with their workgroup maps.
+template <typename T>
+int build_pass_jobs(ppcg_batch* B, int kind) {
+  std::vector<PanelJob<T>> jobs(B->nch);
+  std::vector<int32_t> wj, wl;
+  for (int32_t c = 0; c < B->nch; ++c) {
+    const ChainBufs& C = B->ch[c];
+    const ppcg_matrix* X = C.X;
+    PanelJob<T>& J = jobs[c];
+    J = PanelJob<T>{};
+    const int ti = (kind == kJobRow || kind == kJobCol) ? prec_index<T>() : 0;
+    const Orient& ro = X->rows[ti];
+    const Orient& co = X->cols[ti];
+    const T* om = (kind == kJobRow || kind == kJobCol) ? reinterpret_cast<const T*>(C.omegaT)
+                                                       : reinterpret_cast<const T*>(C.omega64);
+    switch (kind) {
+      case kJobRow:
+      case kJobRow64:
+        J.t = ro.pass;
+        J.x = comb_vec<T>(kind == kJobRow ? reinterpret_cast<const T*>(C.s)
+                                          : reinterpret_cast<const T*>(C.beta64));
+        J.part_out = reinterpret_cast<T*>(C.rpart[ti]);
+        J.piece_out = reinterpret_cast<T*>(C.rpiece[ti]);
+        J.out_scale = rows_direct(ro) ? om : nullptr;
+        break;
+      case kJobCol:
+      case kJobCol64:
+        J.t = co.pass;
+        J.x = comb_buf<T>(ro, C.rpart[ti], C.rpiece[ti], rows_direct(ro) ? nullptr : om);
+        J.part_out = reinterpret_cast<T*>(C.cpart[ti]);
+        J.piece_out = reinterpret_cast<T*>(C.cpiece[ti]);
+        break;
+      default:  // kJobRhs64
+        J.t = co.pass;
+        J.x = comb_vec<T>(reinterpret_cast<const T*>(C.y64));
+        J.part_out = reinterpret_cast<T*>(C.cpart[ti]);
+        J.piece_out = reinterpret_cast<T*>(C.cpiece[ti]);
+        break;
+    }
+    J.done = (kind == kJobRow || kind == kJobCol) ? &B->sc[c].done : nullptr;
+    for (int32_t w = 0; w < J.t.nwg; ++w) {
+      wj.push_back(c);
+      wl.push_back(w);
+    }
+  }
+  PanelJob<T>* dj = nullptr;
+  int rc = upload(B, jobs, &dj);
+  if (rc) return rc;
+  B->jobs[kind] = dj;
+  if ((rc = upload(B, wj, &B->wg_job[kind]))) return rc;
+  if ((rc = upload(B, wl, &B->wg_local[kind]))) return rc;
+  B->nwg[kind] = (int32_t)wj.size();
+  return PPCG_OK;
+}
+
+template <typename T>
+int build_vec_jobs(ppcg_batch* B) {
+  std::vector<VecJob<T>> jobs(B->nch);
+  std::vector<int32_t> bj;
+  const int ti = prec_index<T>();
+  for (int32_t c = 0; c < B->nch; ++c) {
+    const ChainBufs& C = B->ch[c];
+    VecJob<T>& J = jobs[c];
+    J = VecJob<T>{};
+    J.w = VecWork{C.red, &B->sc[c]};
+    J.s = reinterpret_cast<T*>(C.s);
+    J.qsrc = comb_buf<T>(C.X->cols[ti], C.cpart[ti], C.cpiece[ti], nullptr);
+    J.qx = reinterpret_cast<T*>(C.qx);
+    J.b = C.b64;
+    J.qx64 = C.qx64;
+    J.d = C.d;
+    J.m = C.m;
+    J.beta = C.beta64;
+    J.r = C.r64;
+    J.p = C.p;
+    J.max_iter = (int32_t)std::min<int64_t>(C.p, INT32_MAX);
+    J.blk0 = (int32_t)bj.size();
+    J.nblk = vec_blocks(C.p);
+    for (int32_t b = 0; b < J.nblk; ++b) bj.push_back(c);
+  }
+  VecJob<T>* dj = nullptr;
+  int rc = upload(B, jobs, &dj);
+  if (rc) return rc;
+  B->vjobs = dj;
+  if ((rc = upload(B, bj, &B->blk_job))) return rc;
+  B->nblk = (int32_t)bj.size();
+  return PPCG_OK;
+}
+
+int alloc_chain(ppcg_batch* B, ChainBufs& C) {
+  const size_t N = (size_t)C.n, P = (size_t)C.p;
+  const size_t ts = B->dtype == PPCG_F64 ? 8 : 4;
+  unsigned char *om = nullptr, *s = nullptr, *qx = nullptr;
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.y64, N));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.omega64, N));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.d, P));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.m, P));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.b64, P));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.beta64, P));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.r64, P));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.qx64, P));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.red, (size_t)kMaxRedBlocks * 4));
+  PPCG_TRY_ALLOC(B->mem.alloc(&s, P * ts));
+  PPCG_TRY_ALLOC(B->mem.alloc(&qx, P * ts));
+  C.s = s;
+  C.qx = qx;
+  if (B->dtype == PPCG_F64) {
+    C.omegaT = C.omega64;
+  } else {
+    PPCG_TRY_ALLOC(B->mem.alloc(&om, N * ts));
+    C.omegaT = om;
+  }
+  // pass outputs: FP64 tables always (right-hand side, true residual), FP32
+  // tables for the FP32 form's iteration
+  for (int ti = 0; ti < 2; ++ti) {
+    if (ti == 1 && B->dtype == PPCG_F64) continue;
+    const size_t es = ti == 0 ? 8 : 4;
+    const Orient& ro = C.X->rows[ti];
+    const Orient& co = C.X->cols[ti];
+    unsigned char *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
+    const size_t ra = (size_t)ro.npanels * (size_t)ro.out_dim * es;
+    const size_t ca = (size_t)co.npanels * (size_t)co.out_dim * es;
+    PPCG_TRY_ALLOC(B->mem.alloc(&a, ra));
+    PPCG_TRY_ALLOC(B->mem.alloc(&b, (size_t)std::max<int32_t>(ro.pass.npieces, 1) * es));
+    PPCG_TRY_ALLOC(B->mem.alloc(&c, ca));
+    PPCG_TRY_ALLOC(B->mem.alloc(&d, (size_t)std::max<int32_t>(co.pass.npieces, 1) * es));
+    // (segment, panel) pairs with no elements are never written: they stay zero.
+    PPCG_TRY_HIP(hipMemset(a, 0, std::max<size_t>(ra, 1)));
+    PPCG_TRY_HIP(hipMemset(c, 0, std::max<size_t>(ca, 1)));
+    C.rpart[ti] = a;
+    C.rpiece[ti] = b;
+    C.cpart[ti] = c;
+    C.cpiece[ti] = d;
+  }
+  return PPCG_OK;
+}
+
+// CG iterations of every chain until all report done.
+template <typename T>
+int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
+  for (;;) {
+    for (int i = 0; i < o.check_every; ++i) {
+      PPCG_TRY_HIP(launch_panel_pass_batched<T>(reinterpret_cast<const PanelJob<T>*>(
+                                                    B->jobs[kJobRow]),
+                                                B->wg_job[kJobRow], B->wg_local[kJobRow],
+                                                B->nwg[kJobRow], st));
+      PPCG_TRY_HIP(launch_panel_pass_batched<T>(reinterpret_cast<const PanelJob<T>*>(
+                                                    B->jobs[kJobCol]),
+                                                B->wg_job[kJobCol], B->wg_local[kJobCol],
+                                                B->nwg[kJobCol], st));
+      PPCG_TRY_HIP(launch_cg_iteration_batched<T>(
+          reinterpret_cast<const VecJob<T>*>(B->vjobs), B->blk_job, B->nblk, st));
+    }
+    PPCG_TRY_HIP(hipMemcpyAsync(B->h_sc, B->sc, sizeof(DevScal) * B->nch,
+                                hipMemcpyDeviceToHost, st));
+    PPCG_TRY_HIP(hipStreamSynchronize(st));
+    bool all = true;
+    for (int32_t c = 0; c < B->nch; ++c) all = all && B->h_sc[c].done != 0;
+    if (all) return PPCG_OK;
+  }
+}
+
+// FP64 product parts qx64_c = X_c^T (omega_c .* (X_c beta64_c)) of every chain.
+int fp64_parts_batched(ppcg_batch* B, hipStream_t st) {
+  PPCG_TRY_HIP(launch_panel_pass_batched<double>(
+      reinterpret_cast<const PanelJob<double>*>(B->jobs[kJobRow64]), B->wg_job[kJobRow64],
+      B->wg_local[kJobRow64], B->nwg[kJobRow64], st));
+  PPCG_TRY_HIP(launch_panel_pass_batched<double>(
+      reinterpret_cast<const PanelJob<double>*>(B->jobs[kJobCol64]), B->wg_job[kJobCol64],
+      B->wg_local[kJobCol64], B->nwg[kJobCol64], st));
+  for (const ChainBufs& C : B->ch)
+    PPCG_TRY_HIP(launch_combine<double, double>(
+        comb_buf<double>(C.X->cols[0], C.cpart[0], C.cpiece[0], nullptr), C.p, C.qx64, st));
+  return PPCG_OK;
+}
+
+int sync_all(ppcg_batch* B, hipStream_t st) {
+  PPCG_TRY_HIP(hipMemcpyAsync(B->h_sc, B->sc, sizeof(DevScal) * B->nch, hipMemcpyDeviceToHost,
+                              st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  return PPCG_OK;
+}
+
+template <typename T>
+int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
+                ppcg_info* infos, bool draw, hipStream_t st) {
+  const int dt = B->dtype;
+  // per-chain preparation: d, m, FP64 omega (and its FP32 copy), b
+  for (int32_t c = 0; c < B->nch; ++c) {
+    const ChainBufs& C = B->ch[c];
+    const ppcg_chain& A = chains[c];
+    PPCG_TRY_HIP(launch_prep(A.lambda, A.omega, dt, A.tau, C.n, C.p, C.d, C.m, C.omega64, st));
+    if (dt == PPCG_F32)
+      PPCG_TRY_HIP(hipMemcpyAsync(C.omegaT, A.omega, (size_t)C.n * sizeof(float),
+                                  hipMemcpyDeviceToDevice, st));
+    if (draw) {
+      PPCG_TRY_HIP(launch_y_draw(C.omega64, A.z, dt, A.seed, A.chain, A.draw_index, C.n, C.y64,
+                                 st));
+    } else {
+      PPCG_TRY_HIP(launch_convert_to_f64(A.b, dt, C.p, C.b64, st));
+    }
+  }
+  if (draw) {
+    PPCG_TRY_HIP(launch_panel_pass_batched<double>(
+        reinterpret_cast<const PanelJob<double>*>(B->jobs[kJobRhs64]), B->wg_job[kJobRhs64],
+        B->wg_local[kJobRhs64], B->nwg[kJobRhs64], st));
+    for (int32_t c = 0; c < B->nch; ++c) {
+      const ChainBufs& C = B->ch[c];
+      const ppcg_chain& A = chains[c];
+      PPCG_TRY_HIP(launch_combine<double, double>(
+          comb_buf<double>(C.X->cols[0], C.cpart[0], C.cpiece[0], nullptr), C.p, C.qx64, st));
+      PPCG_TRY_HIP(launch_rhs_fin(C.qx64, A.lambda, dt, A.tau, A.seed, A.chain, A.draw_index,
+                                  C.p, C.b64, st));
+    }
+  }
+  const VecJob<T>* vj = reinterpret_cast<const VecJob<T>*>(B->vjobs);
+  const double loop_factor =
+      o.loop_factor > 0.0 ? o.loop_factor : ((sizeof(T) == 4) ? 0.5 : 1.0);
+  // o.max_iter <= 0: each chain's own cap (its p)
+  PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->nblk, 0, o.tol, o.criterion,
+                                          o.max_iter, loop_factor, st));
+  int rc = run_loop_batched<T>(B, o, st);
+  if (rc) return rc;
+  std::vector<ppcg_info> inf(B->nch);
+  for (int32_t c = 0; c < B->nch; ++c) {
+    const DevScal& S = B->h_sc[c];
+    ppcg_info& I = inf[c];
+    I = ppcg_info{};
+    I.status = S.status;
+    I.iters = S.iters;
+    I.resid_rec = ratio(S.meas, S.thresh2);
+    I.resid_true = -1.0;
+    I.resid_true_first = -1.0;
+    I.rms_precond = -1.0;
+    I.bnorm_precond = std::sqrt(S.bm2);
+  }
+  if (o.true_resid || o.refine) {
+    if ((rc = fp64_parts_batched(B, st))) return rc;
+    PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->nblk, 2, o.tol, o.criterion,
+                                            o.max_iter, loop_factor, st));
+    if ((rc = sync_all(B, st))) return rc;
+    bool any = false;
+    for (int32_t c = 0; c < B->nch; ++c) {
+      const DevScal& S = B->h_sc[c];
+      inf[c].resid_true = inf[c].resid_true_first = ratio(S.true_meas, S.thresh2);
+      inf[c].rms_precond = std::sqrt(S.true_rm / (double)B->ch[c].p);
+      any = any || (S.status == PPCG_OK && S.true_meas > S.thresh2);
+    }
+    if (o.refine && any) {
+      // One refinement for the chains whose FP64 true residual misses the
+      // rule: CG restarts from it (the start kernel leaves the others done).
+      PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->nblk, 1, o.tol, o.criterion,
+                                              o.max_iter, loop_factor, st));
+      if ((rc = run_loop_batched<T>(B, o, st))) return rc;
+      std::vector<int32_t> refined(B->nch);
+      for (int32_t c = 0; c < B->nch; ++c) {
+        const DevScal& S = B->h_sc[c];
+        refined[c] = S.refined;
+        if (S.refined) {
+          inf[c].refined = 1;
+          inf[c].refine_iters = S.iters;
+          inf[c].status = S.status;
+          inf[c].resid_rec = ratio(S.meas, S.thresh2);
+        }
+      }
+      if ((rc = fp64_parts_batched(B, st))) return rc;
+      PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->nblk, 2, o.tol, o.criterion,
+                                              o.max_iter, loop_factor, st));
+      if ((rc = sync_all(B, st))) return rc;
+      for (int32_t c = 0; c < B->nch; ++c) {
+        if (!refined[c]) continue;
+        const DevScal& S = B->h_sc[c];
+        inf[c].resid_true = ratio(S.true_meas, S.thresh2);
+        inf[c].rms_precond = std::sqrt(S.true_rm / (double)B->ch[c].p);
+      }
+    }
+  }
+  for (int32_t c = 0; c < B->nch; ++c)
+    PPCG_TRY_HIP(launch_convert_from_f64(B->ch[c].beta64, dt, B->ch[c].p, chains[c].beta_out,
+                                         st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  int status = PPCG_OK;
+  for (int32_t c = 0; c < B->nch; ++c) {
+    if (infos) infos[c] = inf[c];
+    if (status == PPCG_OK && inf[c].status != PPCG_OK) status = inf[c].status;
+  }
+  return status;
+}
+
+int batched_entry(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options* opt,
+                  ppcg_info* infos, bool draw, hipStream_t st) {
+  if (!B || !chains) return PPCG_EINVAL;
+  ppcg_options o = resolve(opt, 1);
+  o.max_iter = (opt && opt->max_iter > 0) ? opt->max_iter : 0;  // 0: each chain's p
+  if (check_opts(o) || o.dtype != B->dtype) return PPCG_EINVAL;
+  for (int32_t c = 0; c < B->nch; ++c) {
+    const ppcg_chain& A = chains[c];
+    if (!A.omega || !A.lambda || !A.beta_out || bad_tau(A.tau)) return PPCG_EINVAL;
+    if (draw ? !A.z : !A.b) return PPCG_EINVAL;
+  }
+  if (B->dtype == PPCG_F64) return batch_solve<double>(B, chains, o, infos, draw, st);
+  return batch_solve<float>(B, chains, o, infos, draw, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppcg_batch_create(ppcg_batch** out, int32_t nchains, const ppcg_matrix* const* X,
+                      int32_t dtype, hipStream_t stream) {
+  (void)stream;
+  try {
+    if (!out) return PPCG_EINVAL;
+    *out = nullptr;
+    if (nchains < 1 || !X || !valid_dtype(dtype)) return PPCG_EINVAL;
+    for (int32_t c = 0; c < nchains; ++c)
+      if (!X[c]) return PPCG_EINVAL;
+    ppcg_batch* B = new (std::nothrow) ppcg_batch();
+    if (!B) return PPCG_ENOMEM;
+    auto fail = [&](int rc) {
+      B->mem.release();
+      if (B->h_sc) (void)hipHostFree(B->h_sc);
+      delete B;
+      return rc;
+    };
+    B->dtype = dtype;
+    B->nch = nchains;
+    if (hipGetDevice(&B->device) != hipSuccess) return fail(PPCG_EHIP);
+    B->ch.resize(nchains);
+    for (int32_t c = 0; c < nchains; ++c) {
+      B->ch[c].X = X[c];
+      B->ch[c].n = X[c]->n;
+      B->ch[c].p = X[c]->p;
+      const int rc = alloc_chain(B, B->ch[c]);
+      if (rc) return fail(rc);
+    }
+    if (B->mem.alloc(&B->sc, (size_t)nchains) != hipSuccess) return fail(PPCG_ENOMEM);
+    if (hipMemset(B->sc, 0, sizeof(DevScal) * nchains) != hipSuccess) return fail(PPCG_EHIP);
+    if (hipHostMalloc(reinterpret_cast<void**>(&B->h_sc), sizeof(DevScal) * nchains, 0) !=
+        hipSuccess) {
+      B->h_sc = nullptr;
+      return fail(PPCG_ENOMEM);
+    }
+    std::memset(B->h_sc, 0, sizeof(DevScal) * nchains);
+    int rc = 0;
+    if (dtype == PPCG_F64) {
+      if ((rc = build_pass_jobs<double>(B, kJobRow)) || (rc = build_pass_jobs<double>(B, kJobCol)) ||
+          (rc = build_vec_jobs<double>(B)))
+        return fail(rc);
+    } else {
+      if ((rc = build_pass_jobs<float>(B, kJobRow)) || (rc = build_pass_jobs<float>(B, kJobCol)) ||
+          (rc = build_vec_jobs<float>(B)))
+        return fail(rc);
+    }
+    if ((rc = build_pass_jobs<double>(B, kJobRow64)) || (rc = build_pass_jobs<double>(B, kJobCol64)) ||
+        (rc = build_pass_jobs<double>(B, kJobRhs64)))
+      return fail(rc);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);
+    *out = B;
+    return PPCG_OK;
+  } catch (const std::bad_alloc&) {
+    return PPCG_ENOMEM;
+  } catch (...) {
+    return PPCG_EINVAL;
+  }
+}
+
+int ppcg_batch_destroy(ppcg_batch* B) {
+  if (!B) return PPCG_OK;
+  (void)hipDeviceSynchronize();
+  B->mem.release();
+  if (B->h_sc) (void)hipHostFree(B->h_sc);
+  delete B;
+  return PPCG_OK;
+}
+
+int ppcg_draw_batched(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options* opt,
+                      ppcg_info* infos, hipStream_t stream) {
+  return batched_entry(B, chains, opt, infos, true, stream);
+}
+
+int ppcg_solve_batched(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options* opt,
+                       ppcg_info* infos, hipStream_t stream) {
+  return batched_entry(B, chains, opt, infos, false, stream);
+}
+
+}  // extern "C"

@@ -72,13 +72,44 @@ struct DevScal {
   int32_t status;
   int32_t max_iter;
   int32_t criterion;
-  int32_t pad0;
+  int32_t refined;  // set by a mode-1 restart
   uint32_t arrive[8]; // last-arriver counters of the reduction phases
 };
 
 struct VecWork {
   double* part;   // [kMaxRedBlocks * 4] per-block partial sums
   DevScal* sc;
+};
+
+// ---- many chains in one launch ----
+// One chain's X pass in a batched launch.
+template <typename T>
+struct PanelJob {
+  PanelPass t;
+  Combine<T> x;
+  T* part_out;
+  T* piece_out;
+  const T* out_scale;
+  const int32_t* done;
+};
+
+// One chain's p-vector state in a batched launch; its blocks are
+// [blk0, blk0 + nblk) of the launch.
+template <typename T>
+struct VecJob {
+  VecWork w;
+  T* s;
+  Combine<T> qsrc;   // the column pass's view of q
+  T* qx;
+  const double* b;
+  const double* qx64;  // FP64 product part (restart and true-residual modes)
+  const double* d;
+  const double* m;
+  double* beta;
+  double* r;
+  int64_t p;
+  int32_t max_iter;    // the chain's iteration cap when the call gives none
+  int32_t blk0, nblk;
 };
 
 // ---- launchers (all asynchronous on `st`) ----
@@ -148,6 +179,24 @@ hipError_t launch_cg_update(VecWork w, const T* s, const T* qx, const double* d,
 template <typename T>
 hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s,
                                int64_t p, hipStream_t st);
+// Blocks of one chain's p-vector phases.
+int32_t vec_blocks(int64_t p);
+
+// Workgroup g of a batched pass runs workgroup wg_local[g] of job wg_job[g].
+template <typename T>
+hipError_t launch_panel_pass_batched(const PanelJob<T>* jobs, const int32_t* wg_job,
+                                     const int32_t* wg_local, int32_t nwg, hipStream_t st);
+// Block g runs block g - blk0 of chain blk_job[g] (nblk blocks in all);
+// max_iter <= 0 takes each chain's own cap.
+template <typename T>
+hipError_t launch_cg_start_batched(const VecJob<T>* jobs, const int32_t* blk_job, int32_t nblk,
+                                   int mode, double tol, int criterion, int max_iter,
+                                   double loop_factor, hipStream_t st);
+// dot, update and direction phases of every chain.
+template <typename T>
+hipError_t launch_cg_iteration_batched(const VecJob<T>* jobs, const int32_t* blk_job,
+                                       int32_t nblk, hipStream_t st);
+
 // Adjoint epilogue: grad_b = a, grad_loglambda = 2 d a beta, grad_logtau = sum.
 hipError_t launch_adjoint_epilogue(VecWork w, const double* a, const void* beta, int dtype,
                                    const double* d, int64_t p, void* grad_b,

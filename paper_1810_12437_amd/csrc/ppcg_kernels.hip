@@ -65,19 +65,26 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
   }
 }
 
+// Block bid of a (possibly virtual) grid of nblk blocks: a batched launch runs
+// the grids of several chains side by side.
+struct VGrid {
+  int bid, nblk;
+};
+__device__ __forceinline__ VGrid own_grid() { return VGrid{(int)blockIdx.x, (int)gridDim.x}; }
+
 // Writes this block's NV partials and reports whether it is the last block
 // of the grid to arrive (then the whole grid's partials are visible to it).
 // Must be called by every thread of the block after block_sum.
 template <int NV>
 __device__ __forceinline__ bool publish_and_arrive(double (&v)[NV], double* part,
-                                                   uint32_t* ctr) {
+                                                   uint32_t* ctr, VGrid g) {
   __shared__ int is_last;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) st_agent(&part[blockIdx.x * NV + i], v[i]);
+    for (int i = 0; i < NV; ++i) st_agent(&part[g.bid * NV + i], v[i]);
     __threadfence();
     uint32_t old = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (old == gridDim.x - 1);
+    is_last = (old == (uint32_t)g.nblk - 1u);
   }
   __syncthreads();
   return is_last != 0;
@@ -87,12 +94,12 @@ __device__ __forceinline__ bool publish_and_arrive(double (&v)[NV], double* part
 // lane 0 of wave 0).  Resets the arrival counter for the next launch.
 template <int NV>
 __device__ __forceinline__ void gather_totals(const double* part, uint32_t* ctr,
-                                              double (&tot)[NV]) {
+                                              double (&tot)[NV], VGrid g) {
   if (threadIdx.x < 64) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       double a = 0.0;
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) a += ld_agent(&part[b * NV + i]);
+      for (int b = threadIdx.x; b < g.nblk; b += 64) a += ld_agent(&part[b * NV + i]);
       tot[i] = wave_sum(a);
     }
     if (threadIdx.x == 0) st_agent(ctr, 0u);
@@ -269,17 +276,16 @@ __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T acc, i
   }
 }
 
+// Workgroup w of one X pass.
 template <typename T>
-__global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin,
-                                                     T* __restrict__ part_out,
-                                                     T* __restrict__ piece_out,
-                                                     const T* __restrict__ out_scale,
-                                                     const int32_t* __restrict__ done) {
+__device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>& xin,
+                                           T* __restrict__ part_out, T* __restrict__ piece_out,
+                                           const T* __restrict__ out_scale,
+                                           const int32_t* __restrict__ done, int w) {
   if (done != nullptr && *done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* xl = reinterpret_cast<T*>(smem);
 
-  const int w = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   // This wavefront's chunks, in order.
@@ -404,16 +410,50 @@ __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin,
+                                                     T* __restrict__ part_out,
+                                                     T* __restrict__ piece_out,
+                                                     const T* __restrict__ out_scale,
+                                                     const int32_t* __restrict__ done) {
+  panel_body<T>(t, xin, part_out, piece_out, out_scale, done, (int)blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPThreads) void k_panel_b(const PanelJob<T>* __restrict__ jobs,
+                                                       const int32_t* __restrict__ wg_job,
+                                                       const int32_t* __restrict__ wg_local) {
+  const PanelJob<T>& J = jobs[wg_job[blockIdx.x]];
+  panel_body<T>(J.t, J.x, J.part_out, J.piece_out, J.out_scale, J.done, wg_local[blockIdx.x]);
+}
+
 static size_t pass_lds_bytes() { return (size_t)kPanelBytes; }
 
 hipError_t setup_pass_kernels() {
   const int bytes = (int)pass_lds_bytes();
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel<float>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel<double>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* fns[] = {reinterpret_cast<const void*>(&k_panel<float>),
+                       reinterpret_cast<const void*>(&k_panel<double>),
+                       reinterpret_cast<const void*>(&k_panel_b<float>),
+                       reinterpret_cast<const void*>(&k_panel_b<double>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
+
+template <typename T>
+hipError_t launch_panel_pass_batched(const PanelJob<T>* jobs, const int32_t* wg_job,
+                                     const int32_t* wg_local, int32_t nwg, hipStream_t st) {
+  if (nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_panel_b<T>), dim3(nwg), dim3(kPThreads), pass_lds_bytes(), st, jobs,
+                     wg_job, wg_local);
+  return hipGetLastError();
+}
+template hipError_t launch_panel_pass_batched<float>(const PanelJob<float>*, const int32_t*,
+                                                     const int32_t*, int32_t, hipStream_t);
+template hipError_t launch_panel_pass_batched<double>(const PanelJob<double>*, const int32_t*,
+                                                      const int32_t*, int32_t, hipStream_t);
 
 template <typename T>
 hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
@@ -659,15 +699,21 @@ static inline unsigned red_grid(int64_t p) {
 enum { kCritRelPrecond = 0, kCritRmsAbs = 1, kCritRelPlain = 2 };
 enum { kStatOK = 0, kStatNotConv = 4, kStatBreakdown = 5 };
 
+// Mode 1 restarts only a run that ended well but whose FP64 true residual
+// misses the rule; any other run is left as it is.
+__device__ __forceinline__ bool restart_wanted(const DevScal* sc) {
+  return sc->status == kStatOK && sc->true_meas > sc->thresh2;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const double* b,
-                                                  const double* qx64, const double* d,
-                                                  const double* m, double* beta, double* r,
-                                                  T* s, int64_t p, double tol, int criterion,
-                                                  int max_iter, double loop_factor) {
+__device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double* b,
+                                              const double* qx64, const double* d,
+                                              const double* m, double* beta, double* r, T* s,
+                                              int64_t p, double tol, int criterion,
+                                              int max_iter, double loop_factor, VGrid g) {
+  if (mode == 1 && !restart_wanted(w.sc)) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // <r,Mr>, <r,r>, <b,Mb>, <b,b>
-  for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < p;
-       j += (int64_t)gridDim.x * kWG) {
+  for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
     const double bj = b[j];
     const double rj = qx64 ? bj - qx64[j] - d[j] * beta[j] : bj;
     const double zj = m[j] * rj;
@@ -684,9 +730,9 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
     }
   }
   block_sum<4>(v);
-  if (!publish_and_arrive<4>(v, w.part, &w.sc->arrive[1])) return;
+  if (!publish_and_arrive<4>(v, w.part, &w.sc->arrive[1], g)) return;
   double tot[4];
-  gather_totals<4>(w.part, &w.sc->arrive[1], tot);
+  gather_totals<4>(w.part, &w.sc->arrive[1], tot, g);
   if (threadIdx.x == 0) {
     DevScal* sc = w.sc;
     const int crit = (mode == 0) ? criterion : sc->criterion;
@@ -697,6 +743,7 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
       return;
     }
     if (mode == 0) {
+      sc->refined = 0;
       sc->criterion = criterion;
       sc->max_iter = max_iter;
       sc->bm2 = tot[2];
@@ -716,6 +763,7 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
     sc->status = kStatOK;
     sc->alpha = 0.0;
     sc->done = (meas <= sc->loop2) ? 1 : 0;
+    if (mode == 1) sc->refined = 1;
     if (!isfinite(tot[0]) || !isfinite(tot[1])) {
       sc->status = kStatBreakdown;
       sc->done = 1;
@@ -724,31 +772,20 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
 }
 
 template <typename T>
-hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
-                           const double* d, const double* m, double* beta, double* r, T* s,
-                           int64_t p, double tol, int criterion, int max_iter,
-                           double loop_factor, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_start<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, mode, b, qx64, d,
-                     m, beta, r, s, p, tol, criterion, max_iter, loop_factor);
-  return hipGetLastError();
-}
-
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_dot(VecWork w, const T* s, Combine<T> qsrc, T* qx,
-                                                const double* d, int64_t p) {
+__device__ __forceinline__ void cg_dot_body(VecWork w, const T* s, const Combine<T>& qsrc,
+                                            T* qx, const double* d, int64_t p, VGrid g) {
   if (w.sc->done) return;
   double v[1] = {0.0};
-  for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < p;
-       j += (int64_t)gridDim.x * kWG) {
+  for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
     const T qj = combine_at(qsrc, j);
     qx[j] = qj;
     const double sj = (double)s[j];
     v[0] += sj * ((double)qj + d[j] * sj);
   }
   block_sum<1>(v);
-  if (!publish_and_arrive<1>(v, w.part, &w.sc->arrive[2])) return;
+  if (!publish_and_arrive<1>(v, w.part, &w.sc->arrive[2], g)) return;
   double tot[1];
-  gather_totals<1>(w.part, &w.sc->arrive[2], tot);
+  gather_totals<1>(w.part, &w.sc->arrive[2], tot, g);
   if (threadIdx.x == 0) {
     DevScal* sc = w.sc;
     sc->sq = tot[0];
@@ -763,14 +800,13 @@ __global__ __launch_bounds__(kWG) void k_cg_dot(VecWork w, const T* s, Combine<T
 }
 
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_update(VecWork w, const T* s, const T* qx,
-                                                   const double* d, const double* m,
-                                                   double* beta, double* r, int64_t p) {
+__device__ __forceinline__ void cg_update_body(VecWork w, const T* s, const T* qx,
+                                               const double* d, const double* m, double* beta,
+                                               double* r, int64_t p, VGrid g) {
   if (w.sc->done) return;
   const double alpha = w.sc->alpha;
   double v[2] = {0.0, 0.0};  // <r, M^-1 r>, <r, r>
-  for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < p;
-       j += (int64_t)gridDim.x * kWG) {
+  for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
     const double sj = (double)s[j];
     const double qj = (double)qx[j] + d[j] * sj;
     beta[j] += alpha * sj;
@@ -780,9 +816,9 @@ __global__ __launch_bounds__(kWG) void k_cg_update(VecWork w, const T* s, const 
     v[1] += rj * rj;
   }
   block_sum<2>(v);
-  if (!publish_and_arrive<2>(v, w.part, &w.sc->arrive[3])) return;
+  if (!publish_and_arrive<2>(v, w.part, &w.sc->arrive[3], g)) return;
   double tot[2];
-  gather_totals<2>(w.part, &w.sc->arrive[3], tot);
+  gather_totals<2>(w.part, &w.sc->arrive[3], tot, g);
   if (threadIdx.x == 0) {
     DevScal* sc = w.sc;
     const double rho_new = tot[0];
@@ -806,15 +842,50 @@ __global__ __launch_bounds__(kWG) void k_cg_update(VecWork w, const T* s, const 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_direction(VecWork w, const double* m,
-                                                      const double* r, T* s, int64_t p) {
+__device__ __forceinline__ void cg_direction_body(VecWork w, const double* m, const double* r,
+                                                  T* s, int64_t p, VGrid g) {
   if (w.sc->done) return;
   const double bc = w.sc->betacg;
-  for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < p;
-       j += (int64_t)gridDim.x * kWG)
+  for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG)
     s[j] = (T)(m[j] * r[j] + bc * (double)s[j]);
 }
 
+// ---- one chain ----
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const double* b,
+                                                  const double* qx64, const double* d,
+                                                  const double* m, double* beta, double* r,
+                                                  T* s, int64_t p, double tol, int criterion,
+                                                  int max_iter, double loop_factor) {
+  cg_start_body<T>(w, mode, b, qx64, d, m, beta, r, s, p, tol, criterion, max_iter, loop_factor,
+                   own_grid());
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_dot(VecWork w, const T* s, Combine<T> qsrc, T* qx,
+                                                const double* d, int64_t p) {
+  cg_dot_body<T>(w, s, qsrc, qx, d, p, own_grid());
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_update(VecWork w, const T* s, const T* qx,
+                                                   const double* d, const double* m,
+                                                   double* beta, double* r, int64_t p) {
+  cg_update_body<T>(w, s, qx, d, m, beta, r, p, own_grid());
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_direction(VecWork w, const double* m,
+                                                      const double* r, T* s, int64_t p) {
+  cg_direction_body<T>(w, m, r, s, p, own_grid());
+}
+
+template <typename T>
+hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
+                           const double* d, const double* m, double* beta, double* r, T* s,
+                           int64_t p, double tol, int criterion, int max_iter,
+                           double loop_factor, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_start<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, mode, b, qx64, d,
+                     m, beta, r, s, p, tol, criterion, max_iter, loop_factor);
+  return hipGetLastError();
+}
 template <typename T>
 hipError_t launch_cg_dot(VecWork w, const T* s, const Combine<T>& qsrc, T* qx, const double* d,
                          int64_t p, hipStream_t st) {
@@ -836,6 +907,66 @@ hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s
   return hipGetLastError();
 }
 
+// ---- many chains: block g runs block g - blk0 of chain blk_job[g] ----
+template <typename T>
+__device__ __forceinline__ const VecJob<T>& vec_job(const VecJob<T>* jobs,
+                                                    const int32_t* blk_job, VGrid& g) {
+  const VecJob<T>& J = jobs[blk_job[blockIdx.x]];
+  g = VGrid{(int)blockIdx.x - J.blk0, J.nblk};
+  return J;
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_start_b(const VecJob<T>* jobs,
+                                                    const int32_t* blk_job, int mode, double tol,
+                                                    int criterion, int max_iter,
+                                                    double loop_factor) {
+  VGrid g;
+  const VecJob<T>& J = vec_job(jobs, blk_job, g);
+  cg_start_body<T>(J.w, mode, J.b, mode == 0 ? nullptr : J.qx64, J.d, J.m, J.beta, J.r, J.s, J.p,
+                   tol, criterion, max_iter > 0 ? max_iter : J.max_iter, loop_factor, g);
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_dot_b(const VecJob<T>* jobs,
+                                                  const int32_t* blk_job) {
+  VGrid g;
+  const VecJob<T>& J = vec_job(jobs, blk_job, g);
+  cg_dot_body<T>(J.w, J.s, J.qsrc, J.qx, J.d, J.p, g);
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_update_b(const VecJob<T>* jobs,
+                                                     const int32_t* blk_job) {
+  VGrid g;
+  const VecJob<T>& J = vec_job(jobs, blk_job, g);
+  cg_update_body<T>(J.w, J.s, J.qx, J.d, J.m, J.beta, J.r, J.p, g);
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_direction_b(const VecJob<T>* jobs,
+                                                        const int32_t* blk_job) {
+  VGrid g;
+  const VecJob<T>& J = vec_job(jobs, blk_job, g);
+  cg_direction_body<T>(J.w, J.m, J.r, J.s, J.p, g);
+}
+
+int32_t vec_blocks(int64_t p) { return (int32_t)red_grid(p); }
+
+template <typename T>
+hipError_t launch_cg_start_batched(const VecJob<T>* jobs, const int32_t* blk_job, int32_t nblk,
+                                   int mode, double tol, int criterion, int max_iter,
+                                   double loop_factor, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cg_start_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job, mode, tol,
+                     criterion, max_iter, loop_factor);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_cg_iteration_batched(const VecJob<T>* jobs, const int32_t* blk_job,
+                                       int32_t nblk, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cg_dot_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job);
+  hipLaunchKernelGGL((k_cg_update_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job);
+  hipLaunchKernelGGL((k_cg_direction_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job);
+  return hipGetLastError();
+}
 
 #define PPCG_INST(T)                                                                         \
   template hipError_t launch_cg_start<T>(VecWork, int, const double*, const double*,         \
@@ -847,7 +978,11 @@ hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s
                                           const double*, double*, double*, int64_t,          \
                                           hipStream_t);                                      \
   template hipError_t launch_cg_direction<T>(VecWork, const double*, const double*, T*,      \
-                                             int64_t, hipStream_t);
+                                             int64_t, hipStream_t);                          \
+  template hipError_t launch_cg_start_batched<T>(const VecJob<T>*, const int32_t*, int32_t,  \
+                                                 int, double, int, int, double, hipStream_t); \
+  template hipError_t launch_cg_iteration_batched<T>(const VecJob<T>*, const int32_t*,       \
+                                                     int32_t, hipStream_t);
 PPCG_INST(float)
 PPCG_INST(double)
 #undef PPCG_INST
@@ -859,6 +994,7 @@ __global__ __launch_bounds__(kWG) void k_adjoint(VecWork w, const double* a, con
                                                  int dtype, const double* d, int64_t p,
                                                  void* grad_b, void* grad_ll,
                                                  double* grad_lt) {
+  const VGrid g = own_grid();
   double v[1] = {0.0};
   for (int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x; j < p;
        j += (int64_t)gridDim.x * kWG) {
@@ -874,9 +1010,9 @@ __global__ __launch_bounds__(kWG) void k_adjoint(VecWork w, const double* a, con
     }
   }
   block_sum<1>(v);
-  if (!publish_and_arrive<1>(v, w.part, &w.sc->arrive[4])) return;
+  if (!publish_and_arrive<1>(v, w.part, &w.sc->arrive[4], g)) return;
   double tot[1];
-  gather_totals<1>(w.part, &w.sc->arrive[4], tot);
+  gather_totals<1>(w.part, &w.sc->arrive[4], tot, g);
   if (threadIdx.x == 0) {
     w.sc->grad_sum = tot[0];
     *grad_lt = tot[0];

@@ -50,6 +50,9 @@ def test_struct_layout_matches_header(tmp_path):
         " offsetof(ppcg_options, loop_factor), offsetof(ppcg_options, reserved));\n"
         ' printf("%zu %zu %zu %zu\\n", sizeof(ppcg_info), offsetof(ppcg_info, resid_rec),'
         " offsetof(ppcg_info, bnorm_precond), offsetof(ppcg_info, resid_true_first));\n"
+        ' printf("%zu %zu %zu %zu %zu\\n", sizeof(ppcg_chain), offsetof(ppcg_chain, lambda),'
+        " offsetof(ppcg_chain, tau), offsetof(ppcg_chain, seed),"
+        " offsetof(ppcg_chain, draw_index));\n"
         " return 0; }\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
@@ -62,6 +65,9 @@ def test_struct_layout_matches_header(tmp_path):
                  pk.Options.reserved.offset]
     assert i == [ctypes.sizeof(pk.Info), pk.Info.resid_rec.offset, pk.Info.bnorm_precond.offset,
                  pk.Info.resid_true_first.offset]
+    ch = [int(x) for x in lines[2].split()]
+    assert ch == [ctypes.sizeof(pk.Chain), pk.Chain.lambda_.offset, pk.Chain.tau.offset,
+                  pk.Chain.seed.offset, pk.Chain.draw_index.offset]
 
 
 @needs_lib
@@ -130,3 +136,19 @@ def test_create_valid_input_reaches_device_check():
         assert L.ppcg_matrix_destroy(h) == pk.OK
     else:
         assert rc == pk.ENODEV
+
+
+@needs_lib
+def test_batch_entry_points_reject_bad_arguments():
+    """Argument checks of the batch entry points happen before any device call."""
+    L = pk.lib()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.ppcg_batch_create(ctypes.byref(h), 0, arr, pk.F64, None) == pk.EINVAL
+    assert L.ppcg_batch_create(ctypes.byref(h), 2, arr, pk.F64, None) == pk.EINVAL  # NULL X
+    assert L.ppcg_batch_create(ctypes.byref(h), 1, None, pk.F64, None) == pk.EINVAL
+    assert L.ppcg_batch_create(None, 1, arr, pk.F64, None) == pk.EINVAL
+    chains = (pk.Chain * 1)()
+    assert L.ppcg_draw_batched(None, chains, None, None, None) == pk.EINVAL
+    assert L.ppcg_solve_batched(None, chains, None, None, None) == pk.EINVAL
+    assert L.ppcg_batch_destroy(None) == pk.OK

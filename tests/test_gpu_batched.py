@@ -1,0 +1,136 @@
+"""GPU parity of the batched form: many chains of uneven size (each with its
+own design, or several on one design) solved with one launch per CG phase.
+
+Each chain's batched result must equal the single-chain call's bitwise (the
+same kernels, blocks and summation order), and the single-chain path is held
+to the oracle by test_gpu_parity.py; the FP64 batch is also checked against
+the oracle directly at a tight tolerance (1e-10 relative in beta).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import paper_1810_12437_amd as pk  # noqa: E402
+import synth  # noqa: E402
+from oracle import philox_ref as H  # noqa: E402
+from oracle import ppcg_ref as R  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def chains_for_test(scale=0.1, count=6):
+    """Uneven chains of the batched workload's laws at reduced size, plus two
+    extra chains on the first chain's design with their own vectors."""
+    probs = synth.batched_problems(count=count, seed=77, scale=scale)
+    base = probs[0]
+    extra = synth.shared_x_chains(base, 2, seed=78)
+    return probs, [(base, om, z, lam, tau) for om, z, lam, tau in extra]
+
+
+def build(dtype):
+    probs, extra = chains_for_test()
+    mats = [pk.Matrix.from_problem(P) for P in probs]
+    dt = torch.float64 if dtype == pk.F64 else torch.float32
+    rows = []  # (matrix, omega, z, lambda, tau)
+    for X, P in zip(mats, probs):
+        rows.append((X, torch.as_tensor(P.omega, device=DEV).to(dt),
+                     torch.as_tensor(P.z, device=DEV).to(dt),
+                     torch.as_tensor(P.lam, device=DEV).to(dt), P.tau))
+    for P, om, z, lam, tau in extra:
+        rows.append((mats[0], torch.as_tensor(om, device=DEV).to(dt),
+                     torch.as_tensor(z, device=DEV).to(dt),
+                     torch.as_tensor(lam, device=DEV).to(dt), tau))
+    return probs, extra, rows
+
+
+@pytest.mark.parametrize("dtype", [pk.F64, pk.F32])
+def test_batched_draw_equals_single_draws(dtype):
+    probs, extra, rows = build(dtype)
+    say("batched draw dtype", dtype, "chains", [(r[0].n, r[0].p) for r in rows])
+    B = pk.Batch([r[0] for r in rows], dtype=dtype)
+    seeds = [12437 + c for c in range(len(rows))]
+    chains = list(range(len(rows)))
+    draws = [3 + c for c in range(len(rows))]
+    betas, infos = B.draw([r[1] for r in rows], [r[2] for r in rows], [r[3] for r in rows],
+                          [r[4] for r in rows], seeds, chains, draws, tol=1e-8)
+    iters = [i["iters"] for i in infos]
+    say("iterations per chain", iters)
+    assert len(set(iters)) > 1  # chains stop at different iterations
+    for c, (X, om, z, lam, tau) in enumerate(rows):
+        ref, info = pk.draw(X, om, z, lam, tau, seeds[c], chains[c], draws[c], tol=1e-8)
+        same = bool(torch.equal(betas[c], ref))
+        say("chain", c, "bitwise equal", same, "iters", infos[c]["iters"], info["iters"])
+        assert same
+        assert infos[c]["iters"] == info["iters"]
+        assert infos[c]["refine_iters"] == info["refine_iters"]
+        assert infos[c]["status"] == pk.OK
+        assert infos[c]["resid_true"] <= 1.0
+
+
+def test_batched_solve_matches_oracle():
+    """FP64 batched solves at a tight tolerance against the oracle's Cholesky
+    solution of each chain (1e-10 relative)."""
+    probs, extra, rows = build(pk.F64)
+    B = pk.Batch([r[0] for r in rows], dtype=pk.F64)
+    rng = np.random.default_rng(5)
+    bs_np = [rng.standard_normal(r[0].p) for r in rows]
+    betas, infos = B.solve([r[1] for r in rows], [r[3] for r in rows], [r[4] for r in rows],
+                           [torch.as_tensor(b, device=DEV) for b in bs_np], tol=1e-13)
+    allp = probs + [e[0] for e in extra]
+    for c, (X, om, z, lam, tau) in enumerate(rows):
+        P = allp[c]
+        Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+        Phi = R.phi_dense(Xs, om.cpu().numpy(), lam.cpu().numpy(), tau)
+        exact = R.solve_chol(Phi, bs_np[c])
+        got = betas[c].cpu().numpy()
+        e = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+        say("chain", c, "p", X.p, "iters", infos[c]["iters"], "rel err", e)
+        assert e <= 1e-10
+        assert infos[c]["resid_true"] <= 1.0
+
+
+def test_batched_draw_matches_oracle_draw():
+    """One FP64 chain of the batch against the oracle's own draw (same eta,
+    delta stream, Prop 2.1's b, CG at a tight tolerance)."""
+    probs, extra, rows = build(pk.F64)
+    B = pk.Batch([r[0] for r in rows], dtype=pk.F64)
+    n = len(rows)
+    betas, infos = B.draw([r[1] for r in rows], [r[2] for r in rows], [r[3] for r in rows],
+                          [r[4] for r in rows], [9] * n, list(range(n)), [0] * n, tol=1e-13)
+    for c in (0, n - 1):
+        P = (probs + [e[0] for e in extra])[c]
+        X, om, z, lam, tau = rows[c]
+        Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+        eta, delta = H.eta_delta(9, c, 0, P.n, P.p)
+        b = R.rhs_b(Xs, om.cpu().numpy(), z.cpu().numpy(), lam.cpu().numpy(), tau, eta, delta)
+        Phi = R.phi_dense(Xs, om.cpu().numpy(), lam.cpu().numpy(), tau)
+        exact = R.solve_chol(Phi, b)
+        e = float(np.linalg.norm(betas[c].cpu().numpy() - exact) / np.linalg.norm(exact))
+        say("chain", c, "rel err vs oracle draw", e)
+        assert e <= 1e-10
+
+
+def test_batched_per_chain_status_and_repeat():
+    """A chain capped below its needs reports ENOTCONV without disturbing the
+    others; a second call on the same batch with other draw indices is again
+    equal to the single-chain draws."""
+    probs, extra, rows = build(pk.F64)
+    B = pk.Batch([r[0] for r in rows], dtype=pk.F64)
+    n = len(rows)
+    args = ([r[1] for r in rows], [r[2] for r in rows], [r[3] for r in rows],
+            [r[4] for r in rows], [1] * n, list(range(n)))
+    betas, infos = B.draw(*args, [5] * n, tol=1e-8, max_iter=3)
+    assert all(i["status"] == pk.ENOTCONV for i in infos if i["iters"] >= 3)
+    betas2, infos2 = B.draw(*args, [6] * n, tol=1e-8)
+    for c, (X, om, z, lam, tau) in enumerate(rows):
+        ref, info = pk.draw(X, om, z, lam, tau, 1, c, 6, tol=1e-8)
+        assert torch.equal(betas2[c], ref)
+        assert infos2[c]["status"] == pk.OK
