@@ -15,6 +15,10 @@ and the CPU oracle timed on this host as a baseline.
 
 ``--copy-calibration`` instead times a plain 512 MiB device copy: its
 FETCH_SIZE / WRITE_SIZE counters calibrate the pass kernel's counters.
+``--form batched`` instead measures the batched form: 32 independent chains
+with n log-uniform in [2e4, 2e5], p in [5e3, 4e4], tau in [1e-4, 1e-2] (the
+same column law), one batched draw of all chains per step, against the same
+chains drawn one at a time.
 """
 from __future__ import annotations
 
@@ -64,6 +68,8 @@ def parse():
                     help="oracle CG iterations in the bounded CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--form", choices=("single", "batched"), default="single",
+                    help="single: the n=1e5 p=2e4 draw (default); batched: 32 uneven chains")
     return ap.parse_args()
 
 
@@ -193,6 +199,81 @@ def copy_calibration():
           flush=True)
 
 
+def run_batched(args):
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+
+    import paper_1810_12437_amd as pk
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    workers = max(1, min(16, os.cpu_count() or 1))
+    print(f"[bench] generating 32 chains ({workers} processes) ...", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    probs = synth.batched_problems(count=32, workers=workers)
+    nnz = sum(P.nnz for P in probs)
+    print(f"[bench] total nnz {nnz} in {time.perf_counter() - t0:.1f} s; building handles",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        mats = list(ex.map(pk.Matrix.from_problem, probs))
+    t_build = time.perf_counter() - t0
+    C = len(probs)
+    out = {
+        "metric": "batched chain-draws/sec, 32 uneven chains",
+        "unit": "chain-draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+        "config": {
+            "workload": ("32 chains, n log-uniform [2e4, 2e5], p log-uniform [5e3, 4e4], "
+                         "column densities log-uniform [1e-4, 0.2], tau log-uniform [1e-4, 1e-2]; "
+                         f"relative preconditioned residual {args.tol:g}"),
+            "chains": C, "nnz_total": int(nnz), "tol": args.tol, "seed": SEED,
+        },
+        "handle_build_s": t_build,
+    }
+    forms = {}
+    for name, dtype, dt in (("f64", pk.F64, torch.float64), ("f32", pk.F32, torch.float32)):
+        if name == "f32" and args.no_f32:
+            continue
+        B = pk.Batch(mats, dtype=dtype)
+        om = [torch.as_tensor(P.omega, device="cuda").to(dt) for P in probs]
+        zz = [torch.as_tensor(P.z, device="cuda").to(dt) for P in probs]
+        la = [torch.as_tensor(P.lam, device="cuda").to(dt) for P in probs]
+        ta = [P.tau for P in probs]
+        seeds = [SEED] * C
+        chains = list(range(C))
+        for w in range(args.warmup):
+            B.draw(om, zz, la, ta, seeds, chains, [1000 + w] * C, tol=args.tol)
+        torch.cuda.synchronize()
+        print(f"[bench] timing batched {name} ({args.steps} steps)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        iters = []
+        for k in range(args.steps):
+            _, infos = B.draw(om, zz, la, ta, seeds, chains, [k] * C, tol=args.tol)
+            iters.append([i["iters"] + i["refine_iters"] for i in infos])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        it = np.array(iters, dtype=np.float64)
+        f = {"chain_draws_per_s": C * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+             "cg_iters_mean": float(it.mean()), "cg_iters_max": float(it.max()),
+             "cg_iters_min": float(it.min())}
+        # the same chains one at a time (single-chain path)
+        t0 = time.perf_counter()
+        for c in range(C):
+            pk.draw(mats[c], om[c], zz[c], la[c], ta[c], SEED, c, 0, tol=args.tol)
+        torch.cuda.synchronize()
+        f["single_chain_path_chain_draws_per_s"] = C / (time.perf_counter() - t0)
+        f["speedup_vs_single_chain_path"] = (f["chain_draws_per_s"] /
+                                             f["single_chain_path_chain_draws_per_s"])
+        forms[name] = f
+        B.close()
+    out["value"] = forms["f64"]["chain_draws_per_s"]
+    out["ms_per_step"] = forms["f64"]["ms_per_step"]
+    out["dtype"] = "f64"
+    out["forms"] = forms
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -202,6 +283,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.form == "batched":
+        run_batched(args)
         return
     import torch
 

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <limits>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/ppcg.h"
@@ -376,17 +377,33 @@ int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
     if (setup_pass_kernels() != hipSuccess) return fail(PPCG_EHIP);
 
     // Panel-blocked index-only tables of both orientations, for FP64 and
-    // FP32 gathered values (the panel width depends on the value size).
+    // FP32 gathered values (the panel width depends on the value size),
+    // built on four host threads, then uploaded.
     {
-      PanelBuild B;
-      for (int pi = 0; pi < 2; ++pi) {
-        const int elem = pi == 0 ? 8 : 4;
-        build_panels(rp, ci, n, p, elem, ncu, B);
-        int rc = upload_orient(X, B, elem, X->rows[pi]);
+      PanelBuild Bt[4];
+      auto job = [&](int q) {
+        const int elem = (q / 2) == 0 ? 8 : 4;
+        if (q % 2 == 0)
+          build_panels(rp, ci, n, p, elem, ncu, Bt[q]);
+        else
+          build_panels(cp, ri, p, n, elem, ncu, Bt[q]);
+      };
+      bool threaded = true;
+      std::vector<std::thread> th;
+      try {
+        for (int q = 1; q < 4; ++q) th.emplace_back(job, q);
+      } catch (...) {
+        threaded = false;
+      }
+      job(0);
+      for (auto& t : th) t.join();
+      if (!threaded)
+        for (int q = 1 + (int)th.size(); q < 4; ++q) job(q);
+      for (int q = 0; q < 4; ++q) {
+        Orient& o = (q % 2 == 0) ? X->rows[q / 2] : X->cols[q / 2];
+        int rc = upload_orient(X, Bt[q], (q / 2) == 0 ? 8 : 4, o);
         if (rc) return fail(rc);
-        build_panels(cp, ri, p, n, elem, ncu, B);
-        rc = upload_orient(X, B, elem, X->cols[pi]);
-        if (rc) return fail(rc);
+        Bt[q] = PanelBuild();
       }
     }
 

@@ -53,12 +53,20 @@ struct ppcg_batch {
   ppcg::DevScal* sc = nullptr;    // [nch]
   ppcg::DevScal* h_sc = nullptr;  // pinned mirror
   void* jobs[kNumJobs] = {};
-  int32_t* wg_job[kNumJobs] = {};
+  int32_t* wg_job[kNumJobs] = {};  // workgroup maps (every chain)
   int32_t* wg_local[kNumJobs] = {};
   int32_t nwg[kNumJobs] = {};
   void* vjobs = nullptr;  // VecJob<T>[nch]
-  int32_t* blk_job = nullptr;
+  int32_t* blk_job = nullptr;  // block maps of the p-vector phases (every chain)
+  int32_t* blk_local = nullptr;
   int32_t nblk = 0;
+  // maps of the CG loop restricted to the chains still iterating, rebuilt
+  // when that set changes (between launches, with the stream idle)
+  int32_t *lp_wg_job[2] = {}, *lp_wg_local[2] = {}, *lp_blk_job = nullptr,
+          *lp_blk_local = nullptr;
+  int32_t lp_nwg[2] = {}, lp_nblk = 0;
+  std::vector<char> lp_active;
+  std::vector<int32_t> chain_nwg[2], chain_nblk;
 };
 
 namespace {
@@ -125,13 +133,20 @@ int build_pass_jobs(ppcg_batch* B, int kind) {
   if ((rc = upload(B, wj, &B->wg_job[kind]))) return rc;
   if ((rc = upload(B, wl, &B->wg_local[kind]))) return rc;
   B->nwg[kind] = (int32_t)wj.size();
+  if (kind == kJobRow || kind == kJobCol) {
+    B->chain_nwg[kind].resize(B->nch);
+    for (int32_t c = 0; c < B->nch; ++c) B->chain_nwg[kind][c] = jobs[c].t.nwg;
+    if ((rc = upload(B, wj, &B->lp_wg_job[kind]))) return rc;
+    if ((rc = upload(B, wl, &B->lp_wg_local[kind]))) return rc;
+    B->lp_nwg[kind] = B->nwg[kind];
+  }
   return PPCG_OK;
 }
 
 template <typename T>
 int build_vec_jobs(ppcg_batch* B) {
   std::vector<VecJob<T>> jobs(B->nch);
-  std::vector<int32_t> bj;
+  std::vector<int32_t> bj, bl;
   const int ti = prec_index<T>();
   for (int32_t c = 0; c < B->nch; ++c) {
     const ChainBufs& C = B->ch[c];
@@ -149,16 +164,24 @@ int build_vec_jobs(ppcg_batch* B) {
     J.r = C.r64;
     J.p = C.p;
     J.max_iter = (int32_t)std::min<int64_t>(C.p, INT32_MAX);
-    J.blk0 = (int32_t)bj.size();
     J.nblk = vec_blocks(C.p);
-    for (int32_t b = 0; b < J.nblk; ++b) bj.push_back(c);
+    for (int32_t b = 0; b < J.nblk; ++b) {
+      bj.push_back(c);
+      bl.push_back(b);
+    }
   }
   VecJob<T>* dj = nullptr;
   int rc = upload(B, jobs, &dj);
   if (rc) return rc;
   B->vjobs = dj;
   if ((rc = upload(B, bj, &B->blk_job))) return rc;
-  B->nblk = (int32_t)bj.size();
+  if ((rc = upload(B, bl, &B->blk_local))) return rc;
+  if ((rc = upload(B, bj, &B->lp_blk_job))) return rc;
+  if ((rc = upload(B, bl, &B->lp_blk_local))) return rc;
+  B->nblk = B->lp_nblk = (int32_t)bj.size();
+  B->chain_nblk.resize(B->nch);
+  for (int32_t c = 0; c < B->nch; ++c) B->chain_nblk[c] = jobs[c].nblk;
+  B->lp_active.assign(B->nch, 1);
   return PPCG_OK;
 }
 
@@ -210,28 +233,74 @@ int alloc_chain(ppcg_batch* B, ChainBufs& C) {
   return PPCG_OK;
 }
 
-// CG iterations of every chain until all report done.
+// Restricts the CG loop's launch maps to the chains in `act` (the stream
+// must be idle: the maps are overwritten in place).
+int set_loop_chains(ppcg_batch* B, const std::vector<char>& act) {
+  if (act == B->lp_active) return PPCG_OK;
+  for (int kind = 0; kind < 2; ++kind) {
+    std::vector<int32_t> wj, wl;
+    for (int32_t c = 0; c < B->nch; ++c) {
+      if (!act[c]) continue;
+      for (int32_t w = 0; w < B->chain_nwg[kind][c]; ++w) {
+        wj.push_back(c);
+        wl.push_back(w);
+      }
+    }
+    if (!wj.empty()) {
+      PPCG_TRY_HIP(hipMemcpy(B->lp_wg_job[kind], wj.data(), wj.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice));
+      PPCG_TRY_HIP(hipMemcpy(B->lp_wg_local[kind], wl.data(), wl.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice));
+    }
+    B->lp_nwg[kind] = (int32_t)wj.size();
+  }
+  std::vector<int32_t> bj, bl;
+  for (int32_t c = 0; c < B->nch; ++c) {
+    if (!act[c]) continue;
+    for (int32_t b = 0; b < B->chain_nblk[c]; ++b) {
+      bj.push_back(c);
+      bl.push_back(b);
+    }
+  }
+  if (!bj.empty()) {
+    PPCG_TRY_HIP(hipMemcpy(B->lp_blk_job, bj.data(), bj.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
+    PPCG_TRY_HIP(hipMemcpy(B->lp_blk_local, bl.data(), bl.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
+  }
+  B->lp_nblk = (int32_t)bj.size();
+  B->lp_active = act;
+  return PPCG_OK;
+}
+
+// CG iterations of every chain until all report done; the launches cover
+// only the chains still iterating at the last check.
 template <typename T>
 int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
+  std::vector<char> act(B->nch);
   for (;;) {
-    for (int i = 0; i < o.check_every; ++i) {
-      PPCG_TRY_HIP(launch_panel_pass_batched<T>(reinterpret_cast<const PanelJob<T>*>(
-                                                    B->jobs[kJobRow]),
-                                                B->wg_job[kJobRow], B->wg_local[kJobRow],
-                                                B->nwg[kJobRow], st));
-      PPCG_TRY_HIP(launch_panel_pass_batched<T>(reinterpret_cast<const PanelJob<T>*>(
-                                                    B->jobs[kJobCol]),
-                                                B->wg_job[kJobCol], B->wg_local[kJobCol],
-                                                B->nwg[kJobCol], st));
-      PPCG_TRY_HIP(launch_cg_iteration_batched<T>(
-          reinterpret_cast<const VecJob<T>*>(B->vjobs), B->blk_job, B->nblk, st));
-    }
     PPCG_TRY_HIP(hipMemcpyAsync(B->h_sc, B->sc, sizeof(DevScal) * B->nch,
                                 hipMemcpyDeviceToHost, st));
     PPCG_TRY_HIP(hipStreamSynchronize(st));
-    bool all = true;
-    for (int32_t c = 0; c < B->nch; ++c) all = all && B->h_sc[c].done != 0;
-    if (all) return PPCG_OK;
+    bool any = false;
+    for (int32_t c = 0; c < B->nch; ++c) {
+      act[c] = B->h_sc[c].done ? 0 : 1;
+      any = any || act[c];
+    }
+    if (!any) return PPCG_OK;
+    int rc = set_loop_chains(B, act);
+    if (rc) return rc;
+    for (int i = 0; i < o.check_every; ++i) {
+      PPCG_TRY_HIP(launch_panel_pass_batched<T>(
+          reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobRow]), B->lp_wg_job[kJobRow],
+          B->lp_wg_local[kJobRow], B->lp_nwg[kJobRow], st));
+      PPCG_TRY_HIP(launch_panel_pass_batched<T>(
+          reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobCol]), B->lp_wg_job[kJobCol],
+          B->lp_wg_local[kJobCol], B->lp_nwg[kJobCol], st));
+      PPCG_TRY_HIP(launch_cg_iteration_batched<T>(reinterpret_cast<const VecJob<T>*>(B->vjobs),
+                                                  B->lp_blk_job, B->lp_blk_local, B->lp_nblk,
+                                                  st));
+    }
   }
 }
 
@@ -292,8 +361,9 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
   const double loop_factor =
       o.loop_factor > 0.0 ? o.loop_factor : ((sizeof(T) == 4) ? 0.5 : 1.0);
   // o.max_iter <= 0: each chain's own cap (its p)
-  PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->nblk, 0, o.tol, o.criterion,
-                                          o.max_iter, loop_factor, st));
+  PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->blk_local, B->nblk, 0,
+                                            o.tol, o.criterion, o.max_iter, loop_factor,
+                                            st));
   int rc = run_loop_batched<T>(B, o, st);
   if (rc) return rc;
   std::vector<ppcg_info> inf(B->nch);
@@ -311,8 +381,9 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
   }
   if (o.true_resid || o.refine) {
     if ((rc = fp64_parts_batched(B, st))) return rc;
-    PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->nblk, 2, o.tol, o.criterion,
-                                            o.max_iter, loop_factor, st));
+    PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->blk_local, B->nblk, 2,
+                                            o.tol, o.criterion, o.max_iter, loop_factor,
+                                            st));
     if ((rc = sync_all(B, st))) return rc;
     bool any = false;
     for (int32_t c = 0; c < B->nch; ++c) {
@@ -324,8 +395,9 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
     if (o.refine && any) {
       // One refinement for the chains whose FP64 true residual misses the
       // rule: CG restarts from it (the start kernel leaves the others done).
-      PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->nblk, 1, o.tol, o.criterion,
-                                              o.max_iter, loop_factor, st));
+      PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->blk_local, B->nblk, 1,
+                                            o.tol, o.criterion, o.max_iter, loop_factor,
+                                            st));
       if ((rc = run_loop_batched<T>(B, o, st))) return rc;
       std::vector<int32_t> refined(B->nch);
       for (int32_t c = 0; c < B->nch; ++c) {
@@ -339,8 +411,9 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
         }
       }
       if ((rc = fp64_parts_batched(B, st))) return rc;
-      PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->nblk, 2, o.tol, o.criterion,
-                                              o.max_iter, loop_factor, st));
+      PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->blk_local, B->nblk, 2,
+                                            o.tol, o.criterion, o.max_iter, loop_factor,
+                                            st));
       if ((rc = sync_all(B, st))) return rc;
       for (int32_t c = 0; c < B->nch; ++c) {
         if (!refined[c]) continue;

@@ -93,8 +93,7 @@ struct PanelJob {
   const int32_t* done;
 };
 
-// One chain's p-vector state in a batched launch; its blocks are
-// [blk0, blk0 + nblk) of the launch.
+// One chain's p-vector state in a batched launch (nblk blocks).
 template <typename T>
 struct VecJob {
   VecWork w;
@@ -109,7 +108,7 @@ struct VecJob {
   double* r;
   int64_t p;
   int32_t max_iter;    // the chain's iteration cap when the call gives none
-  int32_t blk0, nblk;
+  int32_t nblk;
 };
 
 // ---- launchers (all asynchronous on `st`) ----
@@ -186,16 +185,17 @@ int32_t vec_blocks(int64_t p);
 template <typename T>
 hipError_t launch_panel_pass_batched(const PanelJob<T>* jobs, const int32_t* wg_job,
                                      const int32_t* wg_local, int32_t nwg, hipStream_t st);
-// Block g runs block g - blk0 of chain blk_job[g] (nblk blocks in all);
+// Block g runs block blk_local[g] of chain blk_job[g] (nblk blocks in all);
 // max_iter <= 0 takes each chain's own cap.
 template <typename T>
-hipError_t launch_cg_start_batched(const VecJob<T>* jobs, const int32_t* blk_job, int32_t nblk,
-                                   int mode, double tol, int criterion, int max_iter,
-                                   double loop_factor, hipStream_t st);
-// dot, update and direction phases of every chain.
+hipError_t launch_cg_start_batched(const VecJob<T>* jobs, const int32_t* blk_job,
+                                   const int32_t* blk_local, int32_t nblk, int mode, double tol,
+                                   int criterion, int max_iter, double loop_factor,
+                                   hipStream_t st);
+// dot, update and direction phases of the chains listed in blk_job.
 template <typename T>
 hipError_t launch_cg_iteration_batched(const VecJob<T>* jobs, const int32_t* blk_job,
-                                       int32_t nblk, hipStream_t st);
+                                       const int32_t* blk_local, int32_t nblk, hipStream_t st);
 
 // Adjoint epilogue: grad_b = a, grad_loglambda = 2 d a beta, grad_logtau = sum.
 hipError_t launch_adjoint_epilogue(VecWork w, const double* a, const void* beta, int dtype,

@@ -907,64 +907,70 @@ hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s
   return hipGetLastError();
 }
 
-// ---- many chains: block g runs block g - blk0 of chain blk_job[g] ----
+// ---- many chains: block g runs block blk_local[g] of chain blk_job[g] ----
 template <typename T>
 __device__ __forceinline__ const VecJob<T>& vec_job(const VecJob<T>* jobs,
-                                                    const int32_t* blk_job, VGrid& g) {
+                                                    const int32_t* blk_job,
+                                                    const int32_t* blk_local, VGrid& g) {
   const VecJob<T>& J = jobs[blk_job[blockIdx.x]];
-  g = VGrid{(int)blockIdx.x - J.blk0, J.nblk};
+  g = VGrid{blk_local[blockIdx.x], J.nblk};
   return J;
 }
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_cg_start_b(const VecJob<T>* jobs,
-                                                    const int32_t* blk_job, int mode, double tol,
-                                                    int criterion, int max_iter,
+                                                    const int32_t* blk_job,
+                                                    const int32_t* blk_local, int mode,
+                                                    double tol, int criterion, int max_iter,
                                                     double loop_factor) {
   VGrid g;
-  const VecJob<T>& J = vec_job(jobs, blk_job, g);
+  const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
   cg_start_body<T>(J.w, mode, J.b, mode == 0 ? nullptr : J.qx64, J.d, J.m, J.beta, J.r, J.s, J.p,
                    tol, criterion, max_iter > 0 ? max_iter : J.max_iter, loop_factor, g);
 }
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_dot_b(const VecJob<T>* jobs,
-                                                  const int32_t* blk_job) {
+__global__ __launch_bounds__(kWG) void k_cg_dot_b(const VecJob<T>* jobs, const int32_t* blk_job,
+                                                  const int32_t* blk_local) {
   VGrid g;
-  const VecJob<T>& J = vec_job(jobs, blk_job, g);
+  const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
   cg_dot_body<T>(J.w, J.s, J.qsrc, J.qx, J.d, J.p, g);
 }
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_cg_update_b(const VecJob<T>* jobs,
-                                                     const int32_t* blk_job) {
+                                                     const int32_t* blk_job,
+                                                     const int32_t* blk_local) {
   VGrid g;
-  const VecJob<T>& J = vec_job(jobs, blk_job, g);
+  const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
   cg_update_body<T>(J.w, J.s, J.qx, J.d, J.m, J.beta, J.r, J.p, g);
 }
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_cg_direction_b(const VecJob<T>* jobs,
-                                                        const int32_t* blk_job) {
+                                                        const int32_t* blk_job,
+                                                        const int32_t* blk_local) {
   VGrid g;
-  const VecJob<T>& J = vec_job(jobs, blk_job, g);
+  const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
   cg_direction_body<T>(J.w, J.m, J.r, J.s, J.p, g);
 }
 
 int32_t vec_blocks(int64_t p) { return (int32_t)red_grid(p); }
 
 template <typename T>
-hipError_t launch_cg_start_batched(const VecJob<T>* jobs, const int32_t* blk_job, int32_t nblk,
-                                   int mode, double tol, int criterion, int max_iter,
-                                   double loop_factor, hipStream_t st) {
+hipError_t launch_cg_start_batched(const VecJob<T>* jobs, const int32_t* blk_job,
+                                   const int32_t* blk_local, int32_t nblk, int mode, double tol,
+                                   int criterion, int max_iter, double loop_factor,
+                                   hipStream_t st) {
   if (nblk <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_cg_start_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job, mode, tol,
-                     criterion, max_iter, loop_factor);
+  hipLaunchKernelGGL((k_cg_start_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job, blk_local,
+                     mode, tol, criterion, max_iter, loop_factor);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_cg_iteration_batched(const VecJob<T>* jobs, const int32_t* blk_job,
-                                       int32_t nblk, hipStream_t st) {
+                                       const int32_t* blk_local, int32_t nblk, hipStream_t st) {
   if (nblk <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_cg_dot_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job);
-  hipLaunchKernelGGL((k_cg_update_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job);
-  hipLaunchKernelGGL((k_cg_direction_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job);
+  hipLaunchKernelGGL((k_cg_dot_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job, blk_local);
+  hipLaunchKernelGGL((k_cg_update_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job, blk_local);
+  hipLaunchKernelGGL((k_cg_direction_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job,
+                     blk_local);
   return hipGetLastError();
 }
 
@@ -979,10 +985,11 @@ hipError_t launch_cg_iteration_batched(const VecJob<T>* jobs, const int32_t* blk
                                           hipStream_t);                                      \
   template hipError_t launch_cg_direction<T>(VecWork, const double*, const double*, T*,      \
                                              int64_t, hipStream_t);                          \
-  template hipError_t launch_cg_start_batched<T>(const VecJob<T>*, const int32_t*, int32_t,  \
-                                                 int, double, int, int, double, hipStream_t); \
+  template hipError_t launch_cg_start_batched<T>(const VecJob<T>*, const int32_t*,           \
+                                                 const int32_t*, int32_t, int, double, int,    \
+                                                 int, double, hipStream_t);                    \
   template hipError_t launch_cg_iteration_batched<T>(const VecJob<T>*, const int32_t*,       \
-                                                     int32_t, hipStream_t);
+                                                     const int32_t*, int32_t, hipStream_t);
 PPCG_INST(float)
 PPCG_INST(double)
 #undef PPCG_INST

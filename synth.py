@@ -186,22 +186,33 @@ def tiny_problem(p: int, n: int = 40, rho: float = 0.3, tau: float = 1.0,
     return Problem(f"tiny_p{p}", n, p, rp, ci, om, z, lam, float(tau))
 
 
+def _batched_chain(args):
+    c, n, p, tau, subseed = args
+    sub = np.random.default_rng(subseed)
+    rp, ci = column_law_design(n, p, sub)
+    om, z, lam = _vectors(n, p, sub, n_forced=min(50, p // 8))
+    return Problem(f"chain{c}", n, p, rp, ci, om, z, lam, float(tau))
+
+
 def batched_problems(count: int = 32, seed: int = 1813, nmin: float = 2e4,
                      nmax: float = 2e5, pmin: float = 5e3, pmax: float = 4e4,
-                     scale: float = 1.0) -> list[Problem]:
+                     scale: float = 1.0, workers: int = 1) -> list[Problem]:
     """Independent chains of uneven size: n, p log-uniform, tau log-uniform
-    in [1e-4, 1e-2], column-density law.  ``scale`` shrinks n and p for tests."""
+    in [1e-4, 1e-2], column-density law.  ``scale`` shrinks n and p for tests.
+    Each chain draws from its own generator, so ``workers`` > 1 (processes)
+    gives the same chains."""
     rng = np.random.default_rng(seed)
-    out = []
+    specs = []
     for c in range(count):
         n = max(8, int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax))) * scale)))
         p = max(4, int(round(math.exp(rng.uniform(math.log(pmin), math.log(pmax))) * scale)))
         tau = math.exp(rng.uniform(math.log(1e-4), math.log(1e-2)))
-        sub = np.random.default_rng(rng.integers(0, 2**63 - 1))
-        rp, ci = column_law_design(n, p, sub)
-        om, z, lam = _vectors(n, p, sub, n_forced=min(50, p // 8))
-        out.append(Problem(f"chain{c}", n, p, rp, ci, om, z, lam, float(tau)))
-    return out
+        specs.append((c, n, p, tau, int(rng.integers(0, 2**63 - 1))))
+    if workers <= 1:
+        return [_batched_chain(s) for s in specs]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_batched_chain, specs))
 
 
 def shared_x_chains(base: Problem, count: int, seed: int):
