@@ -249,6 +249,23 @@ int ppcg_matrix_pass_bytes(const ppcg_matrix* X, int32_t dtype, int64_t* row_pas
 int ppcg_batch_create(ppcg_batch** out, int32_t nchains, const ppcg_matrix* const* X,
                       int32_t dtype, hipStream_t stream);
 
+/*
+ * A batch of nchains (1..8) chains on ONE design X (given as for
+ * ppcg_matrix_create; copied).  Each X pass reads X's indices once for all
+ * chains: the chains' vectors are interleaved in groups of K = 2, 4 or 8
+ * (the next power of two) and a panel of the gathered vectors holds K values
+ * per entry.  Each chain's omega, z, lambda, tau, b and random stream are its
+ * own (ppcg_chain), so the chains' Phi differ and their CG runs are
+ * independent (a chain that has converged keeps its result while the
+ * others iterate).  Results agree with the single-chain calls to the solver
+ * tolerance, not bitwise (the panels are narrower, so sums group
+ * differently).  Used with ppcg_draw_batched / ppcg_solve_batched and
+ * released by ppcg_batch_destroy.
+ */
+int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64_t p,
+                             int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                             int32_t mem, int32_t dtype, hipStream_t stream);
+
 /* Releases a batch (not its X handles; NULL is allowed). */
 int ppcg_batch_destroy(ppcg_batch* B);
 

@@ -37,7 +37,8 @@ EXPORTED_SYMBOLS = (
     "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
     "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
     "ppcg_solve_backward", "ppcg_matrix_profile", "ppcg_matrix_stats",
-    "ppcg_matrix_pass_bytes", "ppcg_batch_create", "ppcg_batch_destroy",
+    "ppcg_matrix_pass_bytes", "ppcg_batch_create", "ppcg_batch_create_shared",
+    "ppcg_batch_destroy",
     "ppcg_draw_batched", "ppcg_solve_batched",
 )
 
@@ -112,11 +113,13 @@ def _declare(L):
     L.ppcg_matrix_pass_bytes.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
     L.ppcg_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _i32, _vp]
     L.ppcg_batch_destroy.argtypes = [_vp]
+    L.ppcg_batch_create_shared.argtypes = [ctypes.POINTER(_vp), _i32, _i64, _i64, _i64, _vp, _vp,
+                                           _i32, _i32, _vp]
     L.ppcg_draw_batched.argtypes = [_vp, ctypes.POINTER(Chain), ctypes.POINTER(Options),
                                     ctypes.POINTER(Info), _vp]
     L.ppcg_solve_batched.argtypes = [_vp, ctypes.POINTER(Chain), ctypes.POINTER(Options),
                                      ctypes.POINTER(Info), _vp]
-    for name in ("ppcg_batch_create", "ppcg_batch_destroy", "ppcg_draw_batched",
+    for name in ("ppcg_batch_create", "ppcg_batch_create_shared", "ppcg_batch_destroy", "ppcg_draw_batched",
                  "ppcg_solve_batched", "ppcg_matrix_pass_bytes", "ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
                  "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
                  "ppcg_solve_backward"):
@@ -259,6 +262,11 @@ class Matrix:
         return cls(P.n, P.p, P.row_ptr, P.col_idx)
 
 
+class _SharedDims:
+    def __init__(self, n, p):
+        self.n, self.p = n, p
+
+
 class Batch:
     """Handle of C chains solved together (chain c on design matrices[c]; the
     same Matrix may serve several chains).  Each CG phase of all chains is one
@@ -275,6 +283,26 @@ class Batch:
         _check(L.ppcg_batch_create(ctypes.byref(h), len(self.matrices), arr, self.dtype,
                                    _stream()), "ppcg_batch_create")
         self._h = h
+
+    @classmethod
+    def shared(cls, n, p, row_ptr, col_idx, nchains, dtype=F64):
+        """nchains (1..8) chains on one design given as CSR arrays: each X
+        pass reads the indices once for all chains."""
+        L = lib()
+        self = cls.__new__(cls)
+        self.n, self.p = int(n), int(p)
+        self.matrices = [_SharedDims(self.n, self.p)] * int(nchains)
+        self.dtype = int(dtype)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(L.ppcg_batch_create_shared(ctypes.byref(h), int(nchains), self.n, self.p,
+                                          int(ci.size), rp.ctypes.data_as(ctypes.c_void_p),
+                                          ci.ctypes.data_as(ctypes.c_void_p) if ci.size else None,
+                                          MEM_HOST, self.dtype, _stream()),
+               "ppcg_batch_create_shared")
+        self._h = h
+        return self
 
     def __len__(self):
         return len(self.matrices)

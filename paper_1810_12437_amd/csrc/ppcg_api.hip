@@ -22,58 +22,6 @@ using namespace ppcg;
 
 namespace {
 
-// Uploads a host table to the handle's device memory.
-template <typename V>
-int upload_vec(ppcg_matrix* X, const std::vector<V>& h, const V** out, int64_t* bytes) {
-  V* d = nullptr;
-  PPCG_TRY_ALLOC(X->mem.alloc(&d, h.size()));
-  if (!h.empty())
-    PPCG_TRY_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
-  *out = d;
-  *bytes += (int64_t)(h.size() * sizeof(V));
-  return PPCG_OK;
-}
-
-int upload_orient(ppcg_matrix* X, const PanelBuild& B, int elem, Orient& o) {
-  int rc;
-  int64_t by = 0;
-  PanelPass& t = o.pass;
-  if ((rc = upload_vec(X, B.idx, &t.idx, &by))) return rc;
-  if ((rc = upload_vec(X, B.chunks, &t.chunks, &by))) return rc;
-  if ((rc = upload_vec(X, B.seg_out, &t.seg_out, &by))) return rc;
-  if ((rc = upload_vec(X, B.wg_panel, &t.wg_panel, &by))) return rc;
-  if ((rc = upload_vec(X, B.wave_c, &t.wave_c, &by))) return rc;
-  if (!B.sp_off.empty()) {
-    if ((rc = upload_vec(X, B.sp_off, &o.sp_off, &by))) return rc;
-    if ((rc = upload_vec(X, B.sp_c0, &o.sp_c0, &by))) return rc;
-    if ((rc = upload_vec(X, B.sp_c1, &o.sp_c1, &by))) return rc;
-  }
-  t.gdim = B.gdim;
-  t.W = B.W;
-  t.nwg = (int32_t)B.wg_panel.size();
-  t.nchunks = (int32_t)B.chunks.size();
-  t.npieces = B.npieces;
-  o.npanels = B.npanels;
-  o.out_dim = B.out_dim;
-  const size_t part_bytes = (size_t)B.npanels * (size_t)B.out_dim * (size_t)elem;
-  unsigned char* part = nullptr;
-  unsigned char* piece = nullptr;
-  PPCG_TRY_ALLOC(X->mem.alloc(&part, part_bytes));
-  PPCG_TRY_ALLOC(X->mem.alloc(&piece, (size_t)std::max<int32_t>(t.npieces, 1) * elem));
-  // (segment, panel) pairs with no elements are never written: they stay zero.
-  PPCG_TRY_HIP(hipMemset(part, 0, std::max<size_t>(part_bytes, 1)));
-  o.part = part;
-  o.piece = piece;
-  o.dev_bytes = by + (int64_t)part_bytes + (int64_t)t.npieces * elem;
-  // Per launch: the padded index stream, the chunk descriptors, the output
-  // slots, one sum per (segment, panel) pair, and the gathered vector once
-  // (its panel copies come from cache).
-  o.pass_bytes = 2 * (int64_t)B.idx.size() + (int64_t)sizeof(ChunkDesc) * t.nchunks +
-                 4 * (int64_t)B.seg_out.size() + (int64_t)elem * B.nseg +
-                 (int64_t)elem * B.gdim;
-  return PPCG_OK;
-}
-
 // Row pass: u = omega .* (X x), as panel partials (omega applied by the pass
 // when the rows fit one panel, else by the consumer).
 template <typename T>
@@ -318,43 +266,11 @@ int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
     if (n >= INT32_MAX || p >= INT32_MAX || nnz >= ((int64_t)INT32_MAX) * 1024) return PPCG_EINVAL;
     if (mem != PPCG_MEM_HOST && mem != PPCG_MEM_DEVICE) return PPCG_EINVAL;
 
-    std::vector<int64_t> rp(n + 1);
-    std::vector<int32_t> ci(nnz);
-    if (mem == PPCG_MEM_HOST) {
-      std::memcpy(rp.data(), row_ptr, (n + 1) * sizeof(int64_t));
-      if (nnz) std::memcpy(ci.data(), col_idx, nnz * sizeof(int32_t));
-    } else {
-      int nd = 0;
-      if (hipGetDeviceCount(&nd) != hipSuccess || nd < 1) return PPCG_ENODEV;
-      PPCG_TRY_HIP(hipMemcpyAsync(rp.data(), row_ptr, (n + 1) * sizeof(int64_t),
-                                  hipMemcpyDeviceToHost, stream));
-      if (nnz)
-        PPCG_TRY_HIP(hipMemcpyAsync(ci.data(), col_idx, nnz * sizeof(int32_t),
-                                    hipMemcpyDeviceToHost, stream));
-      PPCG_TRY_HIP(hipStreamSynchronize(stream));
-    }
-    // Validate CSR: offsets monotone from 0 to nnz; columns in range and
-    // strictly increasing within a row (binary X has no duplicates).
-    if (rp[0] != 0 || rp[n] != nnz) return PPCG_EINVAL;
-    for (int64_t i = 0; i < n; ++i) {
-      if (rp[i + 1] < rp[i]) return PPCG_EINVAL;
-      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int32_t c = ci[k];
-        if (c < 0 || c >= p) return PPCG_EINVAL;
-        if (k > rp[i] && c <= ci[k - 1]) return PPCG_EINVAL;
-      }
-    }
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PPCG_ENODEV;
-    // CSC twin by a counting sort over columns (rows stay increasing).
-    std::vector<int64_t> cp(p + 1, 0);
-    for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;
-    for (int64_t j = 0; j < p; ++j) cp[j + 1] += cp[j];
-    std::vector<int32_t> ri(nnz);
+    std::vector<int64_t> rp, cp;
+    std::vector<int32_t> ci, ri;
     {
-      std::vector<int64_t> fill(cp.begin(), cp.end() - 1);
-      for (int64_t i = 0; i < n; ++i)
-        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) ri[fill[ci[k]]++] = (int32_t)i;
+      const int rc = read_binary_csr(n, p, nnz, row_ptr, col_idx, mem, stream, rp, ci, cp, ri);
+      if (rc) return rc;
     }
 
     ppcg_matrix* X = new (std::nothrow) ppcg_matrix();
@@ -401,7 +317,7 @@ int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
         for (int q = 1 + (int)th.size(); q < 4; ++q) job(q);
       for (int q = 0; q < 4; ++q) {
         Orient& o = (q % 2 == 0) ? X->rows[q / 2] : X->cols[q / 2];
-        int rc = upload_orient(X, Bt[q], (q / 2) == 0 ? 8 : 4, o);
+        int rc = upload_orient(X->mem, Bt[q], (q / 2) == 0 ? 8 : 4, 1, o);
         if (rc) return fail(rc);
         Bt[q] = PanelBuild();
       }

@@ -4,6 +4,7 @@
 
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/ppcg.h"
@@ -29,6 +30,7 @@ struct ChainBufs {
 template <typename T>
 Combine<T> comb_buf(const Orient& o, const void* part, const void* piece, const T* scale) {
   Combine<T> c{};
+  c.es = 1;
   c.part = reinterpret_cast<const T*>(part);
   c.stride = o.out_dim;
   c.nparts = o.npanels;
@@ -38,6 +40,34 @@ Combine<T> comb_buf(const Orient& o, const void* part, const void* piece, const 
   c.sp_c1 = o.sp_c1;
   c.piece = reinterpret_cast<const T*>(piece);
   return c;
+}
+
+// Vector c's view of a K-wide orientation's pass output ([panel][dim][K]);
+// scale, when given, is [dim][K] too.
+template <typename T>
+Combine<T> comb_k(const Orient& o, int K, int c, const T* scale) {
+  Combine<T> x{};
+  x.part = reinterpret_cast<const T*>(o.part) + c;
+  x.stride = o.out_dim * K;
+  x.nparts = o.npanels;
+  x.es = K;
+  x.scale = scale ? scale + c : nullptr;
+  x.sp_off = o.sp_off;
+  x.sp_c0 = o.sp_c0;
+  x.sp_c1 = o.sp_c1;
+  x.piece = reinterpret_cast<const T*>(o.piece) + c;
+  return x;
+}
+
+// All K interleaved vectors of a [dim][K] array as a pass input.
+template <typename T>
+Combine<T> comb_all(const T* v, int K) {
+  Combine<T> x{};
+  x.part = v;
+  x.stride = 0;
+  x.nparts = 1;
+  x.es = K;
+  return x;
 }
 
 enum { kJobRow = 0, kJobCol, kJobRow64, kJobCol64, kJobRhs64, kNumJobs };
@@ -67,6 +97,13 @@ struct ppcg_batch {
   int32_t lp_nwg[2] = {}, lp_nblk = 0;
   std::vector<char> lp_active;
   std::vector<int32_t> chain_nwg[2], chain_nblk;
+  // shared form: every chain on one design, K interleaved vectors per pass
+  bool shared = false;
+  int32_t K = 1;
+  int64_t n = 0, p = 0;
+  ppcg::Orient srows[2], scols[2];  // K-wide tables: [0] FP64, [1] FP32
+  double *y_K = nullptr, *om64_K = nullptr, *beta_K = nullptr;  // [dim][K]
+  void *omT_K = nullptr, *s_K = nullptr;                         // [dim][K], dtype
 };
 
 namespace {
@@ -154,7 +191,7 @@ int build_vec_jobs(ppcg_batch* B) {
     J = VecJob<T>{};
     J.w = VecWork{C.red, &B->sc[c]};
     J.s = reinterpret_cast<T*>(C.s);
-    J.qsrc = comb_buf<T>(C.X->cols[ti], C.cpart[ti], C.cpiece[ti], nullptr);
+    if (!B->shared) J.qsrc = comb_buf<T>(C.X->cols[ti], C.cpart[ti], C.cpiece[ti], nullptr);
     J.qx = reinterpret_cast<T*>(C.qx);
     J.b = C.b64;
     J.qx64 = C.qx64;
@@ -165,6 +202,13 @@ int build_vec_jobs(ppcg_batch* B) {
     J.p = C.p;
     J.max_iter = (int32_t)std::min<int64_t>(C.p, INT32_MAX);
     J.nblk = vec_blocks(C.p);
+    J.es = 1;
+    if (B->shared) {
+      // s interleaved over the chains; q from the K-wide column pass
+      J.s = reinterpret_cast<T*>(B->s_K) + c;
+      J.es = B->K;
+      J.qsrc = comb_k<T>(B->scols[ti], B->K, c, nullptr);
+    }
     for (int32_t b = 0; b < J.nblk; ++b) {
       bj.push_back(c);
       bl.push_back(b);
@@ -198,10 +242,14 @@ int alloc_chain(ppcg_batch* B, ChainBufs& C) {
   PPCG_TRY_ALLOC(B->mem.alloc(&C.r64, P));
   PPCG_TRY_ALLOC(B->mem.alloc(&C.qx64, P));
   PPCG_TRY_ALLOC(B->mem.alloc(&C.red, (size_t)kMaxRedBlocks * 4));
-  PPCG_TRY_ALLOC(B->mem.alloc(&s, P * ts));
   PPCG_TRY_ALLOC(B->mem.alloc(&qx, P * ts));
-  C.s = s;
   C.qx = qx;
+  if (B->shared) {
+    C.omegaT = C.omega64;  // FP64 copy; the K-wide passes read omT_K
+    return PPCG_OK;
+  }
+  PPCG_TRY_ALLOC(B->mem.alloc(&s, P * ts));
+  C.s = s;
   if (B->dtype == PPCG_F64) {
     C.omegaT = C.omega64;
   } else {
@@ -237,7 +285,7 @@ int alloc_chain(ppcg_batch* B, ChainBufs& C) {
 // must be idle: the maps are overwritten in place).
 int set_loop_chains(ppcg_batch* B, const std::vector<char>& act) {
   if (act == B->lp_active) return PPCG_OK;
-  for (int kind = 0; kind < 2; ++kind) {
+  for (int kind = 0; kind < 2 && !B->shared; ++kind) {
     std::vector<int32_t> wj, wl;
     for (int32_t c = 0; c < B->nch; ++c) {
       if (!act[c]) continue;
@@ -273,6 +321,39 @@ int set_loop_chains(ppcg_batch* B, const std::vector<char>& act) {
   return PPCG_OK;
 }
 
+// Shared form: row pass u = omega .* (X s) and column pass X^T u for the K
+// interleaved vectors of the loop's dtype, skipped once every chain is done.
+template <typename T>
+int shared_loop_passes(ppcg_batch* B, hipStream_t st) {
+  const int ti = prec_index<T>();
+  const Orient& ro = B->srows[ti];
+  const Orient& co = B->scols[ti];
+  const T* om = reinterpret_cast<const T*>(B->omT_K);
+  const int dstride = (int)(sizeof(DevScal) / sizeof(int32_t));
+  PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, ro.pass, comb_all<T>(reinterpret_cast<T*>(B->s_K),
+                                                                 B->K),
+                                      reinterpret_cast<T*>(ro.part),
+                                      reinterpret_cast<T*>(ro.piece),
+                                      rows_direct(ro) ? om : nullptr, &B->sc[0].done, dstride,
+                                      st));
+  PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, co.pass,
+                                      comb_k<T>(ro, B->K, 0, rows_direct(ro) ? nullptr : om),
+                                      reinterpret_cast<T*>(co.part),
+                                      reinterpret_cast<T*>(co.piece), nullptr, &B->sc[0].done,
+                                      dstride, st));
+  return PPCG_OK;
+}
+
+// Shared form: src_c (FP64, one per chain) interleaved into dst [dim][K].
+template <typename T>
+int interleave(ppcg_batch* B, double* const* src_of_chain, int64_t dim, T* dst,
+               hipStream_t st) {
+  VecPtrs v{};
+  for (int32_t c = 0; c < B->nch; ++c) v.p[c] = src_of_chain[c];
+  PPCG_TRY_HIP(launch_interleave<T>(v, B->nch, B->K, dim, dst, st));
+  return PPCG_OK;
+}
+
 // CG iterations of every chain until all report done; the launches cover
 // only the chains still iterating at the last check.
 template <typename T>
@@ -291,12 +372,16 @@ int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
     int rc = set_loop_chains(B, act);
     if (rc) return rc;
     for (int i = 0; i < o.check_every; ++i) {
-      PPCG_TRY_HIP(launch_panel_pass_batched<T>(
-          reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobRow]), B->lp_wg_job[kJobRow],
-          B->lp_wg_local[kJobRow], B->lp_nwg[kJobRow], st));
-      PPCG_TRY_HIP(launch_panel_pass_batched<T>(
-          reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobCol]), B->lp_wg_job[kJobCol],
-          B->lp_wg_local[kJobCol], B->lp_nwg[kJobCol], st));
+      if (B->shared) {
+        if ((rc = shared_loop_passes<T>(B, st))) return rc;
+      } else {
+        PPCG_TRY_HIP(launch_panel_pass_batched<T>(
+            reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobRow]), B->lp_wg_job[kJobRow],
+            B->lp_wg_local[kJobRow], B->lp_nwg[kJobRow], st));
+        PPCG_TRY_HIP(launch_panel_pass_batched<T>(
+            reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobCol]), B->lp_wg_job[kJobCol],
+            B->lp_wg_local[kJobCol], B->lp_nwg[kJobCol], st));
+      }
       PPCG_TRY_HIP(launch_cg_iteration_batched<T>(reinterpret_cast<const VecJob<T>*>(B->vjobs),
                                                   B->lp_blk_job, B->lp_blk_local, B->lp_nblk,
                                                   st));
@@ -306,6 +391,27 @@ int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
 
 // FP64 product parts qx64_c = X_c^T (omega_c .* (X_c beta64_c)) of every chain.
 int fp64_parts_batched(ppcg_batch* B, hipStream_t st) {
+  if (B->shared) {
+    std::vector<double*> src(B->nch);
+    for (int32_t c = 0; c < B->nch; ++c) src[c] = B->ch[c].beta64;
+    int rc = interleave<double>(B, src.data(), B->p, B->beta_K, st);
+    if (rc) return rc;
+    const Orient& ro = B->srows[0];
+    const Orient& co = B->scols[0];
+    PPCG_TRY_HIP(launch_panel_pass_k<double>(B->K, ro.pass, comb_all<double>(B->beta_K, B->K),
+                                             reinterpret_cast<double*>(ro.part),
+                                             reinterpret_cast<double*>(ro.piece),
+                                             rows_direct(ro) ? B->om64_K : nullptr, nullptr, 0,
+                                             st));
+    PPCG_TRY_HIP(launch_panel_pass_k<double>(
+        B->K, co.pass, comb_k<double>(ro, B->K, 0, rows_direct(ro) ? nullptr : B->om64_K),
+        reinterpret_cast<double*>(co.part), reinterpret_cast<double*>(co.piece), nullptr,
+        nullptr, 0, st));
+    for (int32_t c = 0; c < B->nch; ++c)
+      PPCG_TRY_HIP(launch_combine<double, double>(comb_k<double>(co, B->K, c, nullptr), B->p,
+                                                  B->ch[c].qx64, st));
+    return PPCG_OK;
+  }
   PPCG_TRY_HIP(launch_panel_pass_batched<double>(
       reinterpret_cast<const PanelJob<double>*>(B->jobs[kJobRow64]), B->wg_job[kJobRow64],
       B->wg_local[kJobRow64], B->nwg[kJobRow64], st));
@@ -334,7 +440,7 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
     const ChainBufs& C = B->ch[c];
     const ppcg_chain& A = chains[c];
     PPCG_TRY_HIP(launch_prep(A.lambda, A.omega, dt, A.tau, C.n, C.p, C.d, C.m, C.omega64, st));
-    if (dt == PPCG_F32)
+    if (dt == PPCG_F32 && !B->shared)
       PPCG_TRY_HIP(hipMemcpyAsync(C.omegaT, A.omega, (size_t)C.n * sizeof(float),
                                   hipMemcpyDeviceToDevice, st));
     if (draw) {
@@ -344,7 +450,34 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
       PPCG_TRY_HIP(launch_convert_to_f64(A.b, dt, C.p, C.b64, st));
     }
   }
-  if (draw) {
+  int rc = 0;
+  if (B->shared) {
+    std::vector<double*> om(B->nch), y(B->nch);
+    for (int32_t c = 0; c < B->nch; ++c) {
+      om[c] = B->ch[c].omega64;
+      y[c] = B->ch[c].y64;
+    }
+    if ((rc = interleave<double>(B, om.data(), B->n, B->om64_K, st))) return rc;
+    if (dt == PPCG_F32 &&
+        (rc = interleave<float>(B, om.data(), B->n, reinterpret_cast<float*>(B->omT_K), st)))
+      return rc;
+    if (draw) {
+      if ((rc = interleave<double>(B, y.data(), B->n, B->y_K, st))) return rc;
+      const Orient& co = B->scols[0];
+      PPCG_TRY_HIP(launch_panel_pass_k<double>(B->K, co.pass, comb_all<double>(B->y_K, B->K),
+                                               reinterpret_cast<double*>(co.part),
+                                               reinterpret_cast<double*>(co.piece), nullptr,
+                                               nullptr, 0, st));
+      for (int32_t c = 0; c < B->nch; ++c) {
+        const ChainBufs& C = B->ch[c];
+        const ppcg_chain& A = chains[c];
+        PPCG_TRY_HIP(launch_combine<double, double>(comb_k<double>(co, B->K, c, nullptr), C.p,
+                                                    C.qx64, st));
+        PPCG_TRY_HIP(launch_rhs_fin(C.qx64, A.lambda, dt, A.tau, A.seed, A.chain,
+                                    A.draw_index, C.p, C.b64, st));
+      }
+    }
+  } else if (draw) {
     PPCG_TRY_HIP(launch_panel_pass_batched<double>(
         reinterpret_cast<const PanelJob<double>*>(B->jobs[kJobRhs64]), B->wg_job[kJobRhs64],
         B->wg_local[kJobRhs64], B->nwg[kJobRhs64], st));
@@ -364,8 +497,7 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
   PPCG_TRY_HIP(launch_cg_start_batched<T>(vj, B->blk_job, B->blk_local, B->nblk, 0,
                                             o.tol, o.criterion, o.max_iter, loop_factor,
                                             st));
-  int rc = run_loop_batched<T>(B, o, st);
-  if (rc) return rc;
+  if ((rc = run_loop_batched<T>(B, o, st))) return rc;
   std::vector<ppcg_info> inf(B->nch);
   for (int32_t c = 0; c < B->nch; ++c) {
     const DevScal& S = B->h_sc[c];
@@ -503,6 +635,127 @@ int ppcg_batch_create(ppcg_batch** out, int32_t nchains, const ppcg_matrix* cons
     if ((rc = build_pass_jobs<double>(B, kJobRow64)) || (rc = build_pass_jobs<double>(B, kJobCol64)) ||
         (rc = build_pass_jobs<double>(B, kJobRhs64)))
       return fail(rc);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);
+    *out = B;
+    return PPCG_OK;
+  } catch (const std::bad_alloc&) {
+    return PPCG_ENOMEM;
+  } catch (...) {
+    return PPCG_EINVAL;
+  }
+}
+
+int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64_t p,
+                             int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                             int32_t mem, int32_t dtype, hipStream_t stream) {
+  try {
+    if (!out) return PPCG_EINVAL;
+    *out = nullptr;
+    if (nchains < 1 || nchains > 8 || !valid_dtype(dtype)) return PPCG_EINVAL;
+    if (n < 1 || p < 1 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx)) return PPCG_EINVAL;
+    if (n >= INT32_MAX || p >= INT32_MAX || nnz >= ((int64_t)INT32_MAX) * 1024) return PPCG_EINVAL;
+    if (mem != PPCG_MEM_HOST && mem != PPCG_MEM_DEVICE) return PPCG_EINVAL;
+    std::vector<int64_t> rp, cp;
+    std::vector<int32_t> ci, ri;
+    {
+      const int rc = read_binary_csr(n, p, nnz, row_ptr, col_idx, mem, stream, rp, ci, cp, ri);
+      if (rc) return rc;
+    }
+    ppcg_batch* B = new (std::nothrow) ppcg_batch();
+    if (!B) return PPCG_ENOMEM;
+    auto fail = [&](int rc) {
+      B->mem.release();
+      if (B->h_sc) (void)hipHostFree(B->h_sc);
+      delete B;
+      return rc;
+    };
+    B->shared = true;
+    B->dtype = dtype;
+    B->nch = nchains;
+    B->K = nchains <= 2 ? 2 : (nchains <= 4 ? 4 : 8);
+    B->n = n;
+    B->p = p;
+    const int K = B->K;
+    if (hipGetDevice(&B->device) != hipSuccess) return fail(PPCG_EHIP);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, B->device) !=
+            hipSuccess || ncu < 1)
+      ncu = 256;
+    if (setup_pass_kernels() != hipSuccess) return fail(PPCG_EHIP);
+    // K-wide tables (the panel holds K values per entry): FP64 always, FP32
+    // for the FP32 form; built on host threads, then uploaded.
+    {
+      const int nt = dtype == PPCG_F64 ? 2 : 4;
+      PanelBuild Bt[4];
+      auto job = [&](int q) {
+        const int elem = (q / 2) == 0 ? 8 : 4;
+        if (q % 2 == 0)
+          build_panels(rp, ci, n, p, elem * K, ncu, Bt[q]);
+        else
+          build_panels(cp, ri, p, n, elem * K, ncu, Bt[q]);
+      };
+      std::vector<std::thread> th;
+      int started = 1;
+      try {
+        for (int q = 1; q < nt; ++q, ++started) th.emplace_back(job, q);
+      } catch (...) {
+      }
+      job(0);
+      for (auto& t : th) t.join();
+      for (int q = started; q < nt; ++q) job(q);
+      for (int q = 0; q < nt; ++q) {
+        Orient& o = (q % 2 == 0) ? B->srows[q / 2] : B->scols[q / 2];
+        const int rc = upload_orient(B->mem, Bt[q], (q / 2) == 0 ? 8 : 4, K, o);
+        if (rc) return fail(rc);
+        Bt[q] = PanelBuild();
+      }
+    }
+    B->ch.resize(nchains);
+    for (int32_t c = 0; c < nchains; ++c) {
+      B->ch[c].n = n;
+      B->ch[c].p = p;
+      const int rc = alloc_chain(B, B->ch[c]);
+      if (rc) return fail(rc);
+    }
+    const size_t ts = dtype == PPCG_F64 ? 8 : 4;
+    unsigned char *omT = nullptr, *sK = nullptr;
+    if (B->mem.alloc(&B->y_K, (size_t)n * K) != hipSuccess ||
+        B->mem.alloc(&B->om64_K, (size_t)n * K) != hipSuccess ||
+        B->mem.alloc(&B->beta_K, (size_t)p * K) != hipSuccess ||
+        B->mem.alloc(&sK, (size_t)p * K * ts) != hipSuccess)
+      return fail(PPCG_ENOMEM);
+    if (dtype == PPCG_F32) {
+      if (B->mem.alloc(&omT, (size_t)n * K * ts) != hipSuccess) return fail(PPCG_ENOMEM);
+      B->omT_K = omT;
+    } else {
+      B->omT_K = B->om64_K;
+    }
+    B->s_K = sK;
+    // vector slots beyond the chains stay zero (their products are ignored)
+    if (hipMemset(B->y_K, 0, (size_t)n * K * 8) != hipSuccess ||
+        hipMemset(B->om64_K, 0, (size_t)n * K * 8) != hipSuccess ||
+        hipMemset(B->beta_K, 0, (size_t)p * K * 8) != hipSuccess ||
+        hipMemset(sK, 0, (size_t)p * K * ts) != hipSuccess ||
+        (omT && hipMemset(omT, 0, (size_t)n * K * ts) != hipSuccess))
+      return fail(PPCG_EHIP);
+    // one scalar block per vector slot; slots beyond the chains stay done
+    if (B->mem.alloc(&B->sc, (size_t)K) != hipSuccess) return fail(PPCG_ENOMEM);
+    {
+      std::vector<DevScal> init(K);
+      std::memset(init.data(), 0, sizeof(DevScal) * K);
+      for (int c = nchains; c < K; ++c) init[c].done = 1;
+      if (hipMemcpy(B->sc, init.data(), sizeof(DevScal) * K, hipMemcpyHostToDevice) !=
+          hipSuccess)
+        return fail(PPCG_EHIP);
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&B->h_sc), sizeof(DevScal) * K, 0) !=
+        hipSuccess) {
+      B->h_sc = nullptr;
+      return fail(PPCG_ENOMEM);
+    }
+    std::memset(B->h_sc, 0, sizeof(DevScal) * K);
+    const int rc = dtype == PPCG_F64 ? build_vec_jobs<double>(B) : build_vec_jobs<float>(B);
+    if (rc) return fail(rc);
     if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);
     *out = B;
     return PPCG_OK;

@@ -11,6 +11,7 @@
 
 #include "../../include/ppcg.h"
 #include "ppcg_kernels.h"
+#include "ppcg_panels.h"
 
 namespace ppcg {
 
@@ -120,6 +121,7 @@ constexpr int prec_index() {
 template <typename T>
 inline Combine<T> comb_vec(const T* v) {
   Combine<T> c{};
+  c.es = 1;
   c.part = v;
   c.stride = 0;
   c.nparts = 1;
@@ -130,6 +132,7 @@ inline Combine<T> comb_vec(const T* v) {
 template <typename T>
 inline Combine<T> comb_out(const Orient& o, const T* scale) {
   Combine<T> c{};
+  c.es = 1;
   c.part = reinterpret_cast<const T*>(o.part);
   c.stride = o.out_dim;
   c.nparts = o.npanels;
@@ -151,5 +154,29 @@ inline double ratio(double meas, double thresh2) {
 }
 
 inline bool bad_tau(double tau) { return !(tau > 0.0) || !std::isfinite(tau); }
+
+// Uploads a host table to device memory owned by `mem`.
+template <typename V>
+int upload_vec(DevBuf& mem, const std::vector<V>& h, const V** out, int64_t* bytes) {
+  V* d = nullptr;
+  PPCG_TRY_ALLOC(mem.alloc(&d, h.size()));
+  if (!h.empty())
+    PPCG_TRY_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  *out = d;
+  *bytes += (int64_t)(h.size() * sizeof(V));
+  return PPCG_OK;
+}
+
+// Uploads one orientation's tables and allocates its outputs for K
+// interleaved vectors of `elem`-byte values (K = 1: one vector).
+int upload_orient(DevBuf& mem, const PanelBuild& B, int elem, int K, Orient& o);
+
+// Reads (host or device), validates and sorts out a binary CSR: rp, ci as
+// given, cp, ri the CSC twin.  PPCG_EINVAL on malformed input, PPCG_ENODEV
+// without a device.
+int read_binary_csr(int64_t n, int64_t p, int64_t nnz, const int64_t* row_ptr,
+                    const int32_t* col_idx, int32_t mem, hipStream_t stream,
+                    std::vector<int64_t>& rp, std::vector<int32_t>& ci,
+                    std::vector<int64_t>& cp, std::vector<int32_t>& ri);
 
 }  // namespace ppcg

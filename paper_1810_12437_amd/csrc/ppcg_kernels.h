@@ -36,14 +36,16 @@ struct PanelPass {
   int32_t npieces;
 };
 
-// value(i) = scale[i] * (sum_k part[k * stride + i] + sum of the pieces of i):
-// the input a pass gathers, or the consumer's view of a pass output.
+// value(i) = scale[i es] * (sum_k part[k * stride + i es] + sum of the pieces
+// of i): the input a pass gathers, or the consumer's view of a pass output.
+// es is 1 for one vector; K when K vectors are interleaved ([dim][K], with
+// the pointers offset to the vector wanted).
 template <typename T>
 struct Combine {
   const T* part;
   int64_t stride;
   int32_t nparts;
-  int32_t pad;
+  int32_t es;
   const T* scale;         // may be null
   const int32_t* sp_off;  // [dim + 1] pieces of element i (null: none)
   const int32_t* sp_c0;   // piece id ranges [c0, c1]
@@ -109,6 +111,8 @@ struct VecJob {
   int64_t p;
   int32_t max_iter;    // the chain's iteration cap when the call gives none
   int32_t nblk;
+  int32_t es;          // element stride of s (K when the chains' s are interleaved)
+  int32_t pad;
 };
 
 // ---- launchers (all asynchronous on `st`) ----
@@ -148,6 +152,15 @@ hipError_t launch_convert_to_f64(const void* in, int dtype, int64_t count, doubl
 hipError_t launch_convert_from_f64(const double* in, int dtype, int64_t count, void* out,
                                    hipStream_t st);
 
+// Up to eight FP64 source vectors (kernel argument).
+struct VecPtrs {
+  const double* p[8];
+};
+// dst[i K + r] = (T) src[r][i] for r < nsrc, i < dim.
+template <typename T>
+hipError_t launch_interleave(const VecPtrs& src, int nsrc, int K, int64_t dim, T* dst,
+                             hipStream_t st);
+
 // out = qx + d .* v  (dtype T in and out).
 template <typename T>
 hipError_t launch_phi_finish(const T* qx, const double* d, const T* v, int64_t p, T* out,
@@ -178,6 +191,14 @@ hipError_t launch_cg_update(VecWork w, const T* s, const T* qx, const double* d,
 template <typename T>
 hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s,
                                int64_t p, hipStream_t st);
+// One X pass over K in {2, 4, 8} interleaved vectors ([dim][K] inputs and
+// outputs; part_out[(k * out_dim + id) * K + r]); skipped when the K flags
+// done[i * dstride] are all set (done may be null).
+template <typename T>
+hipError_t launch_panel_pass_k(int K, const PanelPass& t, const Combine<T>& x, T* part_out,
+                               T* piece_out, const T* out_scale, const int32_t* done,
+                               int dstride, hipStream_t st);
+
 // Blocks of one chain's p-vector phases.
 int32_t vec_blocks(int64_t p);
 

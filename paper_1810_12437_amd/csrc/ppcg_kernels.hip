@@ -109,25 +109,27 @@ __device__ __forceinline__ void gather_totals(const double* part, uint32_t* ctr,
 // ------------------------------------------------------------------------
 // X pass: panel-resident gathers, one wavefront per chunk
 // ------------------------------------------------------------------------
+// value(i) of vector r of an interleaved set (r = 0 for one vector).
 template <typename T>
-__device__ __forceinline__ T combine_at(const Combine<T>& c, int64_t i) {
+__device__ __forceinline__ T combine_at(const Combine<T>& c, int64_t i, int r = 0) {
+  const int64_t e = i * c.es + r;
   // Issue up to eight partial loads before adding them (fixed order).
   T pv[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) pv[k] = (k < c.nparts) ? c.part[(int64_t)k * c.stride + i] : T(0);
+  for (int k = 0; k < 8; ++k) pv[k] = (k < c.nparts) ? c.part[(int64_t)k * c.stride + e] : T(0);
   T v = pv[0];
 #pragma unroll
   for (int k = 1; k < 8; ++k)
     if (k < c.nparts) v += pv[k];
-  for (int k = 8; k < c.nparts; ++k) v += c.part[(int64_t)k * c.stride + i];
+  for (int k = 8; k < c.nparts; ++k) v += c.part[(int64_t)k * c.stride + e];
   if (c.sp_off != nullptr) {
     const int q1 = c.sp_off[i + 1];
     for (int q = c.sp_off[i]; q < q1; ++q) {
       const int c1 = c.sp_c1[q];
-      for (int cc = c.sp_c0[q]; cc <= c1; ++cc) v += c.piece[cc];
+      for (int cc = c.sp_c0[q]; cc <= c1; ++cc) v += c.piece[(int64_t)cc * c.es + r];
     }
   }
-  return c.scale ? v * c.scale[i] : v;
+  return c.scale ? v * c.scale[e] : v;
 }
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
@@ -206,26 +208,64 @@ __device__ __forceinline__ int32_t out_slot(const PanelPass& t, const ChunkDesc&
   return (last && si < (D.info >> 24)) ? t.seg_out[D.first + si] : -1;
 }
 
-template <typename T>
-__device__ __forceinline__ T gather_sum16(const T* xl, const u16x8& a, const u16x8& b) {
-  T v[kPV];
+// K values of one panel entry (the K vectors of an interleaved set).
+template <typename T, int K>
+struct alignas(sizeof(T) * K) PanelEntry {
+  T v[K];
+};
+
+// Adds this lane's group of kPV elements to acc (per vector), in element
+// order.
+template <typename T, int K>
+__device__ __forceinline__ void gather_add16(const T* xl, const u16x8& a, const u16x8& b,
+                                             T (&acc)[K]) {
+  if constexpr (K == 1) {
+    T v[kPV];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    v[j] = xl[a[j]];
-    v[8 + j] = xl[b[j]];
+    for (int j = 0; j < 8; ++j) {
+      v[j] = xl[a[j]];
+      v[8 + j] = xl[b[j]];
+    }
+    T s = v[0];
+#pragma unroll
+    for (int j = 1; j < kPV; ++j) s += v[j];
+    acc[0] += s;
+  } else {
+    const PanelEntry<T, K>* xp = reinterpret_cast<const PanelEntry<T, K>*>(xl);
+    T s[K];
+    {
+      const PanelEntry<T, K> u = xp[a[0]];
+#pragma unroll
+      for (int r = 0; r < K; ++r) s[r] = u.v[r];
+    }
+#pragma unroll
+    for (int j = 1; j < kPV; ++j) {
+      const PanelEntry<T, K> u = xp[j < 8 ? a[j] : b[j - 8]];
+#pragma unroll
+      for (int r = 0; r < K; ++r) s[r] += u.v[r];
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) acc[r] += s[r];
   }
-  T s = v[0];
+}
+
+// acc[r] += (cond ? DPP move of acc[r] : 0) for every vector.
+template <int CTRL, int RM, typename T, int K>
+__device__ __forceinline__ void dpp_add(T (&acc)[K], bool cond) {
 #pragma unroll
-  for (int j = 1; j < kPV; ++j) s += v[j];
-  return s;
+  for (int r = 0; r < K; ++r) {
+    const T v = dpp_move<CTRL, RM>(acc[r]);
+    if (cond) acc[r] += v;
+  }
 }
 
 // Sum of each slice of chunk D at the slice's last lane (packed), or of the
-// whole wavefront at lane 63 (long), then the write.  Fixed order.
-template <typename T>
-__device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T acc, int32_t slot,
-                                             T scl, int32_t piece, int lane,
-                                             T* __restrict__ part_out,
+// whole wavefront at lane 63 (long), then the write (K values per slot).
+// Fixed order.
+template <typename T, int K>
+__device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T (&acc)[K],
+                                             int32_t slot, const T (&scl)[K], int32_t piece,
+                                             int lane, T* __restrict__ part_out,
                                              T* __restrict__ piece_out,
                                              const T* __restrict__ out_scale) {
   const int kind = ck_kind(info);
@@ -235,54 +275,49 @@ __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T acc, i
     const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
     const int off = lane - (63 - __clzll(sm & upto));
     const int nrow = (info >> 12) & 7;
-    if (nrow > 0) {
-      const T v = dpp_move<kDppRowShr + 1, 0xf>(acc);
-      if (off >= 1) acc += v;
+    if (nrow > 0) dpp_add<kDppRowShr + 1, 0xf>(acc, off >= 1);
+    if (nrow > 1) dpp_add<kDppRowShr + 2, 0xf>(acc, off >= 2);
+    if (nrow > 2) dpp_add<kDppRowShr + 4, 0xf>(acc, off >= 4);
+    if (nrow > 3) dpp_add<kDppRowShr + 8, 0xf>(acc, off >= 8);
+    if ((info >> 16) & 1) dpp_add<kDppBcast15, 0xa>(acc, off > (lane & 15));
+    if ((info >> 17) & 1) dpp_add<kDppBcast31, 0xc>(acc, off >= lane - 31);
+    if (slot >= 0) {
+#pragma unroll
+      for (int r = 0; r < K; ++r)
+        part_out[(int64_t)slot * K + r] = out_scale ? acc[r] * scl[r] : acc[r];
     }
-    if (nrow > 1) {
-      const T v = dpp_move<kDppRowShr + 2, 0xf>(acc);
-      if (off >= 2) acc += v;
-    }
-    if (nrow > 2) {
-      const T v = dpp_move<kDppRowShr + 4, 0xf>(acc);
-      if (off >= 4) acc += v;
-    }
-    if (nrow > 3) {
-      const T v = dpp_move<kDppRowShr + 8, 0xf>(acc);
-      if (off >= 8) acc += v;
-    }
-    if ((info >> 16) & 1) {
-      const T v = dpp_move<kDppBcast15, 0xa>(acc);
-      if (off > (lane & 15)) acc += v;
-    }
-    if ((info >> 17) & 1) {
-      const T v = dpp_move<kDppBcast31, 0xc>(acc);
-      if (off >= lane - 31) acc += v;
-    }
-    if (slot >= 0) part_out[slot] = out_scale ? acc * scl : acc;
     return;
   }
-  acc += dpp_move<kDppRowShr + 1, 0xf>(acc);
-  acc += dpp_move<kDppRowShr + 2, 0xf>(acc);
-  acc += dpp_move<kDppRowShr + 4, 0xf>(acc);
-  acc += dpp_move<kDppRowShr + 8, 0xf>(acc);
-  acc += dpp_move<kDppBcast15, 0xa>(acc);
-  acc += dpp_move<kDppBcast31, 0xc>(acc);
+  dpp_add<kDppRowShr + 1, 0xf>(acc, true);
+  dpp_add<kDppRowShr + 2, 0xf>(acc, true);
+  dpp_add<kDppRowShr + 4, 0xf>(acc, true);
+  dpp_add<kDppRowShr + 8, 0xf>(acc, true);
+  dpp_add<kDppBcast15, 0xa>(acc, true);
+  dpp_add<kDppBcast31, 0xc>(acc, true);
   if (lane == 63) {
-    if (kind == kChunkLong)
-      part_out[slot] = out_scale ? acc * scl : acc;
-    else
-      piece_out[piece] = acc;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      if (kind == kChunkLong)
+        part_out[(int64_t)slot * K + r] = out_scale ? acc[r] * scl[r] : acc[r];
+      else
+        piece_out[(int64_t)piece * K + r] = acc[r];
+    }
   }
 }
 
-// Workgroup w of one X pass.
-template <typename T>
+// Workgroup w of one X pass over K interleaved vectors (K = 1: one vector).
+// The pass is skipped when all ndone flags done[i * dstride] are set.
+template <typename T, int K>
 __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>& xin,
                                            T* __restrict__ part_out, T* __restrict__ piece_out,
                                            const T* __restrict__ out_scale,
-                                           const int32_t* __restrict__ done, int w) {
-  if (done != nullptr && *done) return;
+                                           const int32_t* __restrict__ done, int ndone,
+                                           int dstride, int w) {
+  if (done != nullptr) {
+    bool all = true;
+    for (int i = 0; i < ndone; ++i) all = all && done[(int64_t)i * dstride] != 0;
+    if (all) return;
+  }
   extern __shared__ __align__(16) unsigned char smem[];
   T* xl = reinterpret_cast<T*>(smem);
 
@@ -320,41 +355,43 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   const int64_t g0 = (int64_t)panel * t.W;
   const int64_t rem = t.gdim - g0;
   const int wlen = (int)(rem < t.W ? rem : t.W);
-  // The panel of the gathered vector, assembled once per workgroup; slot W
-  // holds the zero the padding indices point to.  Eight loads in flight per
-  // thread before the LDS stores.
+  // The panel of the gathered vector(s), assembled once per workgroup; entry
+  // W holds the zeros the padding indices point to.  Eight loads in flight
+  // per thread before the LDS stores.
   constexpr int U = 8;
-  if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr) {
-    const T* src = xin.part + g0;
-    for (int j0 = threadIdx.x; j0 < wlen; j0 += kPThreads * U) {
+  if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr && xin.es == K) {
+    const T* src = xin.part + g0 * K;
+    const int cnt = wlen * K;
+    for (int j0 = threadIdx.x; j0 < cnt; j0 += kPThreads * U) {
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + u * kPThreads;
-        v[u] = (j < wlen) ? src[j] : T(0);
+        v[u] = (j < cnt) ? src[j] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + u * kPThreads;
-        if (j < wlen) xl[j] = v[u];
+        if (j < cnt) xl[j] = v[u];
       }
     }
   } else {
-    for (int j0 = threadIdx.x; j0 < wlen; j0 += kPThreads * U) {
+    const int cnt = wlen * K;
+    for (int j0 = threadIdx.x; j0 < cnt; j0 += kPThreads * U) {
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + u * kPThreads;
-        v[u] = (j < wlen) ? combine_at(xin, g0 + j) : T(0);
+        v[u] = (j < cnt) ? combine_at(xin, g0 + j / K, j % K) : T(0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + u * kPThreads;
-        if (j < wlen) xl[j] = v[u];
+        if (j < cnt) xl[j] = v[u];
       }
     }
   }
-  if (threadIdx.x == 0) xl[t.W] = T(0);
+  if (threadIdx.x < K) xl[(int64_t)t.W * K + threadIdx.x] = T(0);
   __syncthreads();
 
   while (c < c_end) {
@@ -375,12 +412,17 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       slot_n = out_slot(t, N, lane);
     }
     const int R = ck_windows(cinfo);
-    const T scl = (out_scale != nullptr && slot >= 0) ? out_scale[slot] : T(1);
+    T scl[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+      scl[r] = (out_scale != nullptr && slot >= 0) ? out_scale[(int64_t)slot * K + r] : T(1);
     // Slots this chunk leaves unused take the next chunk's windows now.
 #pragma unroll
     for (int s = 0; s < kPR; ++s)
       if (s >= R && ((LN.has >> s) & 1u)) load_window(t, nbase + LN.rel[s], sa[s], sb[s]);
-    T acc = T(0);
+    T acc[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) acc[r] = T(0);
     for (int kb = 0; kb < R; kb += kPR) {
 #pragma unroll
       for (int s = 0; s < kPR; ++s) {
@@ -388,7 +430,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
         if (k < R) {
           const bool have = (k < kPR) ? ((chas >> s) & 1u) != 0
                                       : (int64_t)k * kPC + lane * kPV < clen;
-          if (have) acc += gather_sum16(xl, sa[s], sb[s]);
+          if (have) gather_add16<T, K>(xl, sa[s], sb[s], acc);
           if (k + kPR < R) {
             const int64_t e = (int64_t)(k + kPR) * kPC + lane * kPV;
             if (e < clen) load_window(t, cbase + e, sa[s], sb[s]);
@@ -398,7 +440,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
         }
       }
     }
-    finish_chunk<T>(cinfo, csm, acc, slot, scl, cfirst, lane, part_out, piece_out, out_scale);
+    finish_chunk<T, K>(cinfo, csm, acc, slot, scl, cfirst, lane, part_out, piece_out, out_scale);
     cinfo = ninfo;
     cfirst = nfirst;
     cbase = nbase;
@@ -416,7 +458,7 @@ __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin
                                                      T* __restrict__ piece_out,
                                                      const T* __restrict__ out_scale,
                                                      const int32_t* __restrict__ done) {
-  panel_body<T>(t, xin, part_out, piece_out, out_scale, done, (int)blockIdx.x);
+  panel_body<T, 1>(t, xin, part_out, piece_out, out_scale, done, 1, 0, (int)blockIdx.x);
 }
 
 template <typename T>
@@ -424,7 +466,20 @@ __global__ __launch_bounds__(kPThreads) void k_panel_b(const PanelJob<T>* __rest
                                                        const int32_t* __restrict__ wg_job,
                                                        const int32_t* __restrict__ wg_local) {
   const PanelJob<T>& J = jobs[wg_job[blockIdx.x]];
-  panel_body<T>(J.t, J.x, J.part_out, J.piece_out, J.out_scale, J.done, wg_local[blockIdx.x]);
+  panel_body<T, 1>(J.t, J.x, J.part_out, J.piece_out, J.out_scale, J.done, 1, 0,
+                   wg_local[blockIdx.x]);
+}
+
+// One X pass over K interleaved vectors; skipped when the done flags of all
+// K chains are set.
+template <typename T, int K>
+__global__ __launch_bounds__(kPThreads) void k_panel_k(PanelPass t, Combine<T> xin,
+                                                       T* __restrict__ part_out,
+                                                       T* __restrict__ piece_out,
+                                                       const T* __restrict__ out_scale,
+                                                       const int32_t* __restrict__ done,
+                                                       int dstride) {
+  panel_body<T, K>(t, xin, part_out, piece_out, out_scale, done, K, dstride, (int)blockIdx.x);
 }
 
 static size_t pass_lds_bytes() { return (size_t)kPanelBytes; }
@@ -434,7 +489,13 @@ hipError_t setup_pass_kernels() {
   const void* fns[] = {reinterpret_cast<const void*>(&k_panel<float>),
                        reinterpret_cast<const void*>(&k_panel<double>),
                        reinterpret_cast<const void*>(&k_panel_b<float>),
-                       reinterpret_cast<const void*>(&k_panel_b<double>)};
+                       reinterpret_cast<const void*>(&k_panel_b<double>),
+                       reinterpret_cast<const void*>(&k_panel_k<float, 2>),
+                       reinterpret_cast<const void*>(&k_panel_k<double, 2>),
+                       reinterpret_cast<const void*>(&k_panel_k<float, 4>),
+                       reinterpret_cast<const void*>(&k_panel_k<double, 4>),
+                       reinterpret_cast<const void*>(&k_panel_k<float, 8>),
+                       reinterpret_cast<const void*>(&k_panel_k<double, 8>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -450,6 +511,37 @@ hipError_t launch_panel_pass_batched(const PanelJob<T>* jobs, const int32_t* wg_
                      wg_job, wg_local);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_panel_pass_k(int K, const PanelPass& t, const Combine<T>& x, T* part_out,
+                               T* piece_out, const T* out_scale, const int32_t* done,
+                               int dstride, hipStream_t st) {
+  if (t.nwg == 0) return hipSuccess;
+  const dim3 g(t.nwg), b(kPThreads);
+  const size_t lds = pass_lds_bytes();
+  switch (K) {
+    case 2:
+      hipLaunchKernelGGL((k_panel_k<T, 2>), g, b, lds, st, t, x, part_out, piece_out, out_scale,
+                         done, dstride);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_panel_k<T, 4>), g, b, lds, st, t, x, part_out, piece_out, out_scale,
+                         done, dstride);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_panel_k<T, 8>), g, b, lds, st, t, x, part_out, piece_out, out_scale,
+                         done, dstride);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_panel_pass_k<float>(int, const PanelPass&, const Combine<float>&,
+                                               float*, float*, const float*, const int32_t*, int,
+                                               hipStream_t);
+template hipError_t launch_panel_pass_k<double>(int, const PanelPass&, const Combine<double>&,
+                                                double*, double*, const double*, const int32_t*,
+                                                int, hipStream_t);
 template hipError_t launch_panel_pass_batched<float>(const PanelJob<float>*, const int32_t*,
                                                      const int32_t*, int32_t, hipStream_t);
 template hipError_t launch_panel_pass_batched<double>(const PanelJob<double>*, const int32_t*,
@@ -667,6 +759,28 @@ hipError_t launch_convert_from_f64(const double* in, int dtype, int64_t cnt, voi
   return hipGetLastError();
 }
 
+// dst[i K + r] = src[r][i] (r < nsrc; slots r >= nsrc untouched).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_interleave(VecPtrs src, int nsrc, int K, int64_t dim,
+                                                    T* dst) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= dim) return;
+  for (int r = 0; r < nsrc; ++r) dst[i * K + r] = (T)src.p[r][i];
+}
+
+template <typename T>
+hipError_t launch_interleave(const VecPtrs& src, int nsrc, int K, int64_t dim, T* dst,
+                             hipStream_t st) {
+  if (dim <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_interleave<T>), dim3((unsigned)((dim + kWG - 1) / kWG)), dim3(kWG), 0,
+                     st, src, nsrc, K, dim, dst);
+  return hipGetLastError();
+}
+template hipError_t launch_interleave<float>(const VecPtrs&, int, int, int64_t, float*,
+                                             hipStream_t);
+template hipError_t launch_interleave<double>(const VecPtrs&, int, int, int64_t, double*,
+                                              hipStream_t);
+
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_phi_finish(const T* qx, const double* d, const T* v,
                                                     int64_t p, T* out) {
@@ -710,7 +824,8 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
                                               const double* qx64, const double* d,
                                               const double* m, double* beta, double* r, T* s,
                                               int64_t p, double tol, int criterion,
-                                              int max_iter, double loop_factor, VGrid g) {
+                                              int max_iter, double loop_factor, VGrid g,
+                                              int es = 1) {
   if (mode == 1 && !restart_wanted(w.sc)) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // <r,Mr>, <r,r>, <b,Mb>, <b,b>
   for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
@@ -726,7 +841,7 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
     }
     if (mode != 2) {
       r[j] = rj;
-      s[j] = (T)zj;
+      s[j * es] = (T)zj;
     }
   }
   block_sum<4>(v);
@@ -773,13 +888,14 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
 
 template <typename T>
 __device__ __forceinline__ void cg_dot_body(VecWork w, const T* s, const Combine<T>& qsrc,
-                                            T* qx, const double* d, int64_t p, VGrid g) {
+                                            T* qx, const double* d, int64_t p, VGrid g,
+                                            int es = 1) {
   if (w.sc->done) return;
   double v[1] = {0.0};
   for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
     const T qj = combine_at(qsrc, j);
     qx[j] = qj;
-    const double sj = (double)s[j];
+    const double sj = (double)s[j * es];
     v[0] += sj * ((double)qj + d[j] * sj);
   }
   block_sum<1>(v);
@@ -802,12 +918,12 @@ __device__ __forceinline__ void cg_dot_body(VecWork w, const T* s, const Combine
 template <typename T>
 __device__ __forceinline__ void cg_update_body(VecWork w, const T* s, const T* qx,
                                                const double* d, const double* m, double* beta,
-                                               double* r, int64_t p, VGrid g) {
+                                               double* r, int64_t p, VGrid g, int es = 1) {
   if (w.sc->done) return;
   const double alpha = w.sc->alpha;
   double v[2] = {0.0, 0.0};  // <r, M^-1 r>, <r, r>
   for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
-    const double sj = (double)s[j];
+    const double sj = (double)s[j * es];
     const double qj = (double)qx[j] + d[j] * sj;
     beta[j] += alpha * sj;
     const double rj = r[j] - alpha * qj;
@@ -843,11 +959,11 @@ __device__ __forceinline__ void cg_update_body(VecWork w, const T* s, const T* q
 
 template <typename T>
 __device__ __forceinline__ void cg_direction_body(VecWork w, const double* m, const double* r,
-                                                  T* s, int64_t p, VGrid g) {
+                                                  T* s, int64_t p, VGrid g, int es = 1) {
   if (w.sc->done) return;
   const double bc = w.sc->betacg;
   for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG)
-    s[j] = (T)(m[j] * r[j] + bc * (double)s[j]);
+    s[j * es] = (T)(m[j] * r[j] + bc * (double)s[j * es]);
 }
 
 // ---- one chain ----
@@ -925,14 +1041,14 @@ __global__ __launch_bounds__(kWG) void k_cg_start_b(const VecJob<T>* jobs,
   VGrid g;
   const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
   cg_start_body<T>(J.w, mode, J.b, mode == 0 ? nullptr : J.qx64, J.d, J.m, J.beta, J.r, J.s, J.p,
-                   tol, criterion, max_iter > 0 ? max_iter : J.max_iter, loop_factor, g);
+                   tol, criterion, max_iter > 0 ? max_iter : J.max_iter, loop_factor, g, J.es);
 }
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_cg_dot_b(const VecJob<T>* jobs, const int32_t* blk_job,
                                                   const int32_t* blk_local) {
   VGrid g;
   const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
-  cg_dot_body<T>(J.w, J.s, J.qsrc, J.qx, J.d, J.p, g);
+  cg_dot_body<T>(J.w, J.s, J.qsrc, J.qx, J.d, J.p, g, J.es);
 }
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_cg_update_b(const VecJob<T>* jobs,
@@ -940,7 +1056,7 @@ __global__ __launch_bounds__(kWG) void k_cg_update_b(const VecJob<T>* jobs,
                                                      const int32_t* blk_local) {
   VGrid g;
   const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
-  cg_update_body<T>(J.w, J.s, J.qx, J.d, J.m, J.beta, J.r, J.p, g);
+  cg_update_body<T>(J.w, J.s, J.qx, J.d, J.m, J.beta, J.r, J.p, g, J.es);
 }
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_cg_direction_b(const VecJob<T>* jobs,
@@ -948,7 +1064,7 @@ __global__ __launch_bounds__(kWG) void k_cg_direction_b(const VecJob<T>* jobs,
                                                         const int32_t* blk_local) {
   VGrid g;
   const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
-  cg_direction_body<T>(J.w, J.m, J.r, J.s, J.p, g);
+  cg_direction_body<T>(J.w, J.m, J.r, J.s, J.p, g, J.es);
 }
 
 int32_t vec_blocks(int64_t p) { return (int32_t)red_grid(p); }

@@ -134,3 +134,68 @@ def test_batched_per_chain_status_and_repeat():
         ref, info = pk.draw(X, om, z, lam, tau, 1, c, 6, tol=1e-8)
         assert torch.equal(betas2[c], ref)
         assert infos2[c]["status"] == pk.OK
+
+
+# ---- shared design: K interleaved vectors per X pass ----
+
+def shared_setup(nchains, dtype, n=6000, p=3000, seed=31):
+    base = synth.scaled_problem(n, p, seed=seed, tau=2e-3, name="shared")
+    chains = synth.shared_x_chains(base, nchains, seed=seed + 1)
+    dt = torch.float64 if dtype == pk.F64 else torch.float32
+    B = pk.Batch.shared(base.n, base.p, base.row_ptr, base.col_idx, nchains, dtype=dtype)
+    vecs = [(torch.as_tensor(om, device=DEV).to(dt), torch.as_tensor(z, device=DEV).to(dt),
+             torch.as_tensor(lam, device=DEV).to(dt), tau) for om, z, lam, tau in chains]
+    return base, chains, B, vecs
+
+
+@pytest.mark.parametrize("nchains", [3, 8])
+def test_shared_solve_matches_cholesky(nchains):
+    base, chains, B, vecs = shared_setup(nchains, pk.F64)
+    say("shared solve", nchains, "chains, n", base.n, "p", base.p)
+    rng = np.random.default_rng(nchains)
+    bs = [rng.standard_normal(base.p) for _ in range(nchains)]
+    betas, infos = B.solve([v[0] for v in vecs], [v[2] for v in vecs], [v[3] for v in vecs],
+                           [torch.as_tensor(b, device=DEV) for b in bs], tol=1e-13)
+    Xs = R.csr_matrix(base.n, base.p, base.row_ptr, base.col_idx)
+    for c, (om, z, lam, tau) in enumerate(chains):
+        exact = R.solve_chol(R.phi_dense(Xs, om, lam, tau), bs[c])
+        e = float(np.linalg.norm(betas[c].cpu().numpy() - exact) / np.linalg.norm(exact))
+        say("chain", c, "iters", infos[c]["iters"], "rel err", e)
+        assert e <= 1e-10
+        assert infos[c]["status"] == pk.OK and infos[c]["resid_true"] <= 1.0
+
+
+def test_shared_draw_matches_single_chain_draws():
+    """Shared-design draws against the single-chain path on the same
+    arguments: both converge to the same beta (1e-10 at a tight tolerance),
+    with iteration counts within a plateau's reach."""
+    base, chains, B, vecs = shared_setup(5, pk.F64)
+    X = pk.Matrix.from_problem(base)
+    n = len(vecs)
+    betas, infos = B.draw([v[0] for v in vecs], [v[1] for v in vecs], [v[2] for v in vecs],
+                          [v[3] for v in vecs], [44] * n, list(range(n)), [2] * n, tol=1e-13)
+    for c, (om, z, lam, tau) in enumerate(vecs):
+        ref, info = pk.draw(X, om, z, lam, tau, 44, c, 2, tol=1e-13)
+        e = float(torch.linalg.norm(betas[c] - ref) / torch.linalg.norm(ref))
+        say("chain", c, "iters", infos[c]["iters"], info["iters"], "rel diff", e)
+        assert e <= 1e-10
+        assert abs(infos[c]["iters"] - info["iters"]) <= max(3, 0.05 * info["iters"])
+
+
+def test_shared_f32_matches_f64_oracle():
+    base, chains, B, vecs = shared_setup(4, pk.F32)
+    n = len(vecs)
+    betas, infos = B.draw([v[0] for v in vecs], [v[1] for v in vecs], [v[2] for v in vecs],
+                          [v[3] for v in vecs], [5] * n, list(range(n)), [0] * n, tol=1e-12)
+    Xs = R.csr_matrix(base.n, base.p, base.row_ptr, base.col_idx)
+    for c in range(n):
+        om = vecs[c][0].double().cpu().numpy()
+        z = vecs[c][1].double().cpu().numpy()
+        lam = vecs[c][2].double().cpu().numpy()
+        tau = vecs[c][3]
+        eta, delta = H.eta_delta(5, c, 0, base.n, base.p)
+        b = R.rhs_b(Xs, om, z, lam, tau, eta, delta)
+        exact = R.solve_chol(R.phi_dense(Xs, om, lam, tau), b)
+        e = float(np.linalg.norm(betas[c].double().cpu().numpy() - exact) / np.linalg.norm(exact))
+        say("chain", c, "iters", infos[c]["iters"], "+", infos[c]["refine_iters"], "rel err", e)
+        assert e <= 1e-5
