@@ -15,6 +15,8 @@ and the CPU oracle timed on this host as a baseline.
 
 ``--copy-calibration`` instead times a plain 512 MiB device copy: its
 FETCH_SIZE / WRITE_SIZE counters calibrate the pass kernel's counters.
+``--form shared`` measures 8 chains on the n = 1e5, p = 2e4 design (each
+with its own omega, z, lambda, tau and stream), every X pass serving all 8.
 ``--form batched`` instead measures the batched form: 32 independent chains
 with n log-uniform in [2e4, 2e5], p in [5e3, 4e4], tau in [1e-4, 1e-2] (the
 same column law), one batched draw of all chains per step, against the same
@@ -68,8 +70,9 @@ def parse():
                     help="oracle CG iterations in the bounded CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 512 MiB device copy (counter calibration)")
-    ap.add_argument("--form", choices=("single", "batched"), default="single",
-                    help="single: the n=1e5 p=2e4 draw (default); batched: 32 uneven chains")
+    ap.add_argument("--form", choices=("single", "batched", "shared"), default="single",
+                    help="single: the n=1e5 p=2e4 draw (default); batched: 32 uneven chains; "
+                         "shared: 8 chains on the n=1e5 p=2e4 design")
     return ap.parse_args()
 
 
@@ -274,6 +277,72 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_shared(args):
+    import torch
+
+    import paper_1810_12437_amd as pk
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    print("[bench] generating the n=1e5 p=2e4 design and 8 chains ...", file=sys.stderr,
+          flush=True)
+    P = synth.make_problem("c1")
+    C = 8
+    chains = synth.shared_x_chains(P, C, seed=1815)
+    X = pk.Matrix.from_problem(P)
+    out = {
+        "metric": "shared-design chain-draws/sec, 8 chains, n=1e5 p=2e4",
+        "unit": "chain-draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+        "config": {
+            "workload": ("8 chains on one n=1e5 p=2e4 binary X (column densities log-uniform "
+                         "[1e-4, 0.2]); per-chain omega, z, lambda, tau = 1e-3 x exp(U[-1/2, 1/2]); "
+                         f"relative preconditioned residual {args.tol:g}"),
+            "chains": C, "nnz": P.nnz, "tol": args.tol, "seed": SEED,
+        },
+    }
+    forms = {}
+    for name, dtype, dt in (("f64", pk.F64, torch.float64), ("f32", pk.F32, torch.float32)):
+        if name == "f32" and args.no_f32:
+            continue
+        t0 = time.perf_counter()
+        B = pk.Batch.shared(P.n, P.p, P.row_ptr, P.col_idx, C, dtype=dtype)
+        t_build = time.perf_counter() - t0
+        om = [torch.as_tensor(c[0], device="cuda").to(dt) for c in chains]
+        zz = [torch.as_tensor(c[1], device="cuda").to(dt) for c in chains]
+        la = [torch.as_tensor(c[2], device="cuda").to(dt) for c in chains]
+        ta = [c[3] for c in chains]
+        for w in range(args.warmup):
+            B.draw(om, zz, la, ta, [SEED] * C, list(range(C)), [1000 + w] * C, tol=args.tol)
+        torch.cuda.synchronize()
+        print(f"[bench] timing shared {name} ({args.steps} steps)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        iters = []
+        for k in range(args.steps):
+            _, infos = B.draw(om, zz, la, ta, [SEED] * C, list(range(C)), [k] * C, tol=args.tol)
+            iters.append([i["iters"] + i["refine_iters"] for i in infos])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        it = np.array(iters, dtype=np.float64)
+        f = {"chain_draws_per_s": C * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+             "cg_iters_mean": float(it.mean()), "cg_iters_max": float(it.max()),
+             "handle_build_s": t_build}
+        t0 = time.perf_counter()
+        for c in range(C):
+            pk.draw(X, om[c], zz[c], la[c], ta[c], SEED, c, 0, tol=args.tol)
+        torch.cuda.synchronize()
+        f["single_chain_path_chain_draws_per_s"] = C / (time.perf_counter() - t0)
+        f["speedup_vs_single_chain_path"] = (f["chain_draws_per_s"] /
+                                             f["single_chain_path_chain_draws_per_s"])
+        forms[name] = f
+        B.close()
+    out["value"] = forms["f64"]["chain_draws_per_s"]
+    out["ms_per_step"] = forms["f64"]["ms_per_step"]
+    out["dtype"] = "f64"
+    out["forms"] = forms
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -286,6 +355,9 @@ def main():
         return
     if args.form == "batched":
         run_batched(args)
+        return
+    if args.form == "shared":
+        run_shared(args)
         return
     import torch
 

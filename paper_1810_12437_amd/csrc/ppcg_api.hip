@@ -26,11 +26,12 @@ namespace {
 // when the rows fit one panel, else by the consumer).
 template <typename T>
 hipError_t row_pass(ppcg_matrix* X, const Combine<T>& x, const T* omega, const int32_t* done,
-                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                    const DirIn<T>* dir = nullptr, int parity = 0) {
   Orient& o = X->rows[prec_index<T>()];
   return launch_panel_pass<T>(o.pass, x, reinterpret_cast<T*>(o.part),
                               reinterpret_cast<T*>(o.piece), rows_direct(o) ? omega : nullptr,
-                              done, st, ev0, ev1);
+                              done, st, ev0, ev1, dir, nullptr, parity);
 }
 
 // The column pass's view of u.
@@ -43,11 +44,13 @@ Combine<T> u_view(ppcg_matrix* X, const T* omega) {
 // Column pass: segment sums of X^T u, u from the row pass (or y if given).
 template <typename T>
 hipError_t col_pass(ppcg_matrix* X, const T* omega, const Combine<T>* y, const int32_t* done,
-                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                    const DotOut<T>* dot = nullptr, int parity = 0) {
   Orient& o = X->cols[prec_index<T>()];
   const Combine<T> u = y ? *y : u_view<T>(X, omega);
   return launch_panel_pass<T>(o.pass, u, reinterpret_cast<T*>(o.part),
-                              reinterpret_cast<T*>(o.piece), nullptr, done, st, ev0, ev1);
+                              reinterpret_cast<T*>(o.piece), nullptr, done, st, ev0, ev1,
+                              nullptr, dot, parity);
 }
 
 // FP64 product part qx64 = X^T (omega .* (X x)).
@@ -63,13 +66,11 @@ template <typename T>
 struct Bufs;
 template <>
 struct Bufs<double> {
-  static double* s(ppcg_matrix* X) { return X->s64; }
-  static double* qx(ppcg_matrix* X) { return X->qx64; }
+  static double* s(ppcg_matrix* X) { return X->s64; }  // two buffers of p
 };
 template <>
 struct Bufs<float> {
   static float* s(ppcg_matrix* X) { return X->s32; }
-  static float* qx(ppcg_matrix* X) { return X->qx32; }
 };
 
 int sync_scal(ppcg_matrix* X, hipStream_t st) {
@@ -81,12 +82,25 @@ int sync_scal(ppcg_matrix* X, hipStream_t st) {
 // Runs CG iterations until the device reports done; returns via h_sc.
 template <typename T>
 int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t st) {
+  const int ti = prec_index<T>();
   T* s = Bufs<T>::s(X);
-  T* qx = Bufs<T>::qx(X);
   const int32_t* done = &X->sc->done;
   const VecWork w = vw(X);
-  const Combine<T> svec = comb_vec<T>(s);
-  const Combine<T> qsrc = comb_out<T>(X->cols[prec_index<T>()], nullptr);
+  const Combine<T> none{};
+  const Combine<T> qsrc = comb_out<T>(X->cols[ti], nullptr);
+  DirIn<T> dir{};
+  dir.z = X->z64;
+  dir.s = s;
+  dir.sstride = X->p;
+  dir.d = X->d;
+  dir.sc = X->sc;
+  dir.scstride = 0;
+  dir.p1 = X->p1[ti];
+  DotOut<T> dot{};
+  dot.s = s;
+  dot.sstride = X->p;
+  dot.p2 = X->p2[ti];
+  const int32_t n1 = X->rows[ti].pass.nwg, n2 = X->cols[ti].pass.nwg;
   const bool prof = X->profile != 0;
   if (prof && (int)X->ev.size() < 4 * o.check_every) {
     while ((int)X->ev.size() < 4 * o.check_every) {
@@ -95,18 +109,19 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
       X->ev.push_back(e);
     }
   }
+  int parity = 0;
   for (;;) {
     int32_t active_before = 0;
     if (prof) active_before = X->h_sc->done ? 0 : 1;
-    for (int i = 0; i < o.check_every; ++i) {
+    for (int i = 0; i < o.check_every; ++i, parity ^= 1) {
       hipEvent_t* e = prof ? &X->ev[4 * i] : nullptr;
-      PPCG_TRY_HIP(row_pass<T>(X, svec, omegaT, done, st, e ? e[0] : nullptr,
-                               e ? e[1] : nullptr));
+      // row pass forms s (buffer 1 - parity) from z and the old s
+      PPCG_TRY_HIP(row_pass<T>(X, none, omegaT, done, st, e ? e[0] : nullptr,
+                               e ? e[1] : nullptr, &dir, parity));
       PPCG_TRY_HIP(col_pass<T>(X, omegaT, nullptr, done, st, e ? e[2] : nullptr,
-                               e ? e[3] : nullptr));
-      PPCG_TRY_HIP(launch_cg_dot<T>(w, s, qsrc, qx, X->d, X->p, st));
-      PPCG_TRY_HIP(launch_cg_update<T>(w, s, qx, X->d, X->m, X->beta64, X->r64, X->p, st));
-      PPCG_TRY_HIP(launch_cg_direction<T>(w, X->m, X->r64, s, X->p, st));
+                               e ? e[3] : nullptr, &dot, parity));
+      PPCG_TRY_HIP(launch_cg_step<T>(w, s, X->p, parity, qsrc, X->d, X->m, X->beta64, X->r64,
+                                     X->z64, X->p1[ti], n1, X->p2[ti], n2, X->p, st));
     }
     const int32_t it0 = prof ? X->h_sc->iters : 0;
     PPCG_TRY_HIP(hipMemcpyAsync(X->h_sc, X->sc, sizeof(DevScal), hipMemcpyDeviceToHost, st));
@@ -134,7 +149,6 @@ template <typename T>
 int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have_beta0,
                const ppcg_options& o, ppcg_info* info, hipStream_t st) {
   const VecWork w = vw(X);
-  T* s = Bufs<T>::s(X);
   const double* qx0 = nullptr;
   if (have_beta0) {
     int rc = fp64_phi_parts(X, X->beta64, omega64, st);
@@ -146,8 +160,8 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
   // products, and the margin lets the FP64 check pass without a replacement.
   const double loop_factor =
       o.loop_factor > 0.0 ? o.loop_factor : ((sizeof(T) == 4) ? 0.5 : 1.0);
-  PPCG_TRY_HIP(launch_cg_start<T>(w, 0, X->b64, qx0, X->d, X->m, X->beta64, X->r64, s, X->p,
-                                  o.tol, o.criterion, o.max_iter, loop_factor, st));
+  PPCG_TRY_HIP(launch_cg_start(w, 0, X->b64, qx0, X->d, X->m, X->beta64, X->r64, X->z64, X->p,
+                             o.tol, o.criterion, o.max_iter, loop_factor, st));
   if (X->profile) {
     int rc0 = sync_scal(X, st);
     if (rc0) return rc0;
@@ -165,8 +179,8 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
   if (o.true_resid || o.refine) {
     rc = fp64_phi_parts(X, X->beta64, omega64, st);
     if (rc) return rc;
-    PPCG_TRY_HIP(launch_cg_start<T>(w, 2, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
-                                    X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
+    PPCG_TRY_HIP(launch_cg_start(w, 2, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, X->z64,
+                             X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
     rc = sync_scal(X, st);
     if (rc) return rc;
     inf.resid_true = ratio(X->h_sc->true_meas, X->h_sc->thresh2);
@@ -175,8 +189,8 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
     if (o.refine && inf.status == PPCG_OK && X->h_sc->true_meas > X->h_sc->thresh2) {
       // One refinement: restart CG from the FP64 true residual
       // b - Phi beta (qx64 holds the product part of the current beta).
-      PPCG_TRY_HIP(launch_cg_start<T>(w, 1, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
-                                      X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
+      PPCG_TRY_HIP(launch_cg_start(w, 1, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, X->z64,
+                             X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
       if (X->profile) {
         rc = sync_scal(X, st);
         if (rc) return rc;
@@ -189,8 +203,8 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
       inf.resid_rec = ratio(X->h_sc->meas, X->h_sc->thresh2);
       rc = fp64_phi_parts(X, X->beta64, omega64, st);
       if (rc) return rc;
-      PPCG_TRY_HIP(launch_cg_start<T>(w, 2, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, s,
-                                      X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
+      PPCG_TRY_HIP(launch_cg_start(w, 2, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, X->z64,
+                             X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
       rc = sync_scal(X, st);
       if (rc) return rc;
       inf.resid_true = ratio(X->h_sc->true_meas, X->h_sc->thresh2);
@@ -328,8 +342,13 @@ int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
               X->mem.alloc(&X->omega64, N) == hipSuccess &&
               X->mem.alloc(&X->d, P) == hipSuccess && X->mem.alloc(&X->m, P) == hipSuccess &&
               X->mem.alloc(&X->b64, P) == hipSuccess && X->mem.alloc(&X->beta64, P) == hipSuccess &&
-              X->mem.alloc(&X->r64, P) == hipSuccess && X->mem.alloc(&X->s64, P) == hipSuccess &&
-              X->mem.alloc(&X->qx32, P) == hipSuccess && X->mem.alloc(&X->s32, P) == hipSuccess &&
+              X->mem.alloc(&X->r64, P) == hipSuccess && X->mem.alloc(&X->s64, 2 * P) == hipSuccess &&
+              X->mem.alloc(&X->qx32, P) == hipSuccess && X->mem.alloc(&X->s32, 2 * P) == hipSuccess &&
+              X->mem.alloc(&X->z64, P) == hipSuccess &&
+              X->mem.alloc(&X->p1[0], (size_t)X->rows[0].pass.nwg) == hipSuccess &&
+              X->mem.alloc(&X->p2[0], (size_t)X->cols[0].pass.nwg) == hipSuccess &&
+              X->mem.alloc(&X->p1[1], (size_t)X->rows[1].pass.nwg) == hipSuccess &&
+              X->mem.alloc(&X->p2[1], (size_t)X->cols[1].pass.nwg) == hipSuccess &&
               X->mem.alloc(&X->part, (size_t)kMaxRedBlocks * 4) == hipSuccess &&
               X->mem.alloc(&X->sc, 1) == hipSuccess;
     if (!ok) return fail(PPCG_ENOMEM);

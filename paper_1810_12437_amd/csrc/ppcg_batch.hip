@@ -21,7 +21,9 @@ struct ChainBufs {
   int64_t n = 0, p = 0;
   double *y64 = nullptr, *omega64 = nullptr, *d = nullptr, *m = nullptr, *b64 = nullptr,
          *beta64 = nullptr, *r64 = nullptr, *qx64 = nullptr, *red = nullptr;
-  void *omegaT = nullptr, *s = nullptr, *qx = nullptr;  // the batch's dtype
+  void *omegaT = nullptr, *s = nullptr, *qx = nullptr;  // the batch's dtype (s: 2 x p)
+  double* z = nullptr;                                  // M^-1 r for the next row pass
+  double *p1 = nullptr, *p2 = nullptr;                  // the passes' workgroup partials
   void *rpart[2] = {}, *rpiece[2] = {}, *cpart[2] = {}, *cpiece[2] = {};  // per table precision
 };
 
@@ -103,6 +105,8 @@ struct ppcg_batch {
   int64_t n = 0, p = 0;
   ppcg::Orient srows[2], scols[2];  // K-wide tables: [0] FP64, [1] FP32
   double *y_K = nullptr, *om64_K = nullptr, *beta_K = nullptr;  // [dim][K]
+  double *z_K = nullptr, *d_K = nullptr;                         // [p][K]
+  double *p1_K = nullptr, *p2_K = nullptr;                       // [nwg][K]
   void *omT_K = nullptr, *s_K = nullptr;                         // [dim][K], dtype
 };
 
@@ -158,6 +162,23 @@ int build_pass_jobs(ppcg_batch* B, int kind) {
         break;
     }
     J.done = (kind == kJobRow || kind == kJobCol) ? &B->sc[c].done : nullptr;
+    // what the loop's passes read besides the plain pass
+    if (J.t.nwg > 0 && (J.t.wg_s0 == nullptr || J.t.wg_s1 == nullptr || J.t.out_dim <= 0))
+      return PPCG_EHIP;
+    if (kind == kJobRow) {
+      // the loop's row pass forms the direction s from z (DirIn)
+      J.x = Combine<T>{};
+      J.dir.z = C.z;
+      J.dir.s = reinterpret_cast<T*>(C.s);
+      J.dir.sstride = C.p;
+      J.dir.d = C.d;
+      J.dir.sc = &B->sc[c];
+      J.dir.p1 = C.p1;
+    } else if (kind == kJobCol) {
+      J.dot.s = reinterpret_cast<const T*>(C.s);
+      J.dot.sstride = C.p;
+      J.dot.p2 = C.p2;
+    }
     for (int32_t w = 0; w < J.t.nwg; ++w) {
       wj.push_back(c);
       wl.push_back(w);
@@ -191,7 +212,17 @@ int build_vec_jobs(ppcg_batch* B) {
     J = VecJob<T>{};
     J.w = VecWork{C.red, &B->sc[c]};
     J.s = reinterpret_cast<T*>(C.s);
-    if (!B->shared) J.qsrc = comb_buf<T>(C.X->cols[ti], C.cpart[ti], C.cpiece[ti], nullptr);
+    J.sstride = C.p;
+    J.z = C.z;
+    J.zes = 1;
+    J.p1 = C.p1;
+    J.p2 = C.p2;
+    J.pstride = 1;
+    if (!B->shared) {
+      J.qsrc = comb_buf<T>(C.X->cols[ti], C.cpart[ti], C.cpiece[ti], nullptr);
+      J.n1 = C.X->rows[ti].pass.nwg;
+      J.n2 = C.X->cols[ti].pass.nwg;
+    }
     J.qx = reinterpret_cast<T*>(C.qx);
     J.b = C.b64;
     J.qx64 = C.qx64;
@@ -204,9 +235,18 @@ int build_vec_jobs(ppcg_batch* B) {
     J.nblk = vec_blocks(C.p);
     J.es = 1;
     if (B->shared) {
-      // s interleaved over the chains; q from the K-wide column pass
+      // s, z and the pass partials interleaved over the chains; q from the
+      // K-wide column pass
       J.s = reinterpret_cast<T*>(B->s_K) + c;
+      J.sstride = B->p * B->K;
       J.es = B->K;
+      J.z = B->z_K + c;
+      J.zes = B->K;
+      J.p1 = B->p1_K + c;
+      J.p2 = B->p2_K + c;
+      J.pstride = B->K;
+      J.n1 = B->srows[ti].pass.nwg;
+      J.n2 = B->scols[ti].pass.nwg;
       J.qsrc = comb_k<T>(B->scols[ti], B->K, c, nullptr);
     }
     for (int32_t b = 0; b < J.nblk; ++b) {
@@ -242,14 +282,19 @@ int alloc_chain(ppcg_batch* B, ChainBufs& C) {
   PPCG_TRY_ALLOC(B->mem.alloc(&C.r64, P));
   PPCG_TRY_ALLOC(B->mem.alloc(&C.qx64, P));
   PPCG_TRY_ALLOC(B->mem.alloc(&C.red, (size_t)kMaxRedBlocks * 4));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.z, P));
   PPCG_TRY_ALLOC(B->mem.alloc(&qx, P * ts));
   C.qx = qx;
   if (B->shared) {
     C.omegaT = C.omega64;  // FP64 copy; the K-wide passes read omT_K
     return PPCG_OK;
   }
-  PPCG_TRY_ALLOC(B->mem.alloc(&s, P * ts));
+  PPCG_TRY_ALLOC(B->mem.alloc(&s, 2 * P * ts));
+  PPCG_TRY_HIP(hipMemset(s, 0, 2 * P * ts));
   C.s = s;
+  const int ti = B->dtype == PPCG_F64 ? 0 : 1;
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.p1, (size_t)C.X->rows[ti].pass.nwg));
+  PPCG_TRY_ALLOC(B->mem.alloc(&C.p2, (size_t)C.X->cols[ti].pass.nwg));
   if (B->dtype == PPCG_F64) {
     C.omegaT = C.omega64;
   } else {
@@ -324,23 +369,34 @@ int set_loop_chains(ppcg_batch* B, const std::vector<char>& act) {
 // Shared form: row pass u = omega .* (X s) and column pass X^T u for the K
 // interleaved vectors of the loop's dtype, skipped once every chain is done.
 template <typename T>
-int shared_loop_passes(ppcg_batch* B, hipStream_t st) {
+int shared_loop_passes(ppcg_batch* B, int parity, hipStream_t st) {
   const int ti = prec_index<T>();
   const Orient& ro = B->srows[ti];
   const Orient& co = B->scols[ti];
   const T* om = reinterpret_cast<const T*>(B->omT_K);
   const int dstride = (int)(sizeof(DevScal) / sizeof(int32_t));
-  PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, ro.pass, comb_all<T>(reinterpret_cast<T*>(B->s_K),
-                                                                 B->K),
+  DirIn<T> dir{};
+  dir.z = B->z_K;
+  dir.s = reinterpret_cast<T*>(B->s_K);
+  dir.sstride = B->p * B->K;
+  dir.d = B->d_K;
+  dir.sc = B->sc;
+  dir.scstride = 1;
+  dir.p1 = B->p1_K;
+  DotOut<T> dot{};
+  dot.s = reinterpret_cast<const T*>(B->s_K);
+  dot.sstride = B->p * B->K;
+  dot.p2 = B->p2_K;
+  PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, ro.pass, Combine<T>{},
                                       reinterpret_cast<T*>(ro.part),
                                       reinterpret_cast<T*>(ro.piece),
                                       rows_direct(ro) ? om : nullptr, &B->sc[0].done, dstride,
-                                      st));
+                                      st, &dir, nullptr, parity));
   PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, co.pass,
                                       comb_k<T>(ro, B->K, 0, rows_direct(ro) ? nullptr : om),
                                       reinterpret_cast<T*>(co.part),
                                       reinterpret_cast<T*>(co.piece), nullptr, &B->sc[0].done,
-                                      dstride, st));
+                                      dstride, st, nullptr, &dot, parity));
   return PPCG_OK;
 }
 
@@ -359,6 +415,7 @@ int interleave(ppcg_batch* B, double* const* src_of_chain, int64_t dim, T* dst,
 template <typename T>
 int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
   std::vector<char> act(B->nch);
+  int parity = 0;
   for (;;) {
     PPCG_TRY_HIP(hipMemcpyAsync(B->h_sc, B->sc, sizeof(DevScal) * B->nch,
                                 hipMemcpyDeviceToHost, st));
@@ -371,20 +428,20 @@ int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
     if (!any) return PPCG_OK;
     int rc = set_loop_chains(B, act);
     if (rc) return rc;
-    for (int i = 0; i < o.check_every; ++i) {
+    for (int i = 0; i < o.check_every; ++i, parity ^= 1) {
       if (B->shared) {
-        if ((rc = shared_loop_passes<T>(B, st))) return rc;
+        if ((rc = shared_loop_passes<T>(B, parity, st))) return rc;
       } else {
         PPCG_TRY_HIP(launch_panel_pass_batched<T>(
             reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobRow]), B->lp_wg_job[kJobRow],
-            B->lp_wg_local[kJobRow], B->lp_nwg[kJobRow], st));
+            B->lp_wg_local[kJobRow], B->lp_nwg[kJobRow], kPassDir, parity, st));
         PPCG_TRY_HIP(launch_panel_pass_batched<T>(
             reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobCol]), B->lp_wg_job[kJobCol],
-            B->lp_wg_local[kJobCol], B->lp_nwg[kJobCol], st));
+            B->lp_wg_local[kJobCol], B->lp_nwg[kJobCol], kPassDot, parity, st));
       }
-      PPCG_TRY_HIP(launch_cg_iteration_batched<T>(reinterpret_cast<const VecJob<T>*>(B->vjobs),
-                                                  B->lp_blk_job, B->lp_blk_local, B->lp_nblk,
-                                                  st));
+      PPCG_TRY_HIP(launch_cg_step_batched<T>(reinterpret_cast<const VecJob<T>*>(B->vjobs),
+                                             B->lp_blk_job, B->lp_blk_local, B->lp_nblk, parity,
+                                             st));
     }
   }
 }
@@ -414,10 +471,10 @@ int fp64_parts_batched(ppcg_batch* B, hipStream_t st) {
   }
   PPCG_TRY_HIP(launch_panel_pass_batched<double>(
       reinterpret_cast<const PanelJob<double>*>(B->jobs[kJobRow64]), B->wg_job[kJobRow64],
-      B->wg_local[kJobRow64], B->nwg[kJobRow64], st));
+      B->wg_local[kJobRow64], B->nwg[kJobRow64], kPassPlain, 0, st));
   PPCG_TRY_HIP(launch_panel_pass_batched<double>(
       reinterpret_cast<const PanelJob<double>*>(B->jobs[kJobCol64]), B->wg_job[kJobCol64],
-      B->wg_local[kJobCol64], B->nwg[kJobCol64], st));
+      B->wg_local[kJobCol64], B->nwg[kJobCol64], kPassPlain, 0, st));
   for (const ChainBufs& C : B->ch)
     PPCG_TRY_HIP(launch_combine<double, double>(
         comb_buf<double>(C.X->cols[0], C.cpart[0], C.cpiece[0], nullptr), C.p, C.qx64, st));
@@ -458,6 +515,9 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
       y[c] = B->ch[c].y64;
     }
     if ((rc = interleave<double>(B, om.data(), B->n, B->om64_K, st))) return rc;
+    std::vector<double*> dd(B->nch);
+    for (int32_t c = 0; c < B->nch; ++c) dd[c] = B->ch[c].d;
+    if ((rc = interleave<double>(B, dd.data(), B->p, B->d_K, st))) return rc;
     if (dt == PPCG_F32 &&
         (rc = interleave<float>(B, om.data(), B->n, reinterpret_cast<float*>(B->omT_K), st)))
       return rc;
@@ -480,7 +540,7 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
   } else if (draw) {
     PPCG_TRY_HIP(launch_panel_pass_batched<double>(
         reinterpret_cast<const PanelJob<double>*>(B->jobs[kJobRhs64]), B->wg_job[kJobRhs64],
-        B->wg_local[kJobRhs64], B->nwg[kJobRhs64], st));
+        B->wg_local[kJobRhs64], B->nwg[kJobRhs64], kPassPlain, 0, st));
     for (int32_t c = 0; c < B->nch; ++c) {
       const ChainBufs& C = B->ch[c];
       const ppcg_chain& A = chains[c];
@@ -719,10 +779,15 @@ int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64
     }
     const size_t ts = dtype == PPCG_F64 ? 8 : 4;
     unsigned char *omT = nullptr, *sK = nullptr;
+    const int tl = dtype == PPCG_F64 ? 0 : 1;
     if (B->mem.alloc(&B->y_K, (size_t)n * K) != hipSuccess ||
         B->mem.alloc(&B->om64_K, (size_t)n * K) != hipSuccess ||
         B->mem.alloc(&B->beta_K, (size_t)p * K) != hipSuccess ||
-        B->mem.alloc(&sK, (size_t)p * K * ts) != hipSuccess)
+        B->mem.alloc(&B->z_K, (size_t)p * K) != hipSuccess ||
+        B->mem.alloc(&B->d_K, (size_t)p * K) != hipSuccess ||
+        B->mem.alloc(&B->p1_K, (size_t)B->srows[tl].pass.nwg * K) != hipSuccess ||
+        B->mem.alloc(&B->p2_K, (size_t)B->scols[tl].pass.nwg * K) != hipSuccess ||
+        B->mem.alloc(&sK, 2 * (size_t)p * K * ts) != hipSuccess)
       return fail(PPCG_ENOMEM);
     if (dtype == PPCG_F32) {
       if (B->mem.alloc(&omT, (size_t)n * K * ts) != hipSuccess) return fail(PPCG_ENOMEM);
@@ -735,7 +800,9 @@ int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64
     if (hipMemset(B->y_K, 0, (size_t)n * K * 8) != hipSuccess ||
         hipMemset(B->om64_K, 0, (size_t)n * K * 8) != hipSuccess ||
         hipMemset(B->beta_K, 0, (size_t)p * K * 8) != hipSuccess ||
-        hipMemset(sK, 0, (size_t)p * K * ts) != hipSuccess ||
+        hipMemset(B->z_K, 0, (size_t)p * K * 8) != hipSuccess ||
+        hipMemset(B->d_K, 0, (size_t)p * K * 8) != hipSuccess ||
+        hipMemset(sK, 0, 2 * (size_t)p * K * ts) != hipSuccess ||
         (omT && hipMemset(omT, 0, (size_t)n * K * ts) != hipSuccess))
       return fail(PPCG_EHIP);
     // one scalar block per vector slot; slots beyond the chains stay done

@@ -59,7 +59,9 @@ struct ppcg_matrix {
   double *qx64 = nullptr, *y64 = nullptr, *omega64 = nullptr;
   double *d = nullptr, *m = nullptr, *b64 = nullptr, *beta64 = nullptr, *r64 = nullptr,
          *s64 = nullptr;
-  float *qx32 = nullptr, *s32 = nullptr;
+  float *qx32 = nullptr, *s32 = nullptr;  // s64, s32: two direction buffers of p each
+  double* z64 = nullptr;                  // M^-1 r for the next row pass
+  double *p1[2] = {}, *p2[2] = {};        // workgroup partials of the passes, per table
   double* part = nullptr;
   ppcg::DevScal* sc = nullptr;
   ppcg::DevScal* h_sc = nullptr;  // pinned host mirror

@@ -18,12 +18,15 @@ int upload_orient(DevBuf& mem, const PanelBuild& B, int elem, int K, Orient& o) 
   if ((rc = upload_vec(mem, B.seg_out, &t.seg_out, &by))) return rc;
   if ((rc = upload_vec(mem, B.wg_panel, &t.wg_panel, &by))) return rc;
   if ((rc = upload_vec(mem, B.wave_c, &t.wave_c, &by))) return rc;
+  if ((rc = upload_vec(mem, B.wg_s0, &t.wg_s0, &by))) return rc;
+  if ((rc = upload_vec(mem, B.wg_s1, &t.wg_s1, &by))) return rc;
   if (!B.sp_off.empty()) {
     if ((rc = upload_vec(mem, B.sp_off, &o.sp_off, &by))) return rc;
     if ((rc = upload_vec(mem, B.sp_c0, &o.sp_c0, &by))) return rc;
     if ((rc = upload_vec(mem, B.sp_c1, &o.sp_c1, &by))) return rc;
   }
   t.gdim = B.gdim;
+  t.out_dim = B.out_dim;
   t.W = B.W;
   t.nwg = (int32_t)B.wg_panel.size();
   t.nchunks = (int32_t)B.chunks.size();

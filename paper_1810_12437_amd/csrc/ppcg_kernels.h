@@ -9,6 +9,9 @@
 namespace ppcg {
 
 constexpr int kWG = 256;            // threads per workgroup (4 wavefronts of 64)
+// Variants of the X pass: plain, the CG loop's row pass (DirIn), the CG
+// loop's column pass (DotOut).
+enum { kPassPlain = 0, kPassDir = 1, kPassDot = 2 };
 constexpr int kMaxRedBlocks = 1024; // max workgroups of a p-vector phase
 
 // ---- X passes ----
@@ -29,7 +32,10 @@ struct PanelPass {
   const int32_t* seg_out;   // [entries] output slot = panel * out_dim + segment id
   const int32_t* wg_panel;  // [nwg]
   const int32_t* wave_c;    // [kPWaves * nwg + 1]
+  const int32_t* wg_s0;     // [nwg] gathered entries [s0, s1) the workgroup owns
+  const int32_t* wg_s1;
   int64_t gdim;             // gathered dimension (p for rows, n for columns)
+  int64_t out_dim;          // outputs per panel
   int32_t W;                // panel width
   int32_t nwg;
   int32_t nchunks;
@@ -83,6 +89,34 @@ struct VecWork {
   DevScal* sc;
 };
 
+// Row pass of the CG loop: the panel being gathered is the new direction
+// s = z + (rho'/rho) s_old (z = M^-1 r, the ratio from each vector's scalars),
+// formed while the panel is assembled; the workgroup writes its entries
+// [wg_s0, wg_s1) of s and its part of <s, d s> (p1[w K + r]).  The two s
+// buffers are s and s + sstride (old / new by the launch's parity).  All
+// vectors are [dim][K] (K = 1: plain vectors).
+template <typename T>
+struct DirIn {
+  const double* z;
+  T* s;
+  int64_t sstride;
+  const double* d;
+  const DevScal* sc;  // vector r's scalars at sc + r * scstride
+  int32_t scstride;
+  int32_t pad;
+  double* p1;
+};
+
+// Column pass of the CG loop: each workgroup also sums s_j times every
+// output (segment sum) it writes for column j, per vector (p2[w K + r]);
+// s is the new direction (the buffer the row pass wrote).
+template <typename T>
+struct DotOut {
+  const T* s;
+  int64_t sstride;
+  double* p2;
+};
+
 // ---- many chains in one launch ----
 // One chain's X pass in a batched launch.
 template <typename T>
@@ -93,13 +127,20 @@ struct PanelJob {
   T* piece_out;
   const T* out_scale;
   const int32_t* done;
+  DirIn<T> dir;
+  DotOut<T> dot;
 };
 
 // One chain's p-vector state in a batched launch (nblk blocks).
 template <typename T>
 struct VecJob {
   VecWork w;
-  T* s;
+  T* s;              // direction buffers s and s + sstride
+  int64_t sstride;
+  double* z;         // M^-1 r for the next row pass ([p] with stride zes)
+  const double* p1;  // the passes' workgroup partials of <s, d s> and <s, X^T u>
+  const double* p2;  //   (stride pstride)
+  int32_t n1, n2, pstride, zes;
   Combine<T> qsrc;   // the column pass's view of q
   T* qx;
   const double* b;
@@ -124,7 +165,8 @@ template <typename T>
 hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
                              T* piece_out, const T* out_scale, const int32_t* done,
                              hipStream_t st, hipEvent_t ev0 = nullptr,
-                             hipEvent_t ev1 = nullptr);
+                             hipEvent_t ev1 = nullptr, const DirIn<T>* dir = nullptr,
+                             const DotOut<T>* dot = nullptr, int parity = 0);
 
 // out[i] = value(c, i) for i < dim.
 template <typename T, typename U>
@@ -167,37 +209,38 @@ hipError_t launch_phi_finish(const T* qx, const double* d, const T* v, int64_t p
                              hipStream_t st);
 
 // CG start and restart.  If qx64 != NULL, r = b - qx64 - d .* beta, else
-// r = b (beta must then be zero).  z = M^-1 r, s = z.
+// r = b (beta must then be zero).  z = M^-1 r (the first row pass forms s = z
+// from it: the direction ratio is zero after a start).
 // mode 0: fresh start: also computes <b,Mb>, <b,b> and the thresholds (the
 //         recursion runs to loop_factor * tol);
 // mode 1: restart from the FP64 true residual of the current beta (keeps the
 //         thresholds);
 // mode 2: true-residual check only (no state change; writes true_meas, true_rm).
-template <typename T>
 hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
                            const double* d, const double* m, double* beta, double* r,
-                           T* s, int64_t p, double tol, int criterion, int max_iter,
+                           double* z, int64_t p, double tol, int criterion, int max_iter,
                            double loop_factor, hipStream_t st);
 
-// One CG iteration's vector phases after the matvec q = qx + d .* s.  The
-// dot phase assembles qx from the column pass's panel partials and writes it.
+// After the column pass: <s, Phi s> from the passes' workgroup partials
+// (fixed order), alpha = rho / <s, Phi s>; q = qx + d .* s with qx from the
+// column pass's panel partials; beta += alpha s; r -= alpha q; z = M^-1 r;
+// rho' = <r, z> and the stopping rule.  s is the new direction (buffer
+// 1 - parity of s).
 template <typename T>
-hipError_t launch_cg_dot(VecWork w, const T* s, const Combine<T>& qsrc, T* qx,
-                         const double* d, int64_t p, hipStream_t st);
-template <typename T>
-hipError_t launch_cg_update(VecWork w, const T* s, const T* qx, const double* d,
-                            const double* m, double* beta, double* r, int64_t p,
-                            hipStream_t st);
-template <typename T>
-hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s,
-                               int64_t p, hipStream_t st);
+hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity,
+                          const Combine<T>& qsrc, const double* d, const double* m,
+                          double* beta, double* r, double* z, const double* p1, int32_t n1,
+                          const double* p2, int32_t n2, int64_t p, hipStream_t st);
+
 // One X pass over K in {2, 4, 8} interleaved vectors ([dim][K] inputs and
 // outputs; part_out[(k * out_dim + id) * K + r]); skipped when the K flags
-// done[i * dstride] are all set (done may be null).
+// done[i * dstride] are all set (done may be null).  dir / dot as for
+// launch_panel_pass, over the K vectors.
 template <typename T>
 hipError_t launch_panel_pass_k(int K, const PanelPass& t, const Combine<T>& x, T* part_out,
                                T* piece_out, const T* out_scale, const int32_t* done,
-                               int dstride, hipStream_t st);
+                               int dstride, hipStream_t st, const DirIn<T>* dir = nullptr,
+                               const DotOut<T>* dot = nullptr, int parity = 0);
 
 // Blocks of one chain's p-vector phases.
 int32_t vec_blocks(int64_t p);
@@ -205,7 +248,8 @@ int32_t vec_blocks(int64_t p);
 // Workgroup g of a batched pass runs workgroup wg_local[g] of job wg_job[g].
 template <typename T>
 hipError_t launch_panel_pass_batched(const PanelJob<T>* jobs, const int32_t* wg_job,
-                                     const int32_t* wg_local, int32_t nwg, hipStream_t st);
+                                     const int32_t* wg_local, int32_t nwg, int mode, int parity,
+                                     hipStream_t st);
 // Block g runs block blk_local[g] of chain blk_job[g] (nblk blocks in all);
 // max_iter <= 0 takes each chain's own cap.
 template <typename T>
@@ -213,10 +257,11 @@ hipError_t launch_cg_start_batched(const VecJob<T>* jobs, const int32_t* blk_job
                                    const int32_t* blk_local, int32_t nblk, int mode, double tol,
                                    int criterion, int max_iter, double loop_factor,
                                    hipStream_t st);
-// dot, update and direction phases of the chains listed in blk_job.
+// The step kernel (launch_cg_step) of the chains listed in blk_job.
 template <typename T>
-hipError_t launch_cg_iteration_batched(const VecJob<T>* jobs, const int32_t* blk_job,
-                                       const int32_t* blk_local, int32_t nblk, hipStream_t st);
+hipError_t launch_cg_step_batched(const VecJob<T>* jobs, const int32_t* blk_job,
+                                  const int32_t* blk_local, int32_t nblk, int parity,
+                                  hipStream_t st);
 
 // Adjoint epilogue: grad_b = a, grad_loglambda = 2 d a beta, grad_logtau = sum.
 hipError_t launch_adjoint_epilogue(VecWork w, const double* a, const void* beta, int dtype,

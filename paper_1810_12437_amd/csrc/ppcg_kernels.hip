@@ -220,15 +220,17 @@ template <typename T, int K>
 __device__ __forceinline__ void gather_add16(const T* xl, const u16x8& a, const u16x8& b,
                                              T (&acc)[K]) {
   if constexpr (K == 1) {
-    T v[kPV];
+    // two halves of eight gathers in flight (the sum runs in element order)
+    T v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      v[j] = xl[a[j]];
-      v[8 + j] = xl[b[j]];
-    }
+    for (int j = 0; j < 8; ++j) v[j] = xl[a[j]];
     T s = v[0];
 #pragma unroll
-    for (int j = 1; j < kPV; ++j) s += v[j];
+    for (int j = 1; j < 8; ++j) s += v[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = xl[b[j]];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
     acc[0] += s;
   } else {
     const PanelEntry<T, K>* xp = reinterpret_cast<const PanelEntry<T, K>*>(xl);
@@ -262,12 +264,15 @@ __device__ __forceinline__ void dpp_add(T (&acc)[K], bool cond) {
 // Sum of each slice of chunk D at the slice's last lane (packed), or of the
 // whole wavefront at lane 63 (long), then the write (K values per slot).
 // Fixed order.
-template <typename T, int K>
+// With `dotting`, every written sum also adds s_j * sum to p2acc (sd: s_j of
+// the lane's output column, per vector).
+template <typename T, int K, bool dotting>
 __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T (&acc)[K],
                                              int32_t slot, const T (&scl)[K], int32_t piece,
                                              int lane, T* __restrict__ part_out,
                                              T* __restrict__ piece_out,
-                                             const T* __restrict__ out_scale) {
+                                             const T* __restrict__ out_scale,
+                                             const T (&sd)[K], double (&p2acc)[K]) {
   const int kind = ck_kind(info);
   if (kind == kChunkPacked) {
     // Segmented inclusive scan over the slices: row-local shifts, then the
@@ -283,8 +288,10 @@ __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T (&acc)
     if ((info >> 17) & 1) dpp_add<kDppBcast31, 0xc>(acc, off >= lane - 31);
     if (slot >= 0) {
 #pragma unroll
-      for (int r = 0; r < K; ++r)
+      for (int r = 0; r < K; ++r) {
         part_out[(int64_t)slot * K + r] = out_scale ? acc[r] * scl[r] : acc[r];
+        if constexpr (dotting) p2acc[r] += (double)sd[r] * (double)acc[r];
+      }
     }
     return;
   }
@@ -301,18 +308,23 @@ __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T (&acc)
         part_out[(int64_t)slot * K + r] = out_scale ? acc[r] * scl[r] : acc[r];
       else
         piece_out[(int64_t)piece * K + r] = acc[r];
+      if constexpr (dotting) p2acc[r] += (double)sd[r] * (double)acc[r];
     }
   }
 }
 
 // Workgroup w of one X pass over K interleaved vectors (K = 1: one vector).
-// The pass is skipped when all ndone flags done[i * dstride] are set.
-template <typename T, int K>
+// The pass is skipped when all ndone flags done[i * dstride] are set.  With
+// dir.z set the gathered panel is the new CG direction (DirIn); with dot.s
+// set the workgroup also sums its outputs against s (DotOut).
+template <typename T, int K, int MODE>
 __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>& xin,
                                            T* __restrict__ part_out, T* __restrict__ piece_out,
                                            const T* __restrict__ out_scale,
                                            const int32_t* __restrict__ done, int ndone,
-                                           int dstride, int w) {
+                                           int dstride, const DirIn<T>& dir,
+                                           const DotOut<T>& dot, int parity, int w) {
+  constexpr bool dotting = MODE == kPassDot;
   if (done != nullptr) {
     bool all = true;
     for (int i = 0; i < ndone; ++i) all = all && done[(int64_t)i * dstride] != 0;
@@ -332,7 +344,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   // chunk's window k + kPR or else the next chunk's window in that slot.
   u16x8 sa[kPR], sb[kPR];
   int32_t cinfo = 0, cfirst = 0, slot = -1;
-  int64_t cbase = 0, clen = 0;
+  int64_t cbase = 0, clen = 0, cseg = -1;
   uint64_t csm = 0;
   uint32_t chas = 0;
   if (c < c_end) {
@@ -344,6 +356,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       if ((L.has >> s) & 1u) load_window(t, D.base + L.rel[s], sa[s], sb[s]);
     cinfo = D.info;
     cfirst = D.first;
+    cseg = D.seg;
     cbase = D.base;
     clen = (int64_t)D.vm[0];
     csm = D.sm;
@@ -359,7 +372,57 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   // W holds the zeros the padding indices point to.  Eight loads in flight
   // per thread before the LDS stores.
   constexpr int U = 8;
-  if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr && xin.es == K) {
+  double p1acc[K], p2acc[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) p1acc[r] = p2acc[r] = 0.0;
+  const T* sdot = dotting ? dot.s + (int64_t)(1 - parity) * dot.sstride : nullptr;
+  const int64_t pofs = (int64_t)panel * t.out_dim;
+  if constexpr (MODE == kPassDir) {
+    // s = z + bc s_old per vector (s = z right after a start: bc = 0), into
+    // the panel; the workgroup's own entries also go to s_new and <s, d s>.
+    double bc[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      // (a vector whose chain has stopped keeps s = z: its sums are unused)
+      const DevScal& S = dir.sc[(int64_t)r * dir.scstride];
+      bc[r] = S.done ? 0.0 : S.betacg;
+    }
+    const T* s_old = dir.s + (int64_t)parity * dir.sstride;
+    T* s_new = dir.s + (int64_t)(1 - parity) * dir.sstride;
+    const int64_t o0 = t.wg_s0[w], o1 = t.wg_s1[w];
+    constexpr int UE = K >= 4 ? 1 : 8 / K;
+    for (int j0 = threadIdx.x; j0 < wlen; j0 += kPThreads * UE) {
+      T v[UE][K];
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const int j = j0 + u * kPThreads;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          v[u][r] = T(0);
+          if (j < wlen) {
+            const int64_t e = (g0 + j) * K + r;
+            v[u][r] = bc[r] == 0.0 ? (T)dir.z[e] : (T)(dir.z[e] + bc[r] * (double)s_old[e]);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const int j = j0 + u * kPThreads;
+        if (j < wlen) {
+          const bool own = g0 + j >= o0 && g0 + j < o1;
+#pragma unroll
+          for (int r = 0; r < K; ++r) {
+            const int64_t e = (g0 + j) * K + r;
+            xl[(int64_t)j * K + r] = v[u][r];
+            if (own) {
+              s_new[e] = v[u][r];
+              p1acc[r] += dir.d[e] * (double)v[u][r] * (double)v[u][r];
+            }
+          }
+        }
+      }
+    }
+  } else if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr && xin.es == K) {
     const T* src = xin.part + g0 * K;
     const int cnt = wlen * K;
     for (int j0 = threadIdx.x; j0 < cnt; j0 += kPThreads * U) {
@@ -376,16 +439,17 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       }
     }
   } else {
+    constexpr int UC = 2;  // (each value already has up to eight partial loads in flight)
     const int cnt = wlen * K;
-    for (int j0 = threadIdx.x; j0 < cnt; j0 += kPThreads * U) {
-      T v[U];
+    for (int j0 = threadIdx.x; j0 < cnt; j0 += kPThreads * UC) {
+      T v[UC];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UC; ++u) {
         const int j = j0 + u * kPThreads;
         v[u] = (j < cnt) ? combine_at(xin, g0 + j / K, j % K) : T(0);
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UC; ++u) {
         const int j = j0 + u * kPThreads;
         if (j < cnt) xl[j] = v[u];
       }
@@ -397,7 +461,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   while (c < c_end) {
     const int cn = c + 1;
     int32_t ninfo = 0, nfirst = 0, slot_n = -1;
-    int64_t nbase = 0, nlen = 0;
+    int64_t nbase = 0, nlen = 0, nseg = -1;
     uint64_t nsm = 0;
     LaneWindows LN;
     LN.has = 0;
@@ -406,16 +470,27 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       lane_windows(N, lane, LN);
       ninfo = N.info;
       nfirst = N.first;
+      nseg = N.seg;
       nbase = N.base;
       nlen = (int64_t)N.vm[0];
       nsm = N.sm;
       slot_n = out_slot(t, N, lane);
     }
     const int R = ck_windows(cinfo);
-    T scl[K];
+    T scl[K], sd[K];
 #pragma unroll
-    for (int r = 0; r < K; ++r)
+    for (int r = 0; r < K; ++r) {
       scl[r] = (out_scale != nullptr && slot >= 0) ? out_scale[(int64_t)slot * K + r] : T(1);
+      sd[r] = T(0);
+    }
+    if constexpr (dotting) {
+      // the output column of this lane (the piece's column for a piece)
+      const int64_t jd = ck_kind(cinfo) == kChunkPiece ? cseg : (slot >= 0 ? slot - pofs : -1);
+      if (jd >= 0) {
+#pragma unroll
+        for (int r = 0; r < K; ++r) sd[r] = sdot[jd * K + r];
+      }
+    }
     // Slots this chunk leaves unused take the next chunk's windows now.
 #pragma unroll
     for (int s = 0; s < kPR; ++s)
@@ -440,9 +515,11 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
         }
       }
     }
-    finish_chunk<T, K>(cinfo, csm, acc, slot, scl, cfirst, lane, part_out, piece_out, out_scale);
+    finish_chunk<T, K, dotting>(cinfo, csm, acc, slot, scl, cfirst, lane, part_out, piece_out,
+                                out_scale, sd, p2acc);
     cinfo = ninfo;
     cfirst = nfirst;
+    cseg = nseg;
     cbase = nbase;
     clen = nlen;
     csm = nsm;
@@ -450,52 +527,103 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
     slot = slot_n;
     c = cn;
   }
+  if constexpr (MODE != kPassPlain) {
+    // The workgroup's partials, in a fixed order: lanes, then wavefronts
+    // (the panel's LDS is free once every wavefront is done).
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const double a = wave_sum(p1acc[r]);
+      const double b = wave_sum(p2acc[r]);
+      if (lane == 0) {
+        red[(wave * K + r) * 2 + 0] = a;
+        red[(wave * K + r) * 2 + 1] = b;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+      const int r = threadIdx.x;
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < kPWaves; ++q) {
+        a += red[(q * K + r) * 2 + 0];
+        b += red[(q * K + r) * 2 + 1];
+      }
+      if constexpr (MODE == kPassDir) dir.p1[(int64_t)w * K + r] = a;
+      if constexpr (dotting) dot.p2[(int64_t)w * K + r] = b;
+    }
+  }
 }
 
-template <typename T>
+template <typename T, int MODE>
 __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin,
                                                      T* __restrict__ part_out,
                                                      T* __restrict__ piece_out,
                                                      const T* __restrict__ out_scale,
-                                                     const int32_t* __restrict__ done) {
-  panel_body<T, 1>(t, xin, part_out, piece_out, out_scale, done, 1, 0, (int)blockIdx.x);
+                                                     const int32_t* __restrict__ done,
+                                                     DirIn<T> dir, DotOut<T> dot, int parity) {
+  panel_body<T, 1, MODE>(t, xin, part_out, piece_out, out_scale, done, 1, 0, dir, dot, parity,
+                         (int)blockIdx.x);
 }
 
-template <typename T>
+template <typename T, int MODE>
 __global__ __launch_bounds__(kPThreads) void k_panel_b(const PanelJob<T>* __restrict__ jobs,
                                                        const int32_t* __restrict__ wg_job,
-                                                       const int32_t* __restrict__ wg_local) {
+                                                       const int32_t* __restrict__ wg_local,
+                                                       int parity) {
   const PanelJob<T>& J = jobs[wg_job[blockIdx.x]];
-  panel_body<T, 1>(J.t, J.x, J.part_out, J.piece_out, J.out_scale, J.done, 1, 0,
-                   wg_local[blockIdx.x]);
+  panel_body<T, 1, MODE>(J.t, J.x, J.part_out, J.piece_out, J.out_scale, J.done, 1, 0, J.dir,
+                         J.dot, parity, wg_local[blockIdx.x]);
 }
 
 // One X pass over K interleaved vectors; skipped when the done flags of all
 // K chains are set.
-template <typename T, int K>
+template <typename T, int K, int MODE>
 __global__ __launch_bounds__(kPThreads) void k_panel_k(PanelPass t, Combine<T> xin,
                                                        T* __restrict__ part_out,
                                                        T* __restrict__ piece_out,
                                                        const T* __restrict__ out_scale,
                                                        const int32_t* __restrict__ done,
-                                                       int dstride) {
-  panel_body<T, K>(t, xin, part_out, piece_out, out_scale, done, K, dstride, (int)blockIdx.x);
+                                                       int dstride, DirIn<T> dir, DotOut<T> dot,
+                                                       int parity) {
+  panel_body<T, K, MODE>(t, xin, part_out, piece_out, out_scale, done, K, dstride, dir, dot,
+                         parity, (int)blockIdx.x);
 }
 
 static size_t pass_lds_bytes() { return (size_t)kPanelBytes; }
 
-hipError_t setup_pass_kernels() {
-  const int bytes = (int)pass_lds_bytes();
-  const void* fns[] = {reinterpret_cast<const void*>(&k_panel<float>),
-                       reinterpret_cast<const void*>(&k_panel<double>),
-                       reinterpret_cast<const void*>(&k_panel_b<float>),
-                       reinterpret_cast<const void*>(&k_panel_b<double>),
-                       reinterpret_cast<const void*>(&k_panel_k<float, 2>),
-                       reinterpret_cast<const void*>(&k_panel_k<double, 2>),
-                       reinterpret_cast<const void*>(&k_panel_k<float, 4>),
-                       reinterpret_cast<const void*>(&k_panel_k<double, 4>),
-                       reinterpret_cast<const void*>(&k_panel_k<float, 8>),
-                       reinterpret_cast<const void*>(&k_panel_k<double, 8>)};
+// The pass variant: a direction (row pass of the CG loop), a dot output
+// (column pass of the CG loop), or neither; -1 for both.
+template <typename T>
+static int pass_mode(const DirIn<T>* dir, const DotOut<T>* dot) {
+  const bool a = dir != nullptr && dir->z != nullptr;
+  const bool b = dot != nullptr && dot->s != nullptr;
+  if (a && b) return -1;
+  return a ? kPassDir : (b ? kPassDot : kPassPlain);
+}
+
+// Host-side check of what a pass with a direction or a dot output reads
+// besides the plain pass: the workgroup slices and the output dimension.
+template <typename T>
+static bool pass_args_ok(const PanelPass& t, const DirIn<T>* dir, const DotOut<T>* dot) {
+  if (t.idx == nullptr || t.chunks == nullptr || t.wave_c == nullptr || t.wg_panel == nullptr)
+    return false;
+  if (dir != nullptr && dir->z != nullptr &&
+      (t.wg_s0 == nullptr || t.wg_s1 == nullptr || dir->s == nullptr || dir->d == nullptr ||
+       dir->sc == nullptr || dir->p1 == nullptr))
+    return false;
+  if (dot != nullptr && dot->s != nullptr && (t.out_dim <= 0 || dot->p2 == nullptr))
+    return false;
+  return true;
+}
+
+template <typename T, int MODE>
+static hipError_t set_lds(int bytes) {
+  const void* fns[] = {reinterpret_cast<const void*>(&k_panel<T, MODE>),
+                       reinterpret_cast<const void*>(&k_panel_b<T, MODE>),
+                       reinterpret_cast<const void*>(&k_panel_k<T, 2, MODE>),
+                       reinterpret_cast<const void*>(&k_panel_k<T, 4, MODE>),
+                       reinterpret_cast<const void*>(&k_panel_k<T, 8, MODE>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -503,63 +631,119 @@ hipError_t setup_pass_kernels() {
   return hipSuccess;
 }
 
+hipError_t setup_pass_kernels() {
+  const int bytes = (int)pass_lds_bytes();
+  hipError_t e;
+  if ((e = set_lds<float, kPassPlain>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds<float, kPassDir>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds<float, kPassDot>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds<double, kPassPlain>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds<double, kPassDir>(bytes)) != hipSuccess) return e;
+  return set_lds<double, kPassDot>(bytes);
+}
+
 template <typename T>
 hipError_t launch_panel_pass_batched(const PanelJob<T>* jobs, const int32_t* wg_job,
-                                     const int32_t* wg_local, int32_t nwg, hipStream_t st) {
+                                     const int32_t* wg_local, int32_t nwg, int mode, int parity,
+                                     hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_panel_b<T>), dim3(nwg), dim3(kPThreads), pass_lds_bytes(), st, jobs,
-                     wg_job, wg_local);
+  const dim3 g(nwg), b(kPThreads);
+  const size_t lds = pass_lds_bytes();
+  if (mode == kPassDir)
+    hipLaunchKernelGGL((k_panel_b<T, kPassDir>), g, b, lds, st, jobs, wg_job, wg_local, parity);
+  else if (mode == kPassDot)
+    hipLaunchKernelGGL((k_panel_b<T, kPassDot>), g, b, lds, st, jobs, wg_job, wg_local, parity);
+  else if (mode == kPassPlain)
+    hipLaunchKernelGGL((k_panel_b<T, kPassPlain>), g, b, lds, st, jobs, wg_job, wg_local,
+                       parity);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_panel_pass_k(int K, const PanelPass& t, const Combine<T>& x, T* part_out,
                                T* piece_out, const T* out_scale, const int32_t* done,
-                               int dstride, hipStream_t st) {
+                               int dstride, hipStream_t st, const DirIn<T>* dir,
+                               const DotOut<T>* dot, int parity) {
   if (t.nwg == 0) return hipSuccess;
+  if (!pass_args_ok(t, dir, dot)) return hipErrorInvalidValue;
   const dim3 g(t.nwg), b(kPThreads);
   const size_t lds = pass_lds_bytes();
+  const DirIn<T> di = dir ? *dir : DirIn<T>{};
+  const DotOut<T> dd = dot ? *dot : DotOut<T>{};
+  const int mode = pass_mode(dir, dot);
+  if (mode < 0) return hipErrorInvalidValue;
+#define PPCG_LAUNCH_K(KK, M)                                                                   \
+  hipLaunchKernelGGL((k_panel_k<T, KK, M>), g, b, lds, st, t, x, part_out, piece_out,          \
+                     out_scale, done, dstride, di, dd, parity)
+#define PPCG_LAUNCH_M(KK)        \
+  if (mode == kPassDir)          \
+    PPCG_LAUNCH_K(KK, kPassDir); \
+  else if (mode == kPassDot)     \
+    PPCG_LAUNCH_K(KK, kPassDot); \
+  else                           \
+    PPCG_LAUNCH_K(KK, kPassPlain);
   switch (K) {
     case 2:
-      hipLaunchKernelGGL((k_panel_k<T, 2>), g, b, lds, st, t, x, part_out, piece_out, out_scale,
-                         done, dstride);
+      PPCG_LAUNCH_M(2)
       break;
     case 4:
-      hipLaunchKernelGGL((k_panel_k<T, 4>), g, b, lds, st, t, x, part_out, piece_out, out_scale,
-                         done, dstride);
+      PPCG_LAUNCH_M(4)
       break;
     case 8:
-      hipLaunchKernelGGL((k_panel_k<T, 8>), g, b, lds, st, t, x, part_out, piece_out, out_scale,
-                         done, dstride);
+      PPCG_LAUNCH_M(8)
       break;
     default:
       return hipErrorInvalidValue;
   }
+#undef PPCG_LAUNCH_M
+#undef PPCG_LAUNCH_K
   return hipGetLastError();
 }
 template hipError_t launch_panel_pass_k<float>(int, const PanelPass&, const Combine<float>&,
                                                float*, float*, const float*, const int32_t*, int,
-                                               hipStream_t);
+                                               hipStream_t, const DirIn<float>*,
+                                               const DotOut<float>*, int);
 template hipError_t launch_panel_pass_k<double>(int, const PanelPass&, const Combine<double>&,
                                                 double*, double*, const double*, const int32_t*,
-                                                int, hipStream_t);
+                                                int, hipStream_t, const DirIn<double>*,
+                                                const DotOut<double>*, int);
 template hipError_t launch_panel_pass_batched<float>(const PanelJob<float>*, const int32_t*,
-                                                     const int32_t*, int32_t, hipStream_t);
+                                                     const int32_t*, int32_t, int, int,
+                                                     hipStream_t);
 template hipError_t launch_panel_pass_batched<double>(const PanelJob<double>*, const int32_t*,
-                                                      const int32_t*, int32_t, hipStream_t);
+                                                      const int32_t*, int32_t, int, int,
+                                                      hipStream_t);
 
 template <typename T>
 hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_out,
                              T* piece_out, const T* out_scale, const int32_t* done,
-                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                             const DirIn<T>* dir, const DotOut<T>* dot, int parity) {
   if (t.nwg == 0) return hipSuccess;
-  if (ev0 != nullptr) {
-    // Events taken by the dispatch itself: the kernel's own duration.
-    hipExtLaunchKernelGGL((k_panel<T>), dim3(t.nwg), dim3(kPThreads), pass_lds_bytes(), st, ev0,
-                          ev1, 0u, t, x, part_out, piece_out, out_scale, done);
+  if (!pass_args_ok(t, dir, dot)) return hipErrorInvalidValue;
+  const DirIn<T> di = dir ? *dir : DirIn<T>{};
+  const DotOut<T> dd = dot ? *dot : DotOut<T>{};
+  const int mode = pass_mode(dir, dot);
+  if (mode < 0) return hipErrorInvalidValue;
+  const dim3 g(t.nwg), b(kPThreads);
+  const size_t lds = pass_lds_bytes();
+  // With events, the dispatch itself records them: the kernel's own duration.
+#define PPCG_LAUNCH(M)                                                                        \
+  if (ev0 != nullptr)                                                                         \
+    hipExtLaunchKernelGGL((k_panel<T, M>), g, b, lds, st, ev0, ev1, 0u, t, x, part_out,       \
+                          piece_out, out_scale, done, di, dd, parity);                        \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_panel<T, M>), g, b, lds, st, t, x, part_out, piece_out, out_scale,  \
+                       done, di, dd, parity);
+  if (mode == kPassDir) {
+    PPCG_LAUNCH(kPassDir)
+  } else if (mode == kPassDot) {
+    PPCG_LAUNCH(kPassDot)
   } else {
-    hipLaunchKernelGGL((k_panel<T>), dim3(t.nwg), dim3(kPThreads), pass_lds_bytes(), st, t, x,
-                       part_out, piece_out, out_scale, done);
+    PPCG_LAUNCH(kPassPlain)
   }
+#undef PPCG_LAUNCH
   return hipGetLastError();
 }
 
@@ -579,10 +763,12 @@ hipError_t launch_combine(const Combine<T>& c, int64_t dim, U* out, hipStream_t 
 
 template hipError_t launch_panel_pass<float>(const PanelPass&, const Combine<float>&, float*,
                                              float*, const float*, const int32_t*, hipStream_t,
-                                             hipEvent_t, hipEvent_t);
+                                             hipEvent_t, hipEvent_t, const DirIn<float>*,
+                                             const DotOut<float>*, int);
 template hipError_t launch_panel_pass<double>(const PanelPass&, const Combine<double>&, double*,
                                               double*, const double*, const int32_t*,
-                                              hipStream_t, hipEvent_t, hipEvent_t);
+                                              hipStream_t, hipEvent_t, hipEvent_t,
+                                              const DirIn<double>*, const DotOut<double>*, int);
 template hipError_t launch_combine<float, float>(const Combine<float>&, int64_t, float*,
                                                  hipStream_t);
 template hipError_t launch_combine<double, double>(const Combine<double>&, int64_t, double*,
@@ -819,13 +1005,12 @@ __device__ __forceinline__ bool restart_wanted(const DevScal* sc) {
   return sc->status == kStatOK && sc->true_meas > sc->thresh2;
 }
 
-template <typename T>
 __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double* b,
                                               const double* qx64, const double* d,
-                                              const double* m, double* beta, double* r, T* s,
-                                              int64_t p, double tol, int criterion,
+                                              const double* m, double* beta, double* r,
+                                              double* z, int64_t p, double tol, int criterion,
                                               int max_iter, double loop_factor, VGrid g,
-                                              int es = 1) {
+                                              int zes = 1) {
   if (mode == 1 && !restart_wanted(w.sc)) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // <r,Mr>, <r,r>, <b,Mb>, <b,b>
   for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
@@ -841,7 +1026,7 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
     }
     if (mode != 2) {
       r[j] = rj;
-      s[j * es] = (T)zj;
+      z[j * zes] = zj;
     }
   }
   block_sum<4>(v);
@@ -869,7 +1054,7 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
                                                  : t2 * tot[3];
       sc->loop2 = sc->thresh2 * loop_factor * loop_factor;
     }
-    sc->betacg = 0.0;
+    sc->betacg = 0.0;  // the first row pass takes s = z
     sc->rho_prev = tot[0];
     sc->rho = tot[0];
     sc->rr = tot[1];
@@ -886,49 +1071,49 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
   }
 }
 
+// One CG step after the two passes (see launch_cg_step).  p1 / p2 hold the
+// passes' workgroup partials (n1 and n2 of them, stride ps).
 template <typename T>
-__device__ __forceinline__ void cg_dot_body(VecWork w, const T* s, const Combine<T>& qsrc,
-                                            T* qx, const double* d, int64_t p, VGrid g,
-                                            int es = 1) {
-  if (w.sc->done) return;
-  double v[1] = {0.0};
-  for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
-    const T qj = combine_at(qsrc, j);
-    qx[j] = qj;
-    const double sj = (double)s[j * es];
-    v[0] += sj * ((double)qj + d[j] * sj);
+__device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
+                                             const Combine<T>& qsrc, const double* d,
+                                             const double* m, double* beta, double* r,
+                                             double* z, int zes, const double* p1, int n1,
+                                             const double* p2, int n2, int ps, int64_t p,
+                                             VGrid g) {
+  DevScal* sc = w.sc;
+  if (sc->done) return;
+  // <s, Phi s> = <s, d s> + <s, X^T u>: the same fixed-order total in every
+  // block, all threads loading at once (the partials come from other XCDs)
+  __shared__ double sq_sh;
+  {
+    double a[1] = {0.0};
+    for (int q = threadIdx.x; q < n1; q += kWG) a[0] += p1[(int64_t)q * ps];
+    for (int q = threadIdx.x; q < n2; q += kWG) a[0] += p2[(int64_t)q * ps];
+    block_sum<1>(a);
+    if (threadIdx.x == 0) sq_sh = a[0];
   }
-  block_sum<1>(v);
-  if (!publish_and_arrive<1>(v, w.part, &w.sc->arrive[2], g)) return;
-  double tot[1];
-  gather_totals<1>(w.part, &w.sc->arrive[2], tot, g);
-  if (threadIdx.x == 0) {
-    DevScal* sc = w.sc;
-    sc->sq = tot[0];
-    if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
+  __syncthreads();
+  const double sq = sq_sh;
+  if (!(sq > 0.0) || !isfinite(sq)) {
+    if (g.bid == 0 && threadIdx.x == 0) {
+      sc->sq = sq;
       sc->status = kStatBreakdown;
       sc->done = 1;
       sc->alpha = 0.0;
-    } else {
-      sc->alpha = sc->rho / tot[0];
     }
+    return;
   }
-}
-
-template <typename T>
-__device__ __forceinline__ void cg_update_body(VecWork w, const T* s, const T* qx,
-                                               const double* d, const double* m, double* beta,
-                                               double* r, int64_t p, VGrid g, int es = 1) {
-  if (w.sc->done) return;
-  const double alpha = w.sc->alpha;
+  const double alpha = sc->rho / sq;
   double v[2] = {0.0, 0.0};  // <r, M^-1 r>, <r, r>
   for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
     const double sj = (double)s[j * es];
-    const double qj = (double)qx[j] + d[j] * sj;
+    const double qj = (double)combine_at(qsrc, j) + d[j] * sj;
     beta[j] += alpha * sj;
     const double rj = r[j] - alpha * qj;
     r[j] = rj;
-    v[0] += rj * (m[j] * rj);
+    const double zj = m[j] * rj;
+    z[j * zes] = zj;
+    v[0] += rj * zj;
     v[1] += rj * rj;
   }
   block_sum<2>(v);
@@ -936,8 +1121,9 @@ __device__ __forceinline__ void cg_update_body(VecWork w, const T* s, const T* q
   double tot[2];
   gather_totals<2>(w.part, &w.sc->arrive[3], tot, g);
   if (threadIdx.x == 0) {
-    DevScal* sc = w.sc;
     const double rho_new = tot[0];
+    sc->sq = sq;
+    sc->alpha = alpha;
     sc->iters += 1;
     sc->rr = tot[1];
     const double meas = (sc->criterion == kCritRelPlain) ? tot[1] : rho_new;
@@ -957,69 +1143,40 @@ __device__ __forceinline__ void cg_update_body(VecWork w, const T* s, const T* q
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void cg_direction_body(VecWork w, const double* m, const double* r,
-                                                  T* s, int64_t p, VGrid g, int es = 1) {
-  if (w.sc->done) return;
-  const double bc = w.sc->betacg;
-  for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG)
-    s[j * es] = (T)(m[j] * r[j] + bc * (double)s[j * es]);
-}
-
 // ---- one chain ----
-template <typename T>
 __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const double* b,
                                                   const double* qx64, const double* d,
                                                   const double* m, double* beta, double* r,
-                                                  T* s, int64_t p, double tol, int criterion,
-                                                  int max_iter, double loop_factor) {
-  cg_start_body<T>(w, mode, b, qx64, d, m, beta, r, s, p, tol, criterion, max_iter, loop_factor,
-                   own_grid());
+                                                  double* z, int64_t p, double tol,
+                                                  int criterion, int max_iter,
+                                                  double loop_factor) {
+  cg_start_body(w, mode, b, qx64, d, m, beta, r, z, p, tol, criterion, max_iter, loop_factor,
+                own_grid());
 }
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_dot(VecWork w, const T* s, Combine<T> qsrc, T* qx,
-                                                const double* d, int64_t p) {
-  cg_dot_body<T>(w, s, qsrc, qx, d, p, own_grid());
-}
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_update(VecWork w, const T* s, const T* qx,
-                                                   const double* d, const double* m,
-                                                   double* beta, double* r, int64_t p) {
-  cg_update_body<T>(w, s, qx, d, m, beta, r, p, own_grid());
-}
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_direction(VecWork w, const double* m,
-                                                      const double* r, T* s, int64_t p) {
-  cg_direction_body<T>(w, m, r, s, p, own_grid());
+__global__ __launch_bounds__(kWG) void k_cg_step(VecWork w, const T* s, Combine<T> qsrc,
+                                                 const double* d, const double* m, double* beta,
+                                                 double* r, double* z, const double* p1,
+                                                 int n1, const double* p2, int n2, int64_t p) {
+  cg_step_body<T>(w, s, 1, qsrc, d, m, beta, r, z, 1, p1, n1, p2, n2, 1, p, own_grid());
 }
 
-template <typename T>
 hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
-                           const double* d, const double* m, double* beta, double* r, T* s,
-                           int64_t p, double tol, int criterion, int max_iter,
+                           const double* d, const double* m, double* beta, double* r,
+                           double* z, int64_t p, double tol, int criterion, int max_iter,
                            double loop_factor, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_start<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, mode, b, qx64, d,
-                     m, beta, r, s, p, tol, criterion, max_iter, loop_factor);
+  hipLaunchKernelGGL(k_cg_start, dim3(red_grid(p)), dim3(kWG), 0, st, w, mode, b, qx64, d, m,
+                     beta, r, z, p, tol, criterion, max_iter, loop_factor);
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_cg_dot(VecWork w, const T* s, const Combine<T>& qsrc, T* qx, const double* d,
-                         int64_t p, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_dot<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, s, qsrc, qx, d, p);
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_cg_update(VecWork w, const T* s, const T* qx, const double* d,
-                            const double* m, double* beta, double* r, int64_t p,
-                            hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_update<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, s, qx, d, m, beta,
-                     r, p);
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_cg_direction(VecWork w, const double* m, const double* r, T* s, int64_t p,
-                               hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_direction<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, m, r, s, p);
+hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity,
+                          const Combine<T>& qsrc, const double* d, const double* m,
+                          double* beta, double* r, double* z, const double* p1, int32_t n1,
+                          const double* p2, int32_t n2, int64_t p, hipStream_t st) {
+  const T* sn = s + (int64_t)(1 - parity) * sstride;
+  hipLaunchKernelGGL((k_cg_step<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, sn, qsrc, d, m,
+                     beta, r, z, p1, n1, p2, n2, p);
   return hipGetLastError();
 }
 
@@ -1040,31 +1197,16 @@ __global__ __launch_bounds__(kWG) void k_cg_start_b(const VecJob<T>* jobs,
                                                     double loop_factor) {
   VGrid g;
   const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
-  cg_start_body<T>(J.w, mode, J.b, mode == 0 ? nullptr : J.qx64, J.d, J.m, J.beta, J.r, J.s, J.p,
-                   tol, criterion, max_iter > 0 ? max_iter : J.max_iter, loop_factor, g, J.es);
+  cg_start_body(J.w, mode, J.b, mode == 0 ? nullptr : J.qx64, J.d, J.m, J.beta, J.r, J.z, J.p,
+                tol, criterion, max_iter > 0 ? max_iter : J.max_iter, loop_factor, g, J.zes);
 }
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_dot_b(const VecJob<T>* jobs, const int32_t* blk_job,
-                                                  const int32_t* blk_local) {
+__global__ __launch_bounds__(kWG) void k_cg_step_b(const VecJob<T>* jobs, const int32_t* blk_job,
+                                                   const int32_t* blk_local, int parity) {
   VGrid g;
   const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
-  cg_dot_body<T>(J.w, J.s, J.qsrc, J.qx, J.d, J.p, g, J.es);
-}
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_update_b(const VecJob<T>* jobs,
-                                                     const int32_t* blk_job,
-                                                     const int32_t* blk_local) {
-  VGrid g;
-  const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
-  cg_update_body<T>(J.w, J.s, J.qx, J.d, J.m, J.beta, J.r, J.p, g, J.es);
-}
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_cg_direction_b(const VecJob<T>* jobs,
-                                                        const int32_t* blk_job,
-                                                        const int32_t* blk_local) {
-  VGrid g;
-  const VecJob<T>& J = vec_job(jobs, blk_job, blk_local, g);
-  cg_direction_body<T>(J.w, J.m, J.r, J.s, J.p, g, J.es);
+  cg_step_body<T>(J.w, J.s + (int64_t)(1 - parity) * J.sstride, J.es, J.qsrc, J.d, J.m, J.beta,
+                  J.r, J.z, J.zes, J.p1, J.n1, J.p2, J.n2, J.pstride, J.p, g);
 }
 
 int32_t vec_blocks(int64_t p) { return (int32_t)red_grid(p); }
@@ -1080,32 +1222,25 @@ hipError_t launch_cg_start_batched(const VecJob<T>* jobs, const int32_t* blk_job
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_cg_iteration_batched(const VecJob<T>* jobs, const int32_t* blk_job,
-                                       const int32_t* blk_local, int32_t nblk, hipStream_t st) {
+hipError_t launch_cg_step_batched(const VecJob<T>* jobs, const int32_t* blk_job,
+                                  const int32_t* blk_local, int32_t nblk, int parity,
+                                  hipStream_t st) {
   if (nblk <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_cg_dot_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job, blk_local);
-  hipLaunchKernelGGL((k_cg_update_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job, blk_local);
-  hipLaunchKernelGGL((k_cg_direction_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job,
-                     blk_local);
+  hipLaunchKernelGGL((k_cg_step_b<T>), dim3(nblk), dim3(kWG), 0, st, jobs, blk_job, blk_local,
+                     parity);
   return hipGetLastError();
 }
 
 #define PPCG_INST(T)                                                                         \
-  template hipError_t launch_cg_start<T>(VecWork, int, const double*, const double*,         \
-                                         const double*, const double*, double*, double*, T*, \
-                                         int64_t, double, int, int, double, hipStream_t);    \
-  template hipError_t launch_cg_dot<T>(VecWork, const T*, const Combine<T>&, T*,            \
-                                       const double*, int64_t, hipStream_t);                 \
-  template hipError_t launch_cg_update<T>(VecWork, const T*, const T*, const double*,        \
-                                          const double*, double*, double*, int64_t,          \
-                                          hipStream_t);                                      \
-  template hipError_t launch_cg_direction<T>(VecWork, const double*, const double*, T*,      \
-                                             int64_t, hipStream_t);                          \
+  template hipError_t launch_cg_step<T>(VecWork, const T*, int64_t, int, const Combine<T>&,  \
+                                        const double*, const double*, double*, double*,      \
+                                        double*, const double*, int32_t, const double*,      \
+                                        int32_t, int64_t, hipStream_t);                      \
   template hipError_t launch_cg_start_batched<T>(const VecJob<T>*, const int32_t*,           \
                                                  const int32_t*, int32_t, int, double, int,    \
                                                  int, double, hipStream_t);                    \
-  template hipError_t launch_cg_iteration_batched<T>(const VecJob<T>*, const int32_t*,       \
-                                                     const int32_t*, int32_t, hipStream_t);
+  template hipError_t launch_cg_step_batched<T>(const VecJob<T>*, const int32_t*,            \
+                                                const int32_t*, int32_t, int, hipStream_t);
 PPCG_INST(float)
 PPCG_INST(double)
 #undef PPCG_INST

@@ -14,6 +14,7 @@ constexpr int kPR = 4;                 // windows of a packed chunk
 constexpr int kPLongWin = 16;          // most windows of a long chunk
 constexpr int kPLongMax = kPLongWin * kPC;  // longest segment one wavefront sums whole
 constexpr int kPanelBytes = 160 * 1024 - 64;  // LDS for the gathered panel (+ zero slot)
+// (after the pass, the same LDS holds the workgroup's partial-sum reduction)
 
 enum ChunkKind { kChunkPacked = 0, kChunkLong = 1, kChunkPiece = 2 };
 
@@ -33,10 +34,10 @@ struct alignas(64) ChunkDesc {
   int64_t base;      // first element of the chunk in the index stream
   uint64_t vm[kPR];  // see above
   uint64_t sm;
-  int32_t first;     // packed: first seg_out entry; long: its seg_out entry; piece: unused
+  int32_t first;     // packed: first seg_out entry; long: its seg_out entry; piece: its id
   int32_t info;      // windows | kind << 8 | row steps << 12 | bcast15 << 16 | bcast31 << 17
                      //   | segments << 24
-  int64_t pad;
+  int64_t seg;       // piece: the segment (output element) it is part of
 };
 static_assert(sizeof(ChunkDesc) == 64, "chunk descriptor is one 64-byte scalar load");
 

@@ -20,6 +20,7 @@ struct PanelBuild {
                                   // [wave_c[16 w + q], wave_c[16 w + q + 1])
   std::vector<int32_t> seg_out;
   std::vector<int32_t> wg_panel, wave_c;
+  std::vector<int32_t> wg_s0, wg_s1;  // gathered entries [s0, s1) each workgroup owns
   std::vector<int32_t> sp_off, sp_c0, sp_c1;  // pieces of element i: ids sp_c0..sp_c1
   int64_t gdim = 0, out_dim = 0;
   int64_t nseg = 0;    // (segment, panel) pairs with elements
@@ -174,8 +175,9 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
   const int64_t tot = std::max<int64_t>(std::accumulate(pwin.begin(), pwin.end(), (int64_t)0), 1);
   std::vector<int> g_k(B.npanels, 0);
   int assigned = 0;
+  // (every panel gets at least one workgroup: its workgroups also own the
+  // panel's entries of the gathered vector)
   for (int32_t k = 0; k < B.npanels; ++k) {
-    if (pwin[k] == 0) continue;
     g_k[k] = std::max(1, (int)((int64_t)nwg_total * pwin[k] / tot));
     assigned += g_k[k];
   }
@@ -219,6 +221,7 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
         d.vm[0] = (uint64_t)(ng * kPV);
         const int win = (int)((ng + 63) / 64);
         d.first = pieces ? B.npieces++ : (int32_t)B.seg_out.size() - 1;
+        d.seg = en.slot % out_dim;
         d.info = chunk_info(win, pieces ? kChunkPiece : kChunkLong, 0, 0, 0, 1);
         for (int64_t q = o; q < oe; q += kPV) append_group(q, std::min<int64_t>(q + kPV, oe), glo);
         const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -306,8 +309,11 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
       if (!leftover && worst <= (used + nwv - 1) / nwv + 1) break;
       total = used;
     }
+    const int64_t e0 = glo, e1 = std::min<int64_t>(glo + B.W, gdim);
     for (int g = 0; g < g_k[k]; ++g) {
       B.wg_panel.push_back(k);
+      B.wg_s0.push_back((int32_t)(e0 + (e1 - e0) * g / g_k[k]));
+      B.wg_s1.push_back((int32_t)(e0 + (e1 - e0) * (g + 1) / g_k[k]));
       for (int q = 0; q < kPWaves; ++q) {
         for (const ChunkDesc& d : lists[g * kPWaves + q]) B.chunks.push_back(d);
         B.wave_c.push_back((int32_t)B.chunks.size());
