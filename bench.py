@@ -40,9 +40,10 @@ METRIC = "Gibbs beta-draws/sec + SpMV-CG HBM GB/s (% peak), n=1e5 p=2e4, rel err
 SEED = 12437
 COPY_BYTES = 512 << 20
 
-# HBM traffic of one k_panel<double> launch on this workload, from two
+# HBM traffic of one X-pass launch (k_panel<double, 1> row pass and
+# k_panel<double, 2> column pass, averaged) on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean
-# over the launches of the timed draws) scaled by the same counters of a
+# over the launches of the profiled draws) scaled by the same counters of a
 # plain 512 MiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for
 # the kernel sources it was measured on (SHA-256 over the files below); any
 # change to them reports null until the counters are taken again.
@@ -50,9 +51,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "bdab65202b2239311cbef5c2fa457adc149b54863c3980800355cca9377a0879",
-    # (55,864.6 KiB FETCH_SIZE x 2.0 + 787.3 KiB WRITE_SIZE x 1.0) x 1024
-    "bytes_per_launch": 115216966,
+    "sources_sha256": "0b1ccdd56c200adb2d8d94fb8b800a1846be669cfa0c7a2fb5666405c7bca3ff",
+    # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
+    "bytes_per_launch": 121790617,
 }
 
 
@@ -410,7 +411,7 @@ def main():
         "cg_hbm_frac": cg_gbps / HBM_PEAK_GBPS,
         "max_true_resid_over_tol": float(max(i["resid_true"] for i in r64["infos"])),
         "roofline": {
-            "kernel": "k_panel<double> (row pass X s and column pass X^T u)",
+            "kernel": "k_panel<double, 1> row pass (X s) and k_panel<double, 2> column pass (X^T u)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
             "avg_launch_us": 1e3 * t_pass,
