@@ -207,6 +207,26 @@ def test_draw_is_deterministic(problem_cache):
     assert torch.equal(a, b) and not torch.equal(a, c)
 
 
+def test_profile_samples_leave_draw_unchanged(problem_cache):
+    """Pass timing samples one iteration per check batch: the draw is the same
+    bits with it on, and the sampled launches are counted and timed."""
+    P = problem_cache("c0")
+    X = pk.Matrix.from_problem(P)
+    a, ia = pk.draw(X, t64(P.omega), t64(P.z), t64(P.lam), P.tau, 7, 2, 5, tol=1e-10,
+                    check_every=4)
+    X.profile(True)
+    b, ib = pk.draw(X, t64(P.omega), t64(P.z), t64(P.lam), P.tau, 7, 2, 5, tol=1e-10,
+                    check_every=4)
+    st = X.stats()
+    X.profile(False)
+    say(f"[profile] iters={ib['iters']} stats={st}")
+    assert torch.equal(a, b) and ia["iters"] == ib["iters"]
+    # iteration 2 of every batch of 4 that reached it
+    want = sum(1 for k in range(0, ib["iters"], 4) if ib["iters"] - k > 2)
+    assert st["csr_launches"] == want and st["csc_launches"] == want
+    assert st["csr_ms"] > 0.0 and st["csc_ms"] > 0.0
+
+
 @pytest.mark.parametrize("n,p", [(4000, 900), (20000, 3000)])
 def test_draw_f32_matches_f64_oracle(n, p):
     P = synth.scaled_problem(n, p, seed=n + p)
