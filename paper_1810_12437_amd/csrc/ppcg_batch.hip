@@ -163,7 +163,8 @@ int build_pass_jobs(ppcg_batch* B, int kind) {
     }
     J.done = (kind == kJobRow || kind == kJobCol) ? &B->sc[c].done : nullptr;
     // what the loop's passes read besides the plain pass
-    if (J.t.nwg > 0 && (J.t.wg_s0 == nullptr || J.t.wg_s1 == nullptr || J.t.out_dim <= 0))
+    if (J.t.nwg > 0 && (J.t.wg_s0 == nullptr || J.t.wg_s1 == nullptr || J.t.out_dim <= 0 ||
+                        J.t.seg_out == nullptr || J.t.no_slot < 0))
       return PPCG_EHIP;
     if (kind == kJobRow) {
       // the loop's row pass forms the direction s from z (DirIn)

@@ -13,9 +13,23 @@ int upload_orient(DevBuf& mem, const PanelBuild& B, int elem, int K, Orient& o) 
   int rc;
   int64_t by = 0;
   PanelPass& t = o.pass;
-  if ((rc = upload_vec(mem, B.idx, &t.idx, &by))) return rc;
+  if (B.idx.size() >= (size_t)kPV) {
+    if ((rc = upload_vec(mem, B.idx, &t.idx, &by))) return rc;
+  } else {
+    // at least one group: a wavefront without chunks reads group 0
+    std::vector<uint16_t> ix(B.idx);
+    ix.resize(kPV, (uint16_t)B.W);
+    if ((rc = upload_vec(mem, ix, &t.idx, &by))) return rc;
+  }
   if ((rc = upload_vec(mem, B.chunks, &t.chunks, &by))) return rc;
-  if ((rc = upload_vec(mem, B.seg_out, &t.seg_out, &by))) return rc;
+  {
+    // A trailing -1 entry: the slot the index stream reads for lanes and
+    // chunks that write no output.
+    std::vector<int32_t> so(B.seg_out);
+    so.push_back(-1);
+    if ((rc = upload_vec(mem, so, &t.seg_out, &by))) return rc;
+    t.no_slot = (int32_t)B.seg_out.size();
+  }
   if ((rc = upload_vec(mem, B.wg_panel, &t.wg_panel, &by))) return rc;
   if ((rc = upload_vec(mem, B.wave_c, &t.wave_c, &by))) return rc;
   if ((rc = upload_vec(mem, B.wg_s0, &t.wg_s0, &by))) return rc;

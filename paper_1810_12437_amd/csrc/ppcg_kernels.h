@@ -29,7 +29,8 @@ constexpr int kMaxRedBlocks = 1024; // max workgroups of a p-vector phase
 struct PanelPass {
   const uint16_t* idx;      // [stream] panel-local gathered index (padded)
   const ChunkDesc* chunks;  // [nchunks]
-  const int32_t* seg_out;   // [entries] output slot = panel * out_dim + segment id
+  const int32_t* seg_out;   // [entries + 1] output slot = panel * out_dim + segment id;
+                            // entry no_slot (the last) is -1: no output
   const int32_t* wg_panel;  // [nwg]
   const int32_t* wave_c;    // [kPWaves * nwg + 1]
   const int32_t* wg_s0;     // [nwg] gathered entries [s0, s1) the workgroup owns
@@ -40,6 +41,7 @@ struct PanelPass {
   int32_t nwg;
   int32_t nchunks;
   int32_t npieces;
+  int32_t no_slot;          // index of seg_out's trailing -1 entry
 };
 
 // value(i) = scale[i es] * (sum_k part[k * stride + i es] + sum of the pieces

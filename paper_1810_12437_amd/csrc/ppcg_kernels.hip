@@ -133,6 +133,31 @@ __device__ __forceinline__ T combine_at(const Combine<T>& c, int64_t i, int r = 
 }
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// LDS address of the entry in the low / high 16 bits of w, for ES-byte
+// entries of a panel at LDS address lds0: the 16-bit half times ES plus lds0
+// in one multiply-add.
+template <int ES>
+__device__ __forceinline__ uint32_t lo_addr(uint32_t w, uint32_t lds0) {
+  uint32_t r;
+  asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(w), "n"(ES), "s"(lds0));
+  return r;
+}
+template <int ES>
+__device__ __forceinline__ uint32_t hi_addr(uint32_t w, uint32_t lds0) {
+  uint32_t r;
+  asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(r) : "v"(w), "n"(ES), "s"(lds0));
+  return r;
+}
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(size_t)(const lds_u8*)p;
+}
+template <typename T>
+__device__ __forceinline__ T lds_load(uint32_t addr) {
+  return *(const __attribute__((address_space(3))) T*)(size_t)addr;
+}
 
 __device__ __forceinline__ int ck_windows(int32_t info) { return info & 0xff; }
 __device__ __forceinline__ int ck_kind(int32_t info) { return (info >> 8) & 3; }
@@ -161,51 +186,89 @@ constexpr int kDppRowShr = 0x110;   // row_shr:n = 0x110 + n (within 16-lane row
 constexpr int kDppBcast15 = 0x142;  // lane 15 of each row to the next row
 constexpr int kDppBcast31 = 0x143;  // lane 31 to rows 2 and 3
 
-// This lane's groups in the first kPR windows of a chunk: bit s of `has` is
-// set when the lane has a group in window s, at element base + rel[s].
-struct LaneWindows {
-  int32_t rel[kPR];
-  uint32_t has;
+// Chunk descriptors are read-only for the whole pass: read them through the
+// constant address space, so that the uniform reads are scalar loads even
+// after the pass has written outputs.
+__device__ __forceinline__ ChunkDesc read_desc(const ChunkDesc* p, int c) {
+  typedef const __attribute__((address_space(4))) ChunkDesc ConstDesc;
+  ConstDesc* q = (ConstDesc*)p + c;
+  ChunkDesc D;
+  D.base = q->base;
+#pragma unroll
+  for (int s = 0; s < kPR; ++s) D.vm[s] = q->vm[s];
+  D.sm = q->sm;
+  D.first = q->first;
+  D.info = q->info;
+  D.seg = q->seg;
+  return D;
+}
+
+// Load cursor of a wavefront's index stream: window k of chunk c.  Every
+// step issues the same three loads (the window's two halves and the output
+// slot of its chunk for this lane), with in-bounds stand-ins for lanes that
+// have no group in the window and for steps past the wavefront's last
+// window, so that the wait before a window's sums covers its own loads only.
+struct StreamLoad {
+  int32_t c, k, pre, windows, kind;
+  int32_t sidx;        // this lane's seg_out entry for chunk c (no_slot: none)
+  int64_t base, clen, last_base;
+  uint64_t vm0, vm1, vm2, vm3;
 };
 
-__device__ __forceinline__ void lane_windows(const ChunkDesc& D, int lane, LaneWindows& L) {
-  L.has = 0;
-  if (ck_kind(D.info) == kChunkPacked) {
-    int pre = 0;
-#pragma unroll
-    for (int s = 0; s < kPR; ++s) {
-      const uint64_t m = D.vm[s];
-      L.rel[s] = (pre + bits_below(m)) * kPV;
-      if ((m >> lane) & 1ull) L.has |= 1u << s;
-      pre += __popcll(m);
-    }
+__device__ __forceinline__ void stream_open(const PanelPass& t, const ChunkDesc& D, int c,
+                                            int lane, StreamLoad& L) {
+  L.c = c;
+  L.k = 0;
+  L.pre = 0;
+  L.windows = ck_windows(D.info);
+  L.kind = ck_kind(D.info);
+  L.base = D.base;
+  L.last_base = D.base;
+  L.clen = (int64_t)D.vm[0];
+  L.vm0 = D.vm[0];
+  L.vm1 = D.vm[1];
+  L.vm2 = D.vm[2];
+  L.vm3 = D.vm[3];
+  if (L.kind == kChunkLong) {
+    L.sidx = D.first;
+  } else if (L.kind == kChunkPiece) {
+    L.sidx = t.no_slot;
   } else {
-#pragma unroll
-    for (int s = 0; s < kPR; ++s) {
-      L.rel[s] = s * kPC + lane * kPV;
-      if ((int64_t)L.rel[s] < (int64_t)D.vm[0]) L.has |= 1u << s;
-    }
+    // packed: the last lane of each segment's slice writes that segment
+    const uint64_t sm = D.sm;
+    const bool last = lane == 63 || ((sm >> (lane + 1)) & 1ull);
+    const int si = bits_below(sm) + (int)((sm >> lane) & 1ull) - 1;
+    L.sidx = (last && si < (D.info >> 24)) ? D.first + si : t.no_slot;
   }
 }
 
-__device__ __forceinline__ void load_window(const PanelPass& t, int64_t at, u16x8& a,
-                                            u16x8& b) {
-  // Read once per pass: non-temporal.
-  const u16x8* ip = reinterpret_cast<const u16x8*>(t.idx + at);
+// Issues the loads of the cursor's window into one ring slot and advances.
+// Bit `bit` of `have` tells whether this lane has a group in that window.
+__device__ __forceinline__ void stream_issue(const PanelPass& t, int c_end, int lane,
+                                             StreamLoad& L, u16x8& a, u16x8& b, int32_t& slot,
+                                             uint32_t& have, int bit) {
+  int64_t e = L.last_base;
+  int32_t si = t.no_slot;
+  bool h = false;
+  if (L.c < c_end) {
+    if (L.kind == kChunkPacked) {
+      const uint64_t m = L.k == 0 ? L.vm0 : L.k == 1 ? L.vm1 : L.k == 2 ? L.vm2 : L.vm3;
+      h = ((m >> lane) & 1ull) != 0;
+      e = h ? L.base + (int64_t)(L.pre + bits_below(m)) * kPV : L.base;
+      L.pre += __popcll(m);
+    } else {
+      const int64_t rel = (int64_t)L.k * kPC + lane * kPV;
+      h = rel < L.clen;
+      e = h ? L.base + rel : L.base;
+    }
+    si = L.sidx;
+    if (++L.k == L.windows && ++L.c < c_end) stream_open(t, read_desc(t.chunks, L.c), L.c, lane, L);
+  }
+  const u16x8* ip = reinterpret_cast<const u16x8*>(t.idx + e);
   a = __builtin_nontemporal_load(ip);
   b = __builtin_nontemporal_load(ip + 1);
-}
-
-// Output slot of this lane for chunk D: packed chunks write from the last
-// lane of each segment's slice, long chunks from lane 63; -1: no write.
-__device__ __forceinline__ int32_t out_slot(const PanelPass& t, const ChunkDesc& D, int lane) {
-  const int kind = ck_kind(D.info);
-  if (kind == kChunkLong) return t.seg_out[D.first];
-  if (kind == kChunkPiece) return -1;
-  const uint64_t sm = D.sm;
-  const bool last = lane == 63 || ((sm >> (lane + 1)) & 1ull);
-  const int si = bits_below(sm) + (int)((sm >> lane) & 1ull) - 1;
-  return (last && si < (D.info >> 24)) ? t.seg_out[D.first + si] : -1;
+  slot = t.seg_out[si];
+  have = (have & ~(1u << bit)) | ((h ? 1u : 0u) << bit);
 }
 
 // K values of one panel entry (the K vectors of an interleaved set).
@@ -220,18 +283,25 @@ template <typename T, int K>
 __device__ __forceinline__ void gather_add16(const T* xl, const u16x8& a, const u16x8& b,
                                              T (&acc)[K]) {
   if constexpr (K == 1) {
-    // two halves of eight gathers in flight (the sum runs in element order)
-    T v[8];
+    // All sixteen gathers in flight, then a pairwise sum.  Each index dword
+    // holds two 16-bit entries: one multiply-add of a half by the entry size
+    // gives its LDS byte offset.
+    const u32x4 da = __builtin_bit_cast(u32x4, a), db = __builtin_bit_cast(u32x4, b);
+    const uint32_t l0 = __builtin_amdgcn_readfirstlane(lds_addr(xl));
+    T v[16];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = xl[a[j]];
-    T s = v[0];
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t wa = da[j], wb = db[j];
+      v[2 * j] = lds_load<T>(lo_addr<sizeof(T)>(wa, l0));
+      v[2 * j + 1] = lds_load<T>(hi_addr<sizeof(T)>(wa, l0));
+      v[8 + 2 * j] = lds_load<T>(lo_addr<sizeof(T)>(wb, l0));
+      v[8 + 2 * j + 1] = lds_load<T>(hi_addr<sizeof(T)>(wb, l0));
+    }
 #pragma unroll
-    for (int j = 1; j < 8; ++j) s += v[j];
+    for (int w = 1; w < 16; w *= 2)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = xl[b[j]];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) s += v[j];
-    acc[0] += s;
+      for (int j = 0; j < 16; j += 2 * w) v[j] += v[j + w];
+    acc[0] += v[0];
   } else {
     const PanelEntry<T, K>* xp = reinterpret_cast<const PanelEntry<T, K>*>(xl);
     T s[K];
@@ -313,6 +383,98 @@ __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T (&acc)
   }
 }
 
+// ---- panel assembly, FP64 single-vector fast paths ----
+template <typename T, int K>
+constexpr bool kFastPanel = sizeof(T) == 8 && K == 1;
+constexpr int kAsmPairs = 10;  // 16-byte loads per thread: kPThreads * 2 * 10 >= W
+
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return ((uintptr_t)p & 15u) == 0;
+}
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// Pair u of thread tid of a panel assembly: pair tid + b kPThreads of block
+// b = (u + w) mod nb (nb blocks of kPThreads pairs), so that the workgroups
+// of one XCD start on different blocks; -1 past the end.
+__device__ __forceinline__ int asm_pair(int u, int tid, int rb, int nb, int npairs) {
+  int b = u + rb;
+  b = b >= nb ? b - nb : b;
+  const int pl = tid + b * kPThreads;
+  return (u < nb && pl < npairs) ? pl : -1;
+}
+
+// Panel of s = z + bc s_old (FP64; zp, sp at the panel's first entry): pair
+// i is entries 2i, 2i+1.  All loads are issued (stand-ins past the end)
+// before any is waited for: the first half's sums go to LDS, the ring is
+// primed, then the second half.  An odd last entry is read by every thread
+// and stored by thread 0.  (The workgroup's own entries go to s_new after
+// the pass, from LDS.)  Returns false (nothing done) when the panel is not
+// 16-byte aligned or shorter than two entries.
+template <typename PRIME>
+__device__ __forceinline__ bool assemble_dir_fast(const double* zp, const double* sp, double bc,
+                                                  int wlen, int w, double* xl, PRIME& prime) {
+  const int npairs = wlen >> 1;
+  if (npairs < 1 || !aligned16(zp) || !aligned16(sp)) return false;
+  const int nb = (npairs + kPThreads - 1) / kPThreads;
+  const int rb = w % nb;
+  const int tid = threadIdx.x;
+  f64x2 zv[kAsmPairs], sv[kAsmPairs];
+  int pi[kAsmPairs];
+#pragma unroll
+  for (int u = 0; u < kAsmPairs; ++u) {
+    pi[u] = asm_pair(u, tid, rb, nb, npairs);
+    const int at = pi[u] >= 0 ? 2 * pi[u] : 0;
+    zv[u] = *reinterpret_cast<const f64x2*>(zp + at);
+    sv[u] = *reinterpret_cast<const f64x2*>(sp + at);
+  }
+  const int last = wlen - 1;  // the odd entry, when wlen is odd
+  const double zt = zp[last], st = sp[last];
+  auto form = [&](double z, double so) { return bc == 0.0 ? z : z + bc * so; };
+#pragma unroll
+  for (int u = 0; u < kAsmPairs / 2; ++u) {
+    if (pi[u] >= 0) {
+      xl[2 * pi[u]] = form(zv[u].x, sv[u].x);
+      xl[2 * pi[u] + 1] = form(zv[u].y, sv[u].y);
+    }
+  }
+  prime();
+#pragma unroll
+  for (int u = kAsmPairs / 2; u < kAsmPairs; ++u) {
+    if (pi[u] >= 0) {
+      xl[2 * pi[u]] = form(zv[u].x, sv[u].x);
+      xl[2 * pi[u] + 1] = form(zv[u].y, sv[u].y);
+    }
+  }
+  if ((wlen & 1) && tid == 0) xl[last] = form(zt, st);
+  return true;
+}
+
+// Panel copied from src (FP64, one vector), the same way.
+template <typename PRIME>
+__device__ __forceinline__ bool assemble_copy_fast(const double* src, int wlen, int w, double* xl,
+                                                   PRIME& prime) {
+  const int npairs = wlen >> 1;
+  if (npairs < 1 || !aligned16(src)) return false;
+  const int nb = (npairs + kPThreads - 1) / kPThreads;
+  const int rb = w % nb;
+  const int tid = threadIdx.x;
+  f64x2 v[kAsmPairs];
+  int pi[kAsmPairs];
+#pragma unroll
+  for (int u = 0; u < kAsmPairs; ++u) {
+    pi[u] = asm_pair(u, tid, rb, nb, npairs);
+    v[u] = *reinterpret_cast<const f64x2*>(src + (pi[u] >= 0 ? 2 * pi[u] : 0));
+  }
+  const int last = wlen - 1;
+  const double vt = src[last];
+  prime();
+#pragma unroll
+  for (int u = 0; u < kAsmPairs; ++u)
+    if (pi[u] >= 0) *reinterpret_cast<f64x2*>(xl + 2 * pi[u]) = v[u];
+  if ((wlen & 1) && tid == 0) xl[last] = vt;
+  return true;
+}
+
 // Workgroup w of one X pass over K interleaved vectors (K = 1: one vector).
 // The pass is skipped when all ndone flags done[i * dstride] are set.  With
 // dir.z set the gathered panel is the new CG direction (DirIn); with dot.s
@@ -325,59 +487,82 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
                                            int dstride, const DirIn<T>& dir,
                                            const DotOut<T>& dot, int parity, int w) {
   constexpr bool dotting = MODE == kPassDot;
-  if (done != nullptr) {
-    bool all = true;
-    for (int i = 0; i < ndone; ++i) all = all && done[(int64_t)i * dstride] != 0;
-    if (all) return;
-  }
   extern __shared__ __align__(16) unsigned char smem[];
   T* xl = reinterpret_cast<T*>(smem);
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
-  // This wavefront's chunks, in order.
+  // What the start needs, requested together: this wavefront's chunk range
+  // and first descriptor, the panel, the stop flag(s) and the direction's
+  // ratio.
   int c = t.wave_c[kPWaves * w + wave];
   const int c_end = t.wave_c[kPWaves * w + wave + 1];
-
-  // Each window of a chunk has a register slot (window k in slot k % kPR);
-  // a slot is refilled as soon as its window has been summed, with the
-  // chunk's window k + kPR or else the next chunk's window in that slot.
-  u16x8 sa[kPR], sb[kPR];
-  int32_t cinfo = 0, cfirst = 0, slot = -1;
-  int64_t cbase = 0, clen = 0, cseg = -1;
-  uint64_t csm = 0;
-  uint32_t chas = 0;
-  if (c < c_end) {
-    const ChunkDesc D = t.chunks[c];
-    LaneWindows L;
-    lane_windows(D, lane, L);
-#pragma unroll
-    for (int s = 0; s < kPR; ++s)
-      if ((L.has >> s) & 1u) load_window(t, D.base + L.rel[s], sa[s], sb[s]);
-    cinfo = D.info;
-    cfirst = D.first;
-    cseg = D.seg;
-    cbase = D.base;
-    clen = (int64_t)D.vm[0];
-    csm = D.sm;
-    chas = L.has;
-    slot = out_slot(t, D, lane);
+  const int panel = t.wg_panel[w];
+  ChunkDesc D0{};
+  if (c < c_end) D0 = read_desc(t.chunks, c);
+  double bc0 = 0.0;
+  if constexpr (MODE == kPassDir && kFastPanel<T, K>) {
+    const DevScal& S = dir.sc[0];
+    bc0 = S.done ? 0.0 : S.betacg;
+  }
+  if (done != nullptr) {
+    bool all = true;
+    for (int i = 0; i < ndone; ++i) all = all && done[(int64_t)i * dstride] != 0;
+    if (all) return;
   }
 
-  const int panel = t.wg_panel[w];
+  // The wavefront's chunks as one stream of windows with kRing in flight:
+  // ring slot q % kRing holds window q.  The first kRing are requested while
+  // the panel is assembled, after the panel's own loads (the waits count in
+  // issue order), always kRing of them (stand-ins when the wavefront has no
+  // chunk: the index stream has at least kPV entries).
+  StreamLoad ld{};
+  u16x8 ra[kRing], rb[kRing];
+  int32_t rs[kRing];
+  uint32_t rh = 0;
+  auto prime = [&]() {
+    if (c < c_end) {
+      stream_open(t, D0, c, lane, ld);
+    } else {
+      ld.c = c_end;
+      ld.last_base = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kRing; ++q) stream_issue(t, c_end, lane, ld, ra[q], rb[q], rs[q], rh, q);
+  };
+
   const int64_t g0 = (int64_t)panel * t.W;
   const int64_t rem = t.gdim - g0;
   const int wlen = (int)(rem < t.W ? rem : t.W);
   // The panel of the gathered vector(s), assembled once per workgroup; entry
   // W holds the zeros the padding indices point to.  Eight loads in flight
-  // per thread before the LDS stores.
+  // per thread before the LDS stores.  Every workgroup reads the same
+  // entries: each starts at its own offset, so that at any moment the
+  // workgroups of one XCD touch different lines and later reads hit in L2.
+  const int64_t span = (int64_t)wlen * K;
+  const int rot = span > 0 ? (int)(((int64_t)w * 7919) % span) : 0;
   constexpr int U = 8;
   double p1acc[K], p2acc[K];
 #pragma unroll
   for (int r = 0; r < K; ++r) p1acc[r] = p2acc[r] = 0.0;
   const T* sdot = dotting ? dot.s + (int64_t)(1 - parity) * dot.sstride : nullptr;
   const int64_t pofs = (int64_t)panel * t.out_dim;
-  if constexpr (MODE == kPassDir) {
+  bool assembled = false;
+  if constexpr (kFastPanel<T, K>) {
+    // FP64, one vector: every thread's 16-byte loads issued at once, then
+    // the ring's first windows, then the LDS stores.
+    if constexpr (MODE == kPassDir) {
+      const T* s_old = dir.s + (int64_t)parity * dir.sstride;
+      assembled = assemble_dir_fast(dir.z + g0, s_old + g0, bc0, wlen, w, xl, prime);
+    } else if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr &&
+               xin.es == 1) {
+      assembled = assemble_copy_fast(xin.part + g0, wlen, w, xl, prime);
+    }
+  }
+  if (assembled) {
+    // panel done (the ring is primed)
+  } else if constexpr (MODE == kPassDir) {
+    prime();
     // s = z + bc s_old per vector (s = z right after a start: bc = 0), into
     // the panel; the workgroup's own entries also go to s_new and <s, d s>.
     double bc[K];
@@ -391,15 +576,17 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
     T* s_new = dir.s + (int64_t)(1 - parity) * dir.sstride;
     const int64_t o0 = t.wg_s0[w], o1 = t.wg_s1[w];
     constexpr int UE = K >= 4 ? 1 : 8 / K;
+    const int rotj = rot / K;
     for (int j0 = threadIdx.x; j0 < wlen; j0 += kPThreads * UE) {
       T v[UE][K];
 #pragma unroll
       for (int u = 0; u < UE; ++u) {
-        const int j = j0 + u * kPThreads;
+        const int jl = j0 + u * kPThreads;
+        const int j = jl + rotj < wlen ? jl + rotj : jl + rotj - wlen;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
           v[u][r] = T(0);
-          if (j < wlen) {
+          if (jl < wlen) {
             const int64_t e = (g0 + j) * K + r;
             v[u][r] = bc[r] == 0.0 ? (T)dir.z[e] : (T)(dir.z[e] + bc[r] * (double)s_old[e]);
           }
@@ -407,8 +594,9 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       }
 #pragma unroll
       for (int u = 0; u < UE; ++u) {
-        const int j = j0 + u * kPThreads;
-        if (j < wlen) {
+        const int jl = j0 + u * kPThreads;
+        const int j = jl + rotj < wlen ? jl + rotj : jl + rotj - wlen;
+        if (jl < wlen) {
           const bool own = g0 + j >= o0 && g0 + j < o1;
 #pragma unroll
           for (int r = 0; r < K; ++r) {
@@ -423,109 +611,120 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       }
     }
   } else if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr && xin.es == K) {
+    prime();
     const T* src = xin.part + g0 * K;
     const int cnt = wlen * K;
     for (int j0 = threadIdx.x; j0 < cnt; j0 += kPThreads * U) {
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int j = j0 + u * kPThreads;
-        v[u] = (j < cnt) ? src[j] : T(0);
+        const int jl = j0 + u * kPThreads;
+        const int j = jl + rot < cnt ? jl + rot : jl + rot - cnt;
+        v[u] = (jl < cnt) ? src[j] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int j = j0 + u * kPThreads;
-        if (j < cnt) xl[j] = v[u];
+        const int jl = j0 + u * kPThreads;
+        const int j = jl + rot < cnt ? jl + rot : jl + rot - cnt;
+        if (jl < cnt) xl[j] = v[u];
       }
     }
   } else {
+    prime();
     constexpr int UC = 2;  // (each value already has up to eight partial loads in flight)
     const int cnt = wlen * K;
     for (int j0 = threadIdx.x; j0 < cnt; j0 += kPThreads * UC) {
       T v[UC];
 #pragma unroll
       for (int u = 0; u < UC; ++u) {
-        const int j = j0 + u * kPThreads;
-        v[u] = (j < cnt) ? combine_at(xin, g0 + j / K, j % K) : T(0);
+        const int jl = j0 + u * kPThreads;
+        const int j = jl + rot < cnt ? jl + rot : jl + rot - cnt;
+        v[u] = (jl < cnt) ? combine_at(xin, g0 + j / K, j % K) : T(0);
       }
 #pragma unroll
       for (int u = 0; u < UC; ++u) {
-        const int j = j0 + u * kPThreads;
-        if (j < cnt) xl[j] = v[u];
+        const int jl = j0 + u * kPThreads;
+        const int j = jl + rot < cnt ? jl + rot : jl + rot - cnt;
+        if (jl < cnt) xl[j] = v[u];
       }
     }
   }
   if (threadIdx.x < K) xl[(int64_t)t.W * K + threadIdx.x] = T(0);
   __syncthreads();
 
+  // Compute cursor: window k of chunk c, in ring slot q; each step sums its
+  // window, refills the slot with the window kRing ahead and, after a chunk's
+  // last window, writes the chunk's sums.
+  int32_t cinfo = 0, cfirst = 0, slot = -1;
+  int64_t cseg = -1;
+  uint64_t csm = 0;
+  int k = 0;
+  T acc[K], scl[K], sd[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) acc[r] = scl[r] = sd[r] = T(0);
+  if (c < c_end) {
+    const ChunkDesc D = read_desc(t.chunks, c);
+    cinfo = D.info;
+    cfirst = D.first;
+    cseg = D.seg;
+    csm = D.sm;
+  }
+  // Every step refills its slot, also past the last window, so that between
+  // a slot's refill and its next use the other kRing - 1 slots are always
+  // refilled too: the wait before a window's sums then leaves the loads of
+  // the windows after it in flight.
   while (c < c_end) {
-    const int cn = c + 1;
-    int32_t ninfo = 0, nfirst = 0, slot_n = -1;
-    int64_t nbase = 0, nlen = 0, nseg = -1;
-    uint64_t nsm = 0;
-    LaneWindows LN;
-    LN.has = 0;
-    if (cn < c_end) {
-      const ChunkDesc N = t.chunks[cn];
-      lane_windows(N, lane, LN);
-      ninfo = N.info;
-      nfirst = N.first;
-      nseg = N.seg;
-      nbase = N.base;
-      nlen = (int64_t)N.vm[0];
-      nsm = N.sm;
-      slot_n = out_slot(t, N, lane);
-    }
-    const int R = ck_windows(cinfo);
-    T scl[K], sd[K];
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-      scl[r] = (out_scale != nullptr && slot >= 0) ? out_scale[(int64_t)slot * K + r] : T(1);
-      sd[r] = T(0);
-    }
-    if constexpr (dotting) {
-      // the output column of this lane (the piece's column for a piece)
-      const int64_t jd = ck_kind(cinfo) == kChunkPiece ? cseg : (slot >= 0 ? slot - pofs : -1);
-      if (jd >= 0) {
+    for (int q = 0; q < kRing; ++q) {
+      const bool live = c < c_end;
+      if (live) {
+        if (k == 0) {
+          // chunk start: its output slot (from the ring), scale and dot factor
+          slot = rs[q];
 #pragma unroll
-        for (int r = 0; r < K; ++r) sd[r] = sdot[jd * K + r];
-      }
-    }
-    // Slots this chunk leaves unused take the next chunk's windows now.
-#pragma unroll
-    for (int s = 0; s < kPR; ++s)
-      if (s >= R && ((LN.has >> s) & 1u)) load_window(t, nbase + LN.rel[s], sa[s], sb[s]);
-    T acc[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) acc[r] = T(0);
-    for (int kb = 0; kb < R; kb += kPR) {
-#pragma unroll
-      for (int s = 0; s < kPR; ++s) {
-        const int k = kb + s;
-        if (k < R) {
-          const bool have = (k < kPR) ? ((chas >> s) & 1u) != 0
-                                      : (int64_t)k * kPC + lane * kPV < clen;
-          if (have) gather_add16<T, K>(xl, sa[s], sb[s], acc);
-          if (k + kPR < R) {
-            const int64_t e = (int64_t)(k + kPR) * kPC + lane * kPV;
-            if (e < clen) load_window(t, cbase + e, sa[s], sb[s]);
-          } else if ((LN.has >> s) & 1u) {
-            load_window(t, nbase + LN.rel[s], sa[s], sb[s]);
+          for (int r = 0; r < K; ++r) {
+            scl[r] = (out_scale != nullptr && slot >= 0) ? out_scale[(int64_t)slot * K + r] : T(1);
+            sd[r] = T(0);
           }
+          if constexpr (dotting) {
+            const int64_t jd =
+                ck_kind(cinfo) == kChunkPiece ? cseg : (slot >= 0 ? slot - pofs : -1);
+            if (jd >= 0) {
+#pragma unroll
+              for (int r = 0; r < K; ++r) sd[r] = sdot[jd * K + r];
+            }
+          }
+        }
+        if ((rh >> q) & 1u) gather_add16<T, K>(xl, ra[q], rb[q], acc);
+      }
+      stream_issue(t, c_end, lane, ld, ra[q], rb[q], rs[q], rh, q);
+      if (live && ++k == ck_windows(cinfo)) {
+        finish_chunk<T, K, dotting>(cinfo, csm, acc, slot, scl, cfirst, lane, part_out, piece_out,
+                                    out_scale, sd, p2acc);
+#pragma unroll
+        for (int r = 0; r < K; ++r) acc[r] = T(0);
+        k = 0;
+        if (++c < c_end) {
+          const ChunkDesc D = read_desc(t.chunks, c);
+          cinfo = D.info;
+          cfirst = D.first;
+          cseg = D.seg;
+          csm = D.sm;
         }
       }
     }
-    finish_chunk<T, K, dotting>(cinfo, csm, acc, slot, scl, cfirst, lane, part_out, piece_out,
-                                out_scale, sd, p2acc);
-    cinfo = ninfo;
-    cfirst = nfirst;
-    cseg = nseg;
-    cbase = nbase;
-    clen = nlen;
-    csm = nsm;
-    chas = LN.has;
-    slot = slot_n;
-    c = cn;
+  }
+  if constexpr (MODE == kPassDir && kFastPanel<T, K>) {
+    if (assembled) {
+      // the workgroup's own entries of the new direction, from the panel
+      const int64_t o0 = t.wg_s0[w], o1 = t.wg_s1[w];
+      T* s_new = dir.s + (int64_t)(1 - parity) * dir.sstride;
+      for (int64_t j = o0 + threadIdx.x; j < o1; j += kPThreads) {
+        const double v = xl[j - g0];
+        s_new[j] = v;
+        p1acc[0] += dir.d[j] * v * v;
+      }
+    }
   }
   if constexpr (MODE != kPassPlain) {
     // The workgroup's partials, in a fixed order: lanes, then wavefronts
@@ -606,7 +805,8 @@ static int pass_mode(const DirIn<T>* dir, const DotOut<T>* dot) {
 // besides the plain pass: the workgroup slices and the output dimension.
 template <typename T>
 static bool pass_args_ok(const PanelPass& t, const DirIn<T>* dir, const DotOut<T>* dot) {
-  if (t.idx == nullptr || t.chunks == nullptr || t.wave_c == nullptr || t.wg_panel == nullptr)
+  if (t.idx == nullptr || t.chunks == nullptr || t.wave_c == nullptr || t.wg_panel == nullptr ||
+      t.seg_out == nullptr || t.no_slot < 0)
     return false;
   if (dir != nullptr && dir->z != nullptr &&
       (t.wg_s0 == nullptr || t.wg_s1 == nullptr || dir->s == nullptr || dir->d == nullptr ||

@@ -11,10 +11,20 @@ constexpr int kPThreads = kPWaves * 64;
 constexpr int kPV = 16;                // elements per lane in one window (one group)
 constexpr int kPC = 64 * kPV;          // window: the elements one wavefront reads at once
 constexpr int kPR = 4;                 // windows of a packed chunk
+constexpr int kRing = 4;               // windows a pass wavefront has in flight
 constexpr int kPLongWin = 16;          // most windows of a long chunk
 constexpr int kPLongMax = kPLongWin * kPC;  // longest segment one wavefront sums whole
 constexpr int kPanelBytes = 160 * 1024 - 64;  // LDS for the gathered panel (+ zero slot)
 // (after the pass, the same LDS holds the workgroup's partial-sum reduction)
+
+// Relative work of the wavefronts of a pass workgroup by rank.  Wavefront q
+// runs on SIMD q % 4 as the (q / 4)-th oldest of its four, and the SIMD's
+// arbiter issues the older ones first: given equal shares, the youngest end
+// about 40 % after the oldest.  The chunk lists give each rank a share in
+// proportion to its issue rate measured with equal shares, so that all
+// sixteen end together.
+constexpr double kWaveRankWeight[4] = {1.0, 0.91, 0.80, 0.72};
+inline double wave_weight(int q) { return kWaveRankWeight[(q % kPWaves) / 4]; }
 
 enum ChunkKind { kChunkPacked = 0, kChunkLong = 1, kChunkPiece = 2 };
 

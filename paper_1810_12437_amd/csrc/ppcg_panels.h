@@ -81,6 +81,48 @@ struct Packer {
   }
 };
 
+
+// LDS banks of a gathered entry: the panel holds elem-byte values, so entry i
+// starts at dword i * elem / 4 of 64 four-byte banks; a gather instruction
+// reads one entry per lane, and lanes of one half-wavefront that hit the same
+// bank at different entries are served one after the other.
+inline int entry_bank(int i, int elem) { return (int)(((int64_t)i * (elem / 4)) & 63) >> (elem == 8 ? 1 : 0); }
+
+// Orders the kPV entries of each group of one window (lanes[g] is the lane
+// of group g, grp[g] its entries) so that, instruction by instruction, the
+// lanes of each half-wavefront read entries of different banks where they
+// can: a greedy pass over the positions, each lane taking the remaining
+// entry whose bank is least used at that position.  Only the order in which
+// a lane sums its group changes.
+inline void spread_window(uint16_t* const* grp, const int* lanes, int ngroups, int elem,
+                          uint16_t sentinel) {
+  const int nb = elem == 8 ? 32 : 64;
+  for (int pos = 0; pos < kPV; ++pos) {
+    int cnt[2][64] = {};
+    int seen_e[2][64];  // one distinct entry per bank counts once per repeat
+    for (int h = 0; h < 2; ++h)
+      for (int b = 0; b < 64; ++b) seen_e[h][b] = -1;
+    for (int g = 0; g < ngroups; ++g) {
+      uint16_t* e = grp[g];
+      const int h = lanes[g] >> 5;
+      int best = pos, best_cost = 1 << 30;
+      for (int q = pos; q < kPV; ++q) {
+        const int b = entry_bank(e[q], elem) % nb;
+        const int cost = (e[q] == sentinel || seen_e[h][b] == (int)e[q]) ? -1 : cnt[h][b];
+        if (cost < best_cost) {
+          best_cost = cost;
+          best = q;
+        }
+      }
+      std::swap(e[pos], e[best]);
+      if (e[pos] != sentinel) {
+        const int b = entry_bank(e[pos], elem) % nb;
+        if (seen_e[h][b] != (int)e[pos]) cnt[h][b]++;
+        seen_e[h][b] = e[pos];
+      }
+    }
+  }
+}
 }  // namespace detail
 
 // off: segment offsets (out_dim + 1), gidx: gathered index of each element
@@ -95,9 +137,10 @@ struct Packer {
 // one longer than that is cut into pieces whose sums the consumer adds.
 // Each panel gets workgroups in proportion to its windows; every wavefront
 // of them gets an explicit chunk list: long chunks first (least loaded
-// wavefront first), then packed chunks up to an equal share of windows, the
-// last chunk of a share built with fewer windows (from the shortest entries
-// when the longest do not fit in fewer) to end on the share.
+// wavefront per unit of weight first), then packed chunks up to its share of
+// windows (in proportion to wave_weight), the last chunk of a share built
+// with fewer windows (from the shortest entries when the longest do not fit
+// in fewer) to end on the share.
 inline void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& gidx,
                          int64_t out_dim, int64_t gdim, int elem, int ncu, PanelBuild& B) {
   using detail::Entry;
@@ -206,6 +249,16 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
     const int nwv = kPWaves * g_k[k];
     std::vector<std::vector<ChunkDesc>> lists(nwv);
     std::vector<int64_t> load(nwv, 0);
+    // shares by rank (wave_weight): cumulative weights, and the wavefront
+    // with the least load per unit of weight
+    std::vector<double> cumw(nwv + 1, 0.0);
+    for (int q = 0; q < nwv; ++q) cumw[q + 1] = cumw[q] + wave_weight(q);
+    auto least_loaded = [&]() {
+      int best = 0;
+      for (int q = 1; q < nwv; ++q)
+        if ((double)load[q] / wave_weight(q) < (double)load[best] / wave_weight(best)) best = q;
+      return best;
+    };
     // long entries: least loaded wavefront first
     for (const Entry& en : ent[k]) {
       if (en.g <= packed_max) continue;
@@ -224,7 +277,7 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
         d.seg = en.slot % out_dim;
         d.info = chunk_info(win, pieces ? kChunkPiece : kChunkLong, 0, 0, 0, 1);
         for (int64_t q = o; q < oe; q += kPV) append_group(q, std::min<int64_t>(q + kPV, oe), glo);
-        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        const int q = least_loaded();
         lists[q].push_back(d);
         load[q] += win;
       }
@@ -284,10 +337,10 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
       B.seg_out.resize(seg0);
       P.lo = 0;
       P.hi = P.order.size();
-      const double share = (double)total / nwv;
+      const double per_w = (double)total / cumw[nwv];
       for (int q = 0; q < nwv && !P.empty(); ++q) {
         const int64_t target =
-            (int64_t)std::llround(share * (q + 1)) - (int64_t)std::llround(share * q);
+            (int64_t)std::llround(per_w * cumw[q + 1]) - (int64_t)std::llround(per_w * cumw[q]);
         while (!P.empty() && load[q] < target) {
           int R = (int)std::min<int64_t>(kPR, target - load[q]);
           R = std::max(R, P.min_windows());
@@ -299,14 +352,16 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
       bool leftover = false;
       while (!P.empty()) {  // what the share missed: least loaded wavefront
         leftover = true;
-        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        const int q = least_loaded();
         const ChunkDesc d = make_packed(kPR);
         lists[q].push_back(d);
         load[q] += detail::chunk_cost(d);
       }
       const int64_t used = std::accumulate(load.begin(), load.end(), (int64_t)0);
-      const int64_t worst = *std::max_element(load.begin(), load.end());
-      if (!leftover && worst <= (used + nwv - 1) / nwv + 1) break;
+      double excess = 0.0;  // most windows any wavefront has above its share
+      for (int q = 0; q < nwv; ++q)
+        excess = std::max(excess, (double)load[q] - (double)used * wave_weight(q) / cumw[nwv]);
+      if (!leftover && excess <= 2.0) break;
       total = used;
     }
     const int64_t e0 = glo, e1 = std::min<int64_t>(glo + B.W, gdim);
@@ -317,6 +372,39 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
       for (int q = 0; q < kPWaves; ++q) {
         for (const ChunkDesc& d : lists[g * kPWaves + q]) B.chunks.push_back(d);
         B.wave_c.push_back((int32_t)B.chunks.size());
+      }
+    }
+  }
+
+  // 5. bank-spread order within the groups of every window
+  {
+    uint16_t* grp[64];
+    int lanes[64];
+    const uint16_t sentinel = (uint16_t)B.W;
+    for (const ChunkDesc& d : B.chunks) {
+      const int R = d.info & 0xff;
+      if (((d.info >> 8) & 3) == kChunkPacked) {
+        int64_t at = d.base;
+        for (int kw = 0; kw < R; ++kw) {
+          int ng = 0;
+          for (int l = 0; l < 64; ++l)
+            if ((d.vm[kw] >> l) & 1ull) {
+              lanes[ng] = l;
+              grp[ng++] = &B.idx[at];
+              at += kPV;
+            }
+          detail::spread_window(grp, lanes, ng, elem, sentinel);
+        }
+      } else {
+        const int64_t groups = (int64_t)d.vm[0] / kPV;
+        for (int kw = 0; kw < R; ++kw) {
+          int ng = 0;
+          for (int l = 0; l < 64 && (int64_t)kw * 64 + l < groups; ++l) {
+            lanes[ng] = l;
+            grp[ng++] = &B.idx[d.base + ((int64_t)kw * 64 + l) * kPV];
+          }
+          detail::spread_window(grp, lanes, ng, elem, sentinel);
+        }
       }
     }
   }
