@@ -247,26 +247,35 @@ __device__ __forceinline__ void stream_open(const PanelPass& t, const ChunkDesc&
 __device__ __forceinline__ void stream_issue(const PanelPass& t, int c_end, int lane,
                                              StreamLoad& L, u16x8& a, u16x8& b, int32_t& slot,
                                              uint32_t& have, int bit) {
-  int64_t e = L.last_base;
+  constexpr int H = kPV / 2;
+  int64_t ea = L.last_base, eb = L.last_base;
   int32_t si = t.no_slot;
   bool h = false;
   if (L.c < c_end) {
+    // window start w0, its ng groups, this lane's rank r among them
+    int64_t w0;
+    int ng, r;
     if (L.kind == kChunkPacked) {
       const uint64_t m = L.k == 0 ? L.vm0 : L.k == 1 ? L.vm1 : L.k == 2 ? L.vm2 : L.vm3;
       h = ((m >> lane) & 1ull) != 0;
-      e = h ? L.base + (int64_t)(L.pre + bits_below(m)) * kPV : L.base;
-      L.pre += __popcll(m);
+      w0 = L.base + (int64_t)L.pre * kPV;
+      ng = __popcll(m);
+      r = bits_below(m);
+      L.pre += ng;
     } else {
-      const int64_t rel = (int64_t)L.k * kPC + lane * kPV;
-      h = rel < L.clen;
-      e = h ? L.base + rel : L.base;
+      w0 = L.base + (int64_t)L.k * kPC;
+      const int64_t left = (L.clen - (int64_t)L.k * kPC) / kPV;
+      ng = left < 64 ? (int)left : 64;
+      r = lane;
+      h = lane < ng;
     }
+    ea = h ? w0 + (int64_t)r * H : w0;
+    eb = h ? w0 + (int64_t)(ng + r) * H : w0;
     si = L.sidx;
     if (++L.k == L.windows && ++L.c < c_end) stream_open(t, read_desc(t.chunks, L.c), L.c, lane, L);
   }
-  const u16x8* ip = reinterpret_cast<const u16x8*>(t.idx + e);
-  a = __builtin_nontemporal_load(ip);
-  b = __builtin_nontemporal_load(ip + 1);
+  a = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(t.idx + ea));
+  b = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(t.idx + eb));
   slot = t.seg_out[si];
   have = (have & ~(1u << bit)) | ((h ? 1u : 0u) << bit);
 }

@@ -34,12 +34,16 @@ enum ChunkKind { kChunkPacked = 0, kChunkLong = 1, kChunkPiece = 2 };
 // a contiguous lane range (a slice) for the whole chunk: its groups of kPV
 // elements go to its lanes kPR at a time (group j on lane l0 + j / kPR in
 // window j % kPR), so a lane only ever sums elements of one segment.  Bit l
-// of vm[k] is set when lane l has a group in window k; the groups of window k
-// are stored consecutively in lane order.  Bit l of sm is set when lane l
-// starts a slice (lanes after the last segment form one idle slice).
+// of vm[k] is set when lane l has a group in window k; the ng groups of
+// window k follow those of the windows before it, stored as halves: the first
+// kPV / 2 entries of each group in lane order, then the second halves (the
+// lane of rank r reads entries r kPV/2 and (ng + r) kPV/2 of the window).  Bit
+// l of sm is set when lane l starts a slice (lanes after the last segment
+// form one idle slice).
 //
 // Long chunk: one segment (or, for a piece, a part of one) laid out as
-// consecutive windows of 64 groups; vm[0] holds its padded element count.
+// consecutive windows of 64 groups (the last one fewer), each stored as
+// halves the same way; vm[0] holds its padded element count.
 struct alignas(64) ChunkDesc {
   int64_t base;      // first element of the chunk in the index stream
   uint64_t vm[kPR];  // see above

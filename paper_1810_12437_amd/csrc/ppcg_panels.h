@@ -409,6 +409,37 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
     }
   }
 
+  // 6. each window's groups stored as halves: the first kPV / 2 entries of
+  // every group in lane order, then the second halves (one 16-byte load per
+  // lane then reads a contiguous block of the window)
+  {
+    std::vector<uint16_t> tmp;
+    auto split = [&](int64_t at, int ng) {
+      tmp.assign(B.idx.begin() + at, B.idx.begin() + at + (int64_t)ng * kPV);
+      const int h = kPV / 2;
+      for (int g = 0; g < ng; ++g)
+        for (int j = 0; j < h; ++j) {
+          B.idx[at + (int64_t)g * h + j] = tmp[(size_t)g * kPV + j];
+          B.idx[at + (int64_t)ng * h + (int64_t)g * h + j] = tmp[(size_t)g * kPV + h + j];
+        }
+    };
+    for (const ChunkDesc& d : B.chunks) {
+      const int R = d.info & 0xff;
+      if (((d.info >> 8) & 3) == kChunkPacked) {
+        int64_t at = d.base;
+        for (int kw = 0; kw < R; ++kw) {
+          const int ng = __builtin_popcountll(d.vm[kw]);
+          split(at, ng);
+          at += (int64_t)ng * kPV;
+        }
+      } else {
+        const int64_t groups = (int64_t)d.vm[0] / kPV;
+        for (int kw = 0; kw < R; ++kw)
+          split(d.base + (int64_t)kw * kPC, (int)std::min<int64_t>(64, groups - (int64_t)kw * 64));
+      }
+    }
+  }
+
   // pieces of the longest entries, grouped by output element
   if (!splits.empty()) {
     std::stable_sort(splits.begin(), splits.end(),
