@@ -96,6 +96,8 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
   dir.sc = X->sc;
   dir.scstride = 0;
   dir.p1 = X->p1[ti];
+  dir.sp = w.part;  // the row pass finishes each step (pass_finish below)
+  dir.nsb = vec_blocks(X->p);
   DotOut<T> dot{};
   dot.s = s;
   dot.sstride = X->p;
@@ -114,22 +116,26 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
     }
   }
   int parity = 0;
-  int32_t it0 = 0;  // the start kernel has set the iteration count to 0
+  int32_t it = 0;  // iteration of this phase (the start kernel left iteration 0's scalars)
   for (;;) {
-    for (int i = 0; i < o.check_every; ++i, parity ^= 1) {
+    const int32_t it_batch = it;
+    for (int i = 0; i < o.check_every; ++i, parity ^= 1, ++it) {
       hipEvent_t* e = (prof && i == sample) ? &X->ev[0] : nullptr;
-      // row pass forms s (buffer 1 - parity) from z and the old s
+      // row pass: finishes the previous step, forms s (buffer 1 - parity)
+      // from z and the old s
+      dir.it = it;
       PPCG_TRY_HIP(row_pass<T>(X, none, omegaT, done, st, e ? e[0] : nullptr,
                                e ? e[1] : nullptr, &dir, parity));
       PPCG_TRY_HIP(col_pass<T>(X, omegaT, nullptr, done, st, e ? e[2] : nullptr,
                                e ? e[3] : nullptr, &dot, parity));
-      PPCG_TRY_HIP(launch_cg_step<T>(w, s, X->p, parity, qsrc, X->d, X->m, X->beta64, X->r64,
-                                     X->z64, X->p1[ti], n1, X->p2[ti], n2, X->p, st));
+      PPCG_TRY_HIP(launch_cg_step<T>(w, s, X->p, parity, true, qsrc, X->d, X->m, X->beta64,
+                                     X->r64, X->z64, X->p1[ti], n1, X->p2[ti], n2, X->p, st));
     }
     PPCG_TRY_HIP(hipMemcpyAsync(X->h_sc, X->sc, sizeof(DevScal), hipMemcpyDeviceToHost, st));
     PPCG_TRY_HIP(hipStreamSynchronize(st));
-    // The sampled iteration counts only if it ran (later ones exit at once).
-    if (prof && X->h_sc->iters - it0 > sample) {
+    // The sampled iteration counts only if its passes ran: once the rule
+    // holds, the row pass of iteration iters and all later ones exit at once.
+    if (prof && (!X->h_sc->done || it_batch + sample < X->h_sc->iters)) {
       float a = 0.f, b = 0.f;
       PPCG_TRY_HIP(hipEventElapsedTime(&a, X->ev[0], X->ev[1]));
       PPCG_TRY_HIP(hipEventElapsedTime(&b, X->ev[2], X->ev[3]));
@@ -138,7 +144,6 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
       X->pass_cnt[0] += 1;
       X->pass_cnt[1] += 1;
     }
-    it0 = X->h_sc->iters;
     if (X->h_sc->done) return PPCG_OK;
   }
 }

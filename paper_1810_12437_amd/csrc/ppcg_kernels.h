@@ -77,6 +77,7 @@ struct DevScal {
   double true_meas;// rule measure of the FP64 true residual (squared)
   double true_rm;  // <r_t, M^-1 r_t> of the true residual
   double grad_sum; // reduction output of the adjoint epilogue
+  double rho_par[2]; // rho by iteration parity (row passes that finish the step)
   int32_t iters;
   int32_t done;
   int32_t status;
@@ -97,16 +98,26 @@ struct VecWork {
 // [wg_s0, wg_s1) of s and its part of <s, d s> (p1[w K + r]).  The two s
 // buffers are s and s + sstride (old / new by the launch's parity).  All
 // vectors are [dim][K] (K = 1: plain vectors).
+//
+// With sp set (one vector), the row pass also finishes the step before it:
+// the step kernel left per-block partials of <r, M^-1 r> and <r, r> (nsb
+// blocks, at sp + (1 - parity) * 2 * kMaxRedBlocks); every wavefront totals
+// them in the order of the step's own reduction, forms the ratio and applies
+// the stopping rule, and workgroup 0 records the scalars (iteration it of the
+// phase; it = 0: the start kernel left them, s = z).
 template <typename T>
 struct DirIn {
   const double* z;
   T* s;
   int64_t sstride;
   const double* d;
-  const DevScal* sc;  // vector r's scalars at sc + r * scstride
+  DevScal* sc;  // vector r's scalars at sc + r * scstride
   int32_t scstride;
   int32_t pad;
   double* p1;
+  const double* sp;
+  int32_t nsb;
+  int32_t it;
 };
 
 // Column pass of the CG loop: each workgroup also sums s_j times every
@@ -227,9 +238,11 @@ hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* q
 // (fixed order), alpha = rho / <s, Phi s>; q = qx + d .* s with qx from the
 // column pass's panel partials; beta += alpha s; r -= alpha q; z = M^-1 r;
 // rho' = <r, z> and the stopping rule.  s is the new direction (buffer
-// 1 - parity of s).
+// 1 - parity of s).  With pass_finish the kernel stops at the per-block
+// partials of rho' and <r, r> (in w.part + parity * 2 * kMaxRedBlocks) and the
+// next row pass finishes the step (DirIn.sp); otherwise its last block does.
 template <typename T>
-hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity,
+hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity, bool pass_finish,
                           const Combine<T>& qsrc, const double* d, const double* m,
                           double* beta, double* r, double* z, const double* p1, int32_t n1,
                           const double* p2, int32_t n2, int64_t p, hipStream_t st);

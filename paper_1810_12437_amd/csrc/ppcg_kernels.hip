@@ -43,6 +43,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// stopping rules and statuses (the values of ppcg.h)
+enum { kCritRelPrecond = 0, kCritRmsAbs = 1, kCritRelPlain = 2 };
+enum { kStatOK = 0, kStatNotConv = 4, kStatBreakdown = 5 };
+
+// wave_sum's total in every lane.
+__device__ __forceinline__ double wave_total(double v) { return __shfl(wave_sum(v), 0, 64); }
+
 // Fixed-order sum of NV values over the workgroup; result valid in thread 0.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV]) {
@@ -509,16 +516,68 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   const int panel = t.wg_panel[w];
   ChunkDesc D0{};
   if (c < c_end) D0 = read_desc(t.chunks, c);
-  double bc0 = 0.0;
-  if constexpr (MODE == kPassDir && kFastPanel<T, K>) {
-    const DevScal& S = dir.sc[0];
-    bc0 = S.done ? 0.0 : S.betacg;
+  // direction ratio per vector (a vector whose chain has stopped keeps s = z:
+  // its sums are unused)
+  double bc[K];
+  double fin_a = 0.0, fin_b = 0.0;  // the previous step's partials (pass-side finish)
+  if constexpr (MODE == kPassDir) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const DevScal& S = dir.sc[(int64_t)r * dir.scstride];
+      bc[r] = S.done ? 0.0 : S.betacg;
+    }
+    if (K == 1 && dir.sp != nullptr && dir.it > 0) {
+      const double* P = dir.sp + (int64_t)(1 - parity) * 2 * kMaxRedBlocks;
+      for (int q = lane; q < dir.nsb; q += 64) {
+        fin_a += P[2 * q];
+        fin_b += P[2 * q + 1];
+      }
+    }
   }
   if (done != nullptr) {
     bool all = true;
     for (int i = 0; i < ndone; ++i) all = all && done[(int64_t)i * dstride] != 0;
     if (all) return;
   }
+  if constexpr (MODE == kPassDir && K == 1) {
+    if (dir.sp != nullptr) {
+      if (dir.it == 0) {
+        bc[0] = 0.0;  // the start kernel's scalars: s = z
+      } else {
+        // totals in the order of the step kernel's own reduction
+        const double rho_new = wave_total(fin_a), rr = wave_total(fin_b);
+        DevScal* sc = dir.sc;
+        const double rho_old = sc->rho_par[1 - parity];
+        bc[0] = rho_new / rho_old;
+        const double meas = sc->criterion == kCritRelPlain ? rr : rho_new;
+        int stop = 0, status = kStatOK;
+        if (!isfinite(rho_new)) {
+          stop = 1;
+          status = kStatBreakdown;
+        } else if (meas <= sc->loop2) {
+          stop = 1;
+        } else if (dir.it >= sc->max_iter) {
+          stop = 1;
+          status = kStatNotConv;
+        }
+        if (w == 0 && threadIdx.x == 0) {
+          sc->iters = dir.it;
+          sc->rr = rr;
+          sc->meas = meas;
+          sc->betacg = bc[0];
+          sc->rho_prev = rho_old;
+          sc->rho = rho_new;
+          sc->rho_par[parity] = rho_new;
+          if (stop) {
+            sc->status = status;
+            sc->done = 1;
+          }
+        }
+        if (stop) return;
+      }
+    }
+  }
+  const double bc0 = bc[0];
 
   // The wavefront's chunks as one stream of windows with kRing in flight:
   // ring slot q % kRing holds window q.  The first kRing are requested while
@@ -574,13 +633,6 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
     prime();
     // s = z + bc s_old per vector (s = z right after a start: bc = 0), into
     // the panel; the workgroup's own entries also go to s_new and <s, d s>.
-    double bc[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-      // (a vector whose chain has stopped keeps s = z: its sums are unused)
-      const DevScal& S = dir.sc[(int64_t)r * dir.scstride];
-      bc[r] = S.done ? 0.0 : S.betacg;
-    }
     const T* s_old = dir.s + (int64_t)parity * dir.sstride;
     T* s_new = dir.s + (int64_t)(1 - parity) * dir.sstride;
     const int64_t o0 = t.wg_s0[w], o1 = t.wg_s1[w];
@@ -1205,8 +1257,6 @@ static inline unsigned red_grid(int64_t p) {
   return (unsigned)g;
 }
 
-enum { kCritRelPrecond = 0, kCritRmsAbs = 1, kCritRelPlain = 2 };
-enum { kStatOK = 0, kStatNotConv = 4, kStatBreakdown = 5 };
 
 // Mode 1 restarts only a run that ended well but whose FP64 true residual
 // misses the rule; any other run is left as it is.
@@ -1266,6 +1316,7 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
     sc->betacg = 0.0;  // the first row pass takes s = z
     sc->rho_prev = tot[0];
     sc->rho = tot[0];
+    sc->rho_par[0] = tot[0];
     sc->rr = tot[1];
     sc->meas = meas;
     sc->iters = 0;
@@ -1282,13 +1333,13 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
 
 // One CG step after the two passes (see launch_cg_step).  p1 / p2 hold the
 // passes' workgroup partials (n1 and n2 of them, stride ps).
-template <typename T>
+template <typename T, bool PassFinish = false>
 __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
                                              const Combine<T>& qsrc, const double* d,
                                              const double* m, double* beta, double* r,
                                              double* z, int zes, const double* p1, int n1,
                                              const double* p2, int n2, int ps, int64_t p,
-                                             VGrid g) {
+                                             VGrid g, int parity = 0) {
   DevScal* sc = w.sc;
   if (sc->done) return;
   // <s, Phi s> = <s, d s> + <s, X^T u>: the same fixed-order total in every
@@ -1326,6 +1377,19 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
     v[1] += rj * rj;
   }
   block_sum<2>(v);
+  if constexpr (PassFinish) {
+    // the next row pass totals these (see DirIn)
+    if (threadIdx.x == 0) {
+      double* out = w.part + (int64_t)parity * 2 * kMaxRedBlocks + 2 * g.bid;
+      out[0] = v[0];
+      out[1] = v[1];
+      if (g.bid == 0) {
+        sc->sq = sq;
+        sc->alpha = alpha;
+      }
+    }
+    return;
+  }
   if (!publish_and_arrive<2>(v, w.part, &w.sc->arrive[3], g)) return;
   double tot[2];
   gather_totals<2>(w.part, &w.sc->arrive[3], tot, g);
@@ -1369,6 +1433,15 @@ __global__ __launch_bounds__(kWG) void k_cg_step(VecWork w, const T* s, Combine<
                                                  int n1, const double* p2, int n2, int64_t p) {
   cg_step_body<T>(w, s, 1, qsrc, d, m, beta, r, z, 1, p1, n1, p2, n2, 1, p, own_grid());
 }
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_cg_step_pf(VecWork w, const T* s, Combine<T> qsrc,
+                                                    const double* d, const double* m,
+                                                    double* beta, double* r, double* z,
+                                                    const double* p1, int n1, const double* p2,
+                                                    int n2, int64_t p, int parity) {
+  cg_step_body<T, true>(w, s, 1, qsrc, d, m, beta, r, z, 1, p1, n1, p2, n2, 1, p, own_grid(),
+                        parity);
+}
 
 hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
                            const double* d, const double* m, double* beta, double* r,
@@ -1379,13 +1452,17 @@ hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* q
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity,
+hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity, bool pass_finish,
                           const Combine<T>& qsrc, const double* d, const double* m,
                           double* beta, double* r, double* z, const double* p1, int32_t n1,
                           const double* p2, int32_t n2, int64_t p, hipStream_t st) {
   const T* sn = s + (int64_t)(1 - parity) * sstride;
-  hipLaunchKernelGGL((k_cg_step<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, sn, qsrc, d, m,
-                     beta, r, z, p1, n1, p2, n2, p);
+  if (pass_finish)
+    hipLaunchKernelGGL((k_cg_step_pf<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, sn, qsrc, d, m,
+                       beta, r, z, p1, n1, p2, n2, p, parity);
+  else
+    hipLaunchKernelGGL((k_cg_step<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, sn, qsrc, d, m,
+                       beta, r, z, p1, n1, p2, n2, p);
   return hipGetLastError();
 }
 
@@ -1441,7 +1518,7 @@ hipError_t launch_cg_step_batched(const VecJob<T>* jobs, const int32_t* blk_job,
 }
 
 #define PPCG_INST(T)                                                                         \
-  template hipError_t launch_cg_step<T>(VecWork, const T*, int64_t, int, const Combine<T>&,  \
+  template hipError_t launch_cg_step<T>(VecWork, const T*, int64_t, int, bool, const Combine<T>&,  \
                                         const double*, const double*, double*, double*,      \
                                         double*, const double*, int32_t, const double*,      \
                                         int32_t, int64_t, hipStream_t);                      \
