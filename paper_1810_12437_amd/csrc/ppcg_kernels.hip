@@ -257,7 +257,7 @@ __device__ __forceinline__ void stream_issue(const PanelPass& t, int c_end, int 
   constexpr int H = kPV / 2;
   int64_t ea = L.last_base, eb = L.last_base;
   int32_t si = t.no_slot;
-  bool h = false;
+  bool h = false, first = false;
   if (L.c < c_end) {
     // window start w0, its ng groups, this lane's rank r among them
     int64_t w0;
@@ -279,11 +279,13 @@ __device__ __forceinline__ void stream_issue(const PanelPass& t, int c_end, int 
     ea = h ? w0 + (int64_t)r * H : w0;
     eb = h ? w0 + (int64_t)(ng + r) * H : w0;
     si = L.sidx;
+    first = L.k == 0;
     if (++L.k == L.windows && ++L.c < c_end) stream_open(t, read_desc(t.chunks, L.c), L.c, lane, L);
   }
   a = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(t.idx + ea));
   b = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(t.idx + eb));
-  slot = t.seg_out[si];
+  // the chunk's output slot rides with its first window only
+  if (first) slot = t.seg_out[si];
   have = (have & ~(1u << bit)) | ((h ? 1u : 0u) << bit);
 }
 
