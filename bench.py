@@ -51,9 +51,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "0b1ccdd56c200adb2d8d94fb8b800a1846be669cfa0c7a2fb5666405c7bca3ff",
+    "sources_sha256": "d55315ee019007b9c5c7af745a905a841e989fb494db49facc8b7fe397613ea8",
     # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
-    "bytes_per_launch": 121790617,
+    "bytes_per_launch": 121390182,
 }
 
 
