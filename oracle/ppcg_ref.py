@@ -320,3 +320,50 @@ def sampler_draw(X, omega, z, lam, tau, eta, delta, tol=1e-10,
     Phi beta = b by prior-preconditioned CG from beta0 = 0."""
     b = rhs_b(X, omega, z, lam, tau, eta, delta)
     return b, pcg_solve(X, omega, lam, tau, b, None, tol, criterion, max_iter)
+
+
+# ---- general diagonal prior and preconditioner (Supplement S4.4) ----
+# Coefficients estimated without shrinkage (an intercept, effects of
+# interest) get independent N(0, sigma_j^2) priors, sigma_j = infinity for a
+# flat prior: Phi = X^T Omega X + diag(d) with d_j = sigma_j^-2 (0 when flat)
+# for them and tau^-2 lambda_j^-2 for the rest, and the preconditioner
+# becomes M = diag(gamma^-2, tau^-2 lambda^-2) for scales gamma_j chosen by
+# the caller (the supplement suggests c times a posterior scale estimate).
+# Here d is any non-negative prior precision and m = M^-1's diagonal.
+
+
+def phi_dense_general(X, omega, d):
+    """Phi = X^T Omega X + diag(d) formed explicitly (small problems only)."""
+    XO = X.multiply(np.asarray(omega, dtype=np.float64)[:, None]).tocsr()
+    Phi = (X.T @ XO).toarray()
+    Phi[np.diag_indices_from(Phi)] += np.asarray(d, dtype=np.float64)
+    return Phi
+
+
+def phi_matvec_general(X, omega, d, v):
+    """v -> Phi v = X^T (omega * (X v)) + d * v through the two products only."""
+    v = np.asarray(v, dtype=np.float64)
+    return X.T @ (np.asarray(omega, dtype=np.float64) * (X @ v)) + np.asarray(d) * v
+
+
+def phi_diag(X, omega, d):
+    """diag(Phi) = sum over the non-zeros of column j of omega_i (X binary)
+    plus d_j: the inverse of the Jacobi preconditioner's diagonal."""
+    return np.asarray(X.T @ np.asarray(omega, dtype=np.float64)).ravel() + np.asarray(d)
+
+
+def rhs_b_general(X, omega, z, d, eta, delta):
+    """Prop 2.1 with the prior precision diag(d):
+    b = X^T Omega z + X^T Omega^1/2 eta + diag(d)^1/2 delta, so that
+    b ~ N(X^T Omega z, X^T Omega X + diag(d)) = N(X^T Omega z, Phi)."""
+    omega = np.asarray(omega, dtype=np.float64)
+    y = omega * np.asarray(z, dtype=np.float64) + np.sqrt(omega) * np.asarray(eta)
+    return X.T @ y + np.sqrt(np.asarray(d, dtype=np.float64)) * np.asarray(delta)
+
+
+def pcg_solve_general(X, omega, d, m, b, beta0=None, tol=1e-10,
+                      criterion=REL_PRECOND, max_iter=None):
+    """Preconditioned CG (the recurrences of ``pcg``) on
+    (X^T Omega X + diag(d)) beta = b with M^-1 = diag(m)."""
+    mv = lambda v: phi_matvec_general(X, omega, d, v)  # noqa: E731
+    return pcg(mv, b, m, beta0, tol, criterion, max_iter)
