@@ -191,6 +191,51 @@ int ppcg_draw(const ppcg_matrix* X, const void* omega, const void* z,
               ppcg_info* info, hipStream_t stream);
 
 /*
+ * General diagonal prior and preconditioner (Supplement S4.4): coefficients
+ * estimated without shrinkage (an intercept, effects of interest) take
+ * independent N(0, sigma_j^2) priors, flat when sigma_j is infinite, so
+ *   Phi = X^T Omega X + diag(prior_prec),   M^-1 = diag(precond_inv),
+ * with prior_prec_j = sigma_j^-2 (0 for a flat prior) for those and
+ * tau^-2 lambda_j^-2 for shrunk ones, and precond_inv_j = gamma_j^2 for
+ * unshrunk ones (the supplement takes gamma_j = c times an estimate of
+ * beta_j's posterior scale, c >= 1) and (tau lambda_j)^2 for shrunk ones.
+ * prior_prec (>= 0) and precond_inv (> 0, or NULL for 1 / prior_prec, which
+ * needs every prior_prec_j > 0) are FP64 device arrays of p owned by the
+ * caller; the other arguments are as in ppcg_solve.  The stopping rules
+ * measure the residual in the norm of this M.  A flat prior needs a proper
+ * likelihood (X^T Omega X positive on those coordinates) for Phi to be
+ * positive definite; otherwise CG reports PPCG_EBREAKDOWN.
+ */
+int ppcg_solve_general(const ppcg_matrix* X, const void* omega, const double* prior_prec,
+                       const double* precond_inv, const void* b, const void* beta0,
+                       const ppcg_options* opt, void* beta_out, ppcg_info* info,
+                       hipStream_t stream);
+
+/*
+ * One draw under the general prior: Prop 2.1 with the prior precision
+ * diag(prior_prec), b = X^T Omega z + X^T Omega^1/2 eta +
+ * diag(prior_prec)^1/2 delta (eta, delta from (seed, chain, draw_index) as in
+ * ppcg_draw), then ppcg_solve_general from beta0 (NULL: zero; a warm start
+ * such as the running mean of earlier draws, Section 2.6, saves iterations
+ * without changing the law of the draw).
+ */
+int ppcg_draw_general(const ppcg_matrix* X, const void* omega, const void* z,
+                      const double* prior_prec, const double* precond_inv, const void* beta0,
+                      uint64_t seed, uint64_t chain, uint64_t draw_index,
+                      const ppcg_options* opt, void* beta_out, ppcg_info* info,
+                      hipStream_t stream);
+
+/*
+ * diag(Phi)_j = sum over the non-zeros of column j of omega_i, plus
+ * prior_prec_j: one column pass.  Its reciprocal is the Jacobi
+ * preconditioner's M^-1, the alternative the paper compares with (Section
+ * 2.4) — pass it as precond_inv.  omega: n of `dtype`; prior_prec, diag_out:
+ * FP64 device arrays of p.  Blocks until diag_out is written.
+ */
+int ppcg_phi_diag(const ppcg_matrix* X, const void* omega, int32_t dtype,
+                  const double* prior_prec, double* diag_out, hipStream_t stream);
+
+/*
  * Adjoint of beta = Phi(lambda, tau)^-1 b for a loss L with g = dL/dbeta:
  * solves Phi a = g with the same preconditioned CG, then
  *   grad_b = a,  grad_loglambda_j = 2 d_j a_j beta_j,  grad_logtau = sum_j of those,

@@ -19,6 +19,7 @@ __all__ = [
     "F64", "F32", "REL_PRECOND", "RMS_PRECOND_ABS", "REL_PLAIN",
     "STREAM_ETA", "STREAM_DELTA", "Matrix", "Batch", "Options", "Info", "Chain",
     "phi_matvec", "normals", "rhs", "solve", "draw", "solve_backward",
+    "solve_general", "draw_general", "phi_diag",
     "PPCGSolve", "PPCGError", "PPCGUnavailable", "lib", "LIB_PATH", "EXPORTED_SYMBOLS",
 ]
 
@@ -40,6 +41,7 @@ EXPORTED_SYMBOLS = (
     "ppcg_matrix_pass_bytes", "ppcg_batch_create", "ppcg_batch_create_shared",
     "ppcg_batch_destroy",
     "ppcg_draw_batched", "ppcg_solve_batched",
+    "ppcg_solve_general", "ppcg_draw_general", "ppcg_phi_diag",
 )
 
 
@@ -105,6 +107,11 @@ def _declare(L):
                              ctypes.POINTER(Info), _vp]
     L.ppcg_draw.argtypes = [_vp, _vp, _vp, _vp, _dbl, _u64, _u64, _u64, ctypes.POINTER(Options),
                             _vp, ctypes.POINTER(Info), _vp]
+    L.ppcg_solve_general.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Options), _vp,
+                                     ctypes.POINTER(Info), _vp]
+    L.ppcg_draw_general.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _u64, _u64, _u64,
+                                    ctypes.POINTER(Options), _vp, ctypes.POINTER(Info), _vp]
+    L.ppcg_phi_diag.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
     L.ppcg_solve_backward.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, ctypes.POINTER(Options),
                                       _vp, _vp, _vp, ctypes.POINTER(Info), _vp]
     L.ppcg_matrix_profile.argtypes = [_vp, _i32]
@@ -122,7 +129,8 @@ def _declare(L):
     for name in ("ppcg_batch_create", "ppcg_batch_create_shared", "ppcg_batch_destroy", "ppcg_draw_batched",
                  "ppcg_solve_batched", "ppcg_matrix_pass_bytes", "ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
                  "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
-                 "ppcg_solve_backward"):
+                 "ppcg_solve_backward", "ppcg_solve_general", "ppcg_draw_general",
+                 "ppcg_phi_diag"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -440,6 +448,63 @@ def draw(X, omega, z, lam, tau, seed, chain=0, draw_index=0, **opts):
                          ctypes.byref(info), _stream())
     _check(rc, "ppcg_draw", solver=True)
     return beta, info.as_dict()
+
+
+def _f64(v, n, name):
+    """Device pointer of a float64 vector (prior precision, preconditioner)."""
+    return _dev(v, F64, n, name)
+
+
+def solve_general(X, omega, prior_prec, b, precond_inv=None, beta0=None, **opts):
+    """beta = Phi^-1 b with Phi = X^T Omega X + diag(prior_prec) by CG with
+    M^-1 = diag(precond_inv) (default 1 / prior_prec); prior_prec and
+    precond_inv are float64 (Supplement S4.4).  Returns (beta, info dict)."""
+    torch = _torch()
+    dt = _dtype_of(b)
+    o = make_options(dtype=dt, **opts)
+    beta = torch.empty(X.p, dtype=b.dtype, device=b.device)
+    info = Info()
+    rc = lib().ppcg_solve_general(
+        X.handle, _dev(omega, dt, X.n, "omega"), _f64(prior_prec, X.p, "prior_prec"),
+        None if precond_inv is None else _f64(precond_inv, X.p, "precond_inv"),
+        _dev(b, dt, X.p, "b"), None if beta0 is None else _dev(beta0, dt, X.p, "beta0"),
+        ctypes.byref(o), _dev(beta, dt, X.p, "beta"), ctypes.byref(info), _stream())
+    _check(rc, "ppcg_solve_general", solver=True)
+    return beta, info.as_dict()
+
+
+def draw_general(X, omega, z, prior_prec, seed, chain=0, draw_index=0, precond_inv=None,
+                 beta0=None, **opts):
+    """One draw of beta ~ N(Phi^-1 X^T Omega z, Phi^-1) with Phi = X^T Omega X +
+    diag(prior_prec) (Prop 2.1 with that prior), CG preconditioned by
+    M^-1 = diag(precond_inv), started from beta0.  Returns (beta, info dict)."""
+    torch = _torch()
+    dt = _dtype_of(omega)
+    o = make_options(dtype=dt, **opts)
+    beta = torch.empty(X.p, dtype=omega.dtype, device=omega.device)
+    info = Info()
+    rc = lib().ppcg_draw_general(
+        X.handle, _dev(omega, dt, X.n, "omega"), _dev(z, dt, X.n, "z"),
+        _f64(prior_prec, X.p, "prior_prec"),
+        None if precond_inv is None else _f64(precond_inv, X.p, "precond_inv"),
+        None if beta0 is None else _dev(beta0, dt, X.p, "beta0"), int(seed), int(chain),
+        int(draw_index), ctypes.byref(o), _dev(beta, dt, X.p, "beta"), ctypes.byref(info),
+        _stream())
+    _check(rc, "ppcg_draw_general", solver=True)
+    return beta, info.as_dict()
+
+
+def phi_diag(X, omega, prior_prec):
+    """diag(Phi) = X^T omega + prior_prec (float64); 1 / it is the Jacobi
+    preconditioner's M^-1."""
+    torch = _torch()
+    dt = _dtype_of(omega)
+    out = torch.empty(X.p, dtype=torch.float64, device=omega.device)
+    rc = lib().ppcg_phi_diag(X.handle, _dev(omega, dt, X.n, "omega"), dt,
+                             _f64(prior_prec, X.p, "prior_prec"),
+                             ctypes.c_void_p(out.data_ptr()), _stream())
+    _check(rc, "ppcg_phi_diag")
+    return out
 
 
 def solve_backward(X, omega, lam, tau, beta, grad_beta, **opts):

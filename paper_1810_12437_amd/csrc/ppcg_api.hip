@@ -506,6 +506,75 @@ int ppcg_draw(const ppcg_matrix* Xc, const void* omega, const void* z, const voi
   return status;
 }
 
+// ---- general diagonal prior and preconditioner (Supplement S4.4) ----
+static int prepare_general(ppcg_matrix* X, const void* omega, const double* prior_prec,
+                           const double* precond_inv, int dtype, hipStream_t st) {
+  PPCG_TRY_HIP(launch_prep_general(prior_prec, precond_inv, omega, dtype, X->n, X->p, X->d, X->m,
+                                   dtype == PPCG_F64 ? nullptr : X->omega64, st));
+  return PPCG_OK;
+}
+
+int ppcg_solve_general(const ppcg_matrix* Xc, const void* omega, const double* prior_prec,
+                       const double* precond_inv, const void* b, const void* beta0,
+                       const ppcg_options* opt, void* beta_out, ppcg_info* info,
+                       hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !omega || !prior_prec || !b || !beta_out) return PPCG_EINVAL;
+  const ppcg_options o = resolve(opt, X->p);
+  if (check_opts(o)) return PPCG_EINVAL;
+  int rc = prepare_general(X, omega, prior_prec, precond_inv, o.dtype, st);
+  if (rc) return rc;
+  PPCG_TRY_HIP(launch_convert_to_f64(b, o.dtype, X->p, X->b64, st));
+  if (beta0) PPCG_TRY_HIP(launch_convert_to_f64(beta0, o.dtype, X->p, X->beta64, st));
+  const int status = dispatch_solve(X, omega, o.dtype, beta0 != nullptr, o, info, st);
+  if (status == PPCG_EINVAL || status == PPCG_ENOMEM || status == PPCG_EHIP) return status;
+  PPCG_TRY_HIP(launch_convert_from_f64(X->beta64, o.dtype, X->p, beta_out, st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  return status;
+}
+
+int ppcg_draw_general(const ppcg_matrix* Xc, const void* omega, const void* z,
+                      const double* prior_prec, const double* precond_inv, const void* beta0,
+                      uint64_t seed, uint64_t chain, uint64_t draw_index,
+                      const ppcg_options* opt, void* beta_out, ppcg_info* info,
+                      hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !omega || !z || !prior_prec || !beta_out) return PPCG_EINVAL;
+  const ppcg_options o = resolve(opt, X->p);
+  if (check_opts(o)) return PPCG_EINVAL;
+  int rc = prepare_general(X, omega, prior_prec, precond_inv, o.dtype, st);
+  if (rc) return rc;
+  const double* om64 = omega_f64(X, omega, o.dtype);
+  PPCG_TRY_HIP(launch_y_draw(om64, z, o.dtype, seed, chain, draw_index, X->n, X->y64, st));
+  const Combine<double> y = comb_vec<double>(X->y64);
+  PPCG_TRY_HIP(col_pass<double>(X, nullptr, &y, nullptr, st));
+  PPCG_TRY_HIP(launch_combine<double, double>(comb_out<double>(X->cols[0], nullptr), X->p,
+                                              X->qx64, st));
+  PPCG_TRY_HIP(
+      launch_rhs_fin_general(X->qx64, X->d, seed, chain, draw_index, X->p, X->b64, st));
+  if (beta0) PPCG_TRY_HIP(launch_convert_to_f64(beta0, o.dtype, X->p, X->beta64, st));
+  const int status = dispatch_solve(X, omega, o.dtype, beta0 != nullptr, o, info, st);
+  if (status == PPCG_EINVAL || status == PPCG_ENOMEM || status == PPCG_EHIP) return status;
+  PPCG_TRY_HIP(launch_convert_from_f64(X->beta64, o.dtype, X->p, beta_out, st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  return status;
+}
+
+int ppcg_phi_diag(const ppcg_matrix* Xc, const void* omega, int32_t dtype,
+                  const double* prior_prec, double* diag_out, hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !omega || !prior_prec || !diag_out || !valid_dtype(dtype)) return PPCG_EINVAL;
+  if (dtype != PPCG_F64)
+    PPCG_TRY_HIP(launch_convert_to_f64(omega, dtype, X->n, X->omega64, st));
+  const double* om64 = omega_f64(X, omega, dtype);
+  const Combine<double> w = comb_vec<double>(om64);
+  PPCG_TRY_HIP(col_pass<double>(X, nullptr, &w, nullptr, st));
+  PPCG_TRY_HIP(
+      launch_phi_diag(comb_out<double>(X->cols[0], nullptr), prior_prec, X->p, diag_out, st));
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  return PPCG_OK;
+}
+
 int ppcg_solve_backward(const ppcg_matrix* Xc, const void* omega, const void* lambda,
                         double tau, const void* beta, const void* grad_beta,
                         const ppcg_options* opt, void* grad_b, void* grad_loglambda,

@@ -192,12 +192,27 @@ hipError_t launch_prep(const void* lambda, const void* omega, int dtype, double 
                        int64_t n, int64_t p, double* d, double* m, double* omega64,
                        hipStream_t st);
 
+// General diagonal prior (Supplement S4.4): d = prior_prec, m = precond_inv
+// (NULL: 1 / prior_prec), omega64 as launch_prep.
+hipError_t launch_prep_general(const double* prior_prec, const double* precond_inv,
+                               const void* omega, int dtype, int64_t n, int64_t p, double* d,
+                               double* m, double* omega64, hipStream_t st);
+
 hipError_t launch_y_draw(const double* omega64, const void* z, int dtype, uint64_t seed,
                          uint64_t chain, uint64_t draw, int64_t n, double* y, hipStream_t st);
 
 hipError_t launch_rhs_fin(const double* bx, const void* lambda, int dtype, double tau,
                           uint64_t seed, uint64_t chain, uint64_t draw, int64_t p,
                           double* b, hipStream_t st);
+
+// b = bx + sqrt(d) .* delta (Prop 2.1 with the prior precision diag(d)).
+hipError_t launch_rhs_fin_general(const double* bx, const double* d, uint64_t seed,
+                                  uint64_t chain, uint64_t draw, int64_t p, double* b,
+                                  hipStream_t st);
+
+// out[j] = value(c, j) + d[j] (diag(Phi) from the column pass of omega).
+hipError_t launch_phi_diag(const Combine<double>& c, const double* d, int64_t p, double* out,
+                           hipStream_t st);
 
 hipError_t launch_normals(uint64_t seed, uint64_t stream_id, uint64_t chain, uint64_t draw,
                           int64_t count, double* out, hipStream_t st);

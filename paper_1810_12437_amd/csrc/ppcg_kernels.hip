@@ -1146,6 +1146,29 @@ __global__ __launch_bounds__(kWG) void k_rhs_fin(const double* bx, const void* l
   }
 }
 
+__global__ __launch_bounds__(kWG) void k_rhs_fin_general(const double* bx, const double* d,
+                                                         uint64_t seed, uint64_t chain,
+                                                         uint64_t draw, int64_t p, double* b) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (4 * i >= p) return;
+  double g[4];
+  normals4(seed, 1ull, chain, draw, (uint64_t)i, g);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = 4 * i + q;
+    if (j < p) b[j] = bx[j] + g[q] * sqrt(d[j]);
+  }
+}
+
+hipError_t launch_rhs_fin_general(const double* bx, const double* d, uint64_t seed,
+                                  uint64_t chain, uint64_t draw, int64_t p, double* b,
+                                  hipStream_t st) {
+  const int64_t nb = (p + 3) / 4;
+  hipLaunchKernelGGL(k_rhs_fin_general, dim3((unsigned)((nb + kWG - 1) / kWG)), dim3(kWG), 0,
+                     st, bx, d, seed, chain, draw, p, b);
+  return hipGetLastError();
+}
+
 hipError_t launch_rhs_fin(const double* bx, const void* lambda, int dtype, double tau,
                           uint64_t seed, uint64_t chain, uint64_t draw, int64_t p, double* b,
                           hipStream_t st) {
@@ -1175,6 +1198,43 @@ hipError_t launch_prep(const void* lambda, const void* omega, int dtype, double 
   const int64_t cnt = n > p ? n : p;
   hipLaunchKernelGGL(k_prep, dim3((unsigned)((cnt + kWG - 1) / kWG)), dim3(kWG), 0, st, lambda,
                      omega, dtype, tau, n, p, d, m, omega64);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kWG) void k_prep_general(const double* prior_prec,
+                                                      const double* precond_inv,
+                                                      const void* omega, int dtype, int64_t n,
+                                                      int64_t p, double* d, double* m,
+                                                      double* omega64) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < p) {
+    const double pr = prior_prec[i];
+    d[i] = pr;
+    m[i] = precond_inv != nullptr ? precond_inv[i] : 1.0 / pr;
+  }
+  if (omega64 != nullptr && i < n) omega64[i] = ld_dtype(omega, dtype, i);
+}
+
+hipError_t launch_prep_general(const double* prior_prec, const double* precond_inv,
+                               const void* omega, int dtype, int64_t n, int64_t p, double* d,
+                               double* m, double* omega64, hipStream_t st) {
+  const int64_t cnt = n > p ? n : p;
+  hipLaunchKernelGGL(k_prep_general, dim3((unsigned)((cnt + kWG - 1) / kWG)), dim3(kWG), 0, st,
+                     prior_prec, precond_inv, omega, dtype, n, p, d, m, omega64);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kWG) void k_phi_diag(Combine<double> c, const double* d, int64_t p,
+                                                  double* out) {
+  const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (j < p) out[j] = combine_at(c, j) + d[j];
+}
+
+hipError_t launch_phi_diag(const Combine<double>& c, const double* d, int64_t p, double* out,
+                           hipStream_t st) {
+  if (p <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_phi_diag, dim3((unsigned)((p + kWG - 1) / kWG)), dim3(kWG), 0, st, c, d,
+                     p, out);
   return hipGetLastError();
 }
 

@@ -152,3 +152,14 @@ def test_batch_entry_points_reject_bad_arguments():
     assert L.ppcg_draw_batched(None, chains, None, None, None) == pk.EINVAL
     assert L.ppcg_solve_batched(None, chains, None, None, None) == pk.EINVAL
     assert L.ppcg_batch_destroy(None) == pk.OK
+
+
+@needs_lib
+def test_general_prior_entry_points_reject_bad_arguments():
+    """NULL handle or NULL prior precision is rejected before any device call."""
+    L = pk.lib()
+    assert L.ppcg_solve_general(None, None, None, None, None, None, None, None, None,
+                                None) == pk.EINVAL
+    assert L.ppcg_draw_general(None, None, None, None, None, None, 0, 0, 0, None, None, None,
+                               None) == pk.EINVAL
+    assert L.ppcg_phi_diag(None, None, pk.F64, None, None, None) == pk.EINVAL

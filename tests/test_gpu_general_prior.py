@@ -1,0 +1,140 @@
+"""GPU parity of the general diagonal prior and preconditioner (Supplement
+S4.4): a flat-prior intercept column and N(0, sigma^2) coefficients beside
+shrunk ones, the Jacobi preconditioner from diag(Phi), and warm starts —
+against the oracle's Cholesky solution of the same b (1e-10 relative in FP64
+at tight tolerance, 1e-5 in the FP32 form)."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+torch = pytest.importorskip("torch")
+import paper_1810_12437_amd as pk  # noqa: E402
+import synth  # noqa: E402
+from oracle import philox_ref as H  # noqa: E402
+from oracle import ppcg_ref as R  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def with_intercept(P):
+    """P's design with a column of ones prepended (column 0: the intercept)."""
+    rows = []
+    for i in range(P.n):
+        cols = P.col_idx[P.row_ptr[i]:P.row_ptr[i + 1]].astype(np.int64) + 1
+        rows.append(np.concatenate([[0], cols]))
+    row_ptr = np.zeros(P.n + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum([len(r) for r in rows])
+    col_idx = np.concatenate(rows).astype(np.int32)
+    return P.n, P.p + 1, row_ptr, col_idx
+
+
+def setup(n=3000, p=400, q=2, seed=5):
+    P = synth.scaled_problem(n, p, seed=seed, tau=2e-2)
+    n, p1, row_ptr, col_idx = with_intercept(P)
+    X = pk.Matrix(n, p1, row_ptr, col_idx)
+    Xs = R.csr_matrix(n, p1, row_ptr, col_idx)
+    lam = np.concatenate([[1.0], P.lam])
+    d = 1.0 / (P.tau * lam) ** 2
+    d[0] = 0.0                  # flat prior on the intercept
+    d[1:q + 1] = 1.0 / 9.0      # sigma = 3 for q effects of interest
+    Phi = R.phi_dense_general(Xs, P.omega, d)
+    psi = np.sqrt(np.diag(np.linalg.inv(Phi)))
+    m = (P.tau * lam) ** 2
+    m[:q + 1] = (2.0 * psi[:q + 1]) ** 2   # gamma = c psi, c = 2
+    return P, X, Xs, d, m, Phi
+
+
+def t64(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64), device=DEV)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_phi_diag_matches_oracle():
+    P, X, Xs, d, m, Phi = setup()
+    got = pk.phi_diag(X, t64(P.omega), t64(d)).cpu().numpy()
+    ref = R.phi_diag(Xs, P.omega, d)
+    say("[phi_diag] rel err", rel(got, ref))
+    assert rel(got, ref) <= 1e-13
+    got32 = pk.phi_diag(X, t64(P.omega).float(), t64(d)).cpu().numpy()
+    ref32 = R.phi_diag(Xs, np.float32(P.omega).astype(np.float64), d)
+    assert rel(got32, ref32) <= 1e-13
+
+
+def test_draw_general_matches_oracle():
+    P, X, Xs, d, m, Phi = setup()
+    for draw_index in (0, 3):
+        eta, delta = H.eta_delta(41, 0, draw_index, P.n, Phi.shape[0])
+        b = R.rhs_b_general(Xs, P.omega, P.z, d, eta, delta)
+        exact = R.solve_chol(Phi, b)
+        beta, info = pk.draw_general(X, t64(P.omega), t64(P.z), t64(d), 41, 0, draw_index,
+                                     precond_inv=t64(m), tol=1e-13)
+        e = rel(beta.cpu().numpy(), exact)
+        say(f"[draw_general] draw {draw_index} iters {info['iters']} rel err {e:.2e}")
+        assert info["status"] == pk.OK and e <= 1e-10
+
+
+def test_solve_general_jacobi_and_prior_preconditioners():
+    """Both preconditioners reach the Cholesky solution; the iteration counts
+    are reported (the paper compares the two, Section 2.4)."""
+    P, X, Xs, d, m, Phi = setup(seed=6)
+    b = np.random.default_rng(2).standard_normal(Phi.shape[0])
+    exact = R.solve_chol(Phi, b)
+    diag = pk.phi_diag(X, t64(P.omega), t64(d))
+    its = {}
+    for name, mi in (("prior", t64(m)), ("jacobi", 1.0 / diag)):
+        beta, info = pk.solve_general(X, t64(P.omega), t64(d), t64(b), precond_inv=mi, tol=1e-13)
+        e = rel(beta.cpu().numpy(), exact)
+        its[name] = info["iters"]
+        say(f"[solve_general] {name}: iters {info['iters']} rel err {e:.2e}")
+        assert info["status"] == pk.OK and e <= 1e-10
+        ref = R.pcg_solve_general(Xs, P.omega, d, mi.cpu().numpy(), b, tol=1e-13)
+        assert abs(info["iters"] - ref.iters) <= max(3, 0.05 * ref.iters)
+
+
+def test_warm_start_from_the_solution_stops_at_once():
+    P, X, Xs, d, m, Phi = setup(seed=7)
+    b = np.random.default_rng(4).standard_normal(Phi.shape[0])
+    exact = R.solve_chol(Phi, b)
+    _, cold = pk.solve_general(X, t64(P.omega), t64(d), t64(b), precond_inv=t64(m), tol=1e-8)
+    beta, warm = pk.solve_general(X, t64(P.omega), t64(d), t64(b), precond_inv=t64(m),
+                                  beta0=t64(exact), tol=1e-8)
+    say(f"[warm start] cold {cold['iters']} warm {warm['iters']}")
+    assert warm["iters"] <= 1 and cold["iters"] > 10
+    assert rel(beta.cpu().numpy(), exact) <= 1e-8
+
+
+def test_general_prior_reduces_to_the_shrinkage_prior():
+    """prior_prec = tau^-2 lambda^-2 with the default preconditioner gives the
+    ppcg_draw draw (same b up to the rounding of sqrt(d) against 1/(tau
+    lambda))."""
+    P = synth.scaled_problem(3000, 400, seed=8, tau=2e-2)
+    X = pk.Matrix.from_problem(P)
+    d = R.prior_precision(P.lam, P.tau)
+    a, ia = pk.draw(X, t64(P.omega), t64(P.z), t64(P.lam), P.tau, 5, 1, 2, tol=1e-12)
+    b_, ib = pk.draw_general(X, t64(P.omega), t64(P.z), t64(d), 5, 1, 2, tol=1e-12)
+    say(f"[reduces] iters {ia['iters']} {ib['iters']} rel diff {rel(b_.cpu().numpy(), a.cpu().numpy()):.2e}")
+    assert rel(b_.cpu().numpy(), a.cpu().numpy()) <= 1e-10
+
+
+def test_draw_general_f32_matches_f64_oracle():
+    P, X, Xs, d, m, Phi = setup(seed=9)
+    c32 = lambda a: np.float32(a).astype(np.float64)  # noqa: E731
+    eta, delta = H.eta_delta(13, 0, 0, P.n, Phi.shape[0])
+    Phi32 = R.phi_dense_general(Xs, c32(P.omega), d)
+    b = R.rhs_b_general(Xs, c32(P.omega), c32(P.z), d, eta, delta)
+    exact = R.solve_chol(Phi32, b)
+    beta, info = pk.draw_general(X, t64(P.omega).float(), t64(P.z).float(), t64(d), 13, 0, 0,
+                                 precond_inv=t64(m), tol=1e-8)
+    e = rel(beta.double().cpu().numpy(), exact)
+    say(f"[draw_general f32] iters {info['iters']}+{info['refine_iters']} rel err {e:.2e}")
+    assert info["status"] == pk.OK and e <= 1e-5
