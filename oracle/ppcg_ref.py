@@ -367,3 +367,17 @@ def pcg_solve_general(X, omega, d, m, b, beta0=None, tol=1e-10,
     (X^T Omega X + diag(d)) beta = b with M^-1 = diag(m)."""
     mv = lambda v: phi_matvec_general(X, omega, d, v)  # noqa: E731
     return pcg(mv, b, m, beta0, tol, criterion, max_iter)
+
+
+# ---- initial vector (Supplement S2: choice of initial vector) ----
+def warm_start_accumulate(acc, beta, lam_prev, tau_prev):
+    """Running sum of the draws rescaled by the shrinkage scales they were
+    drawn under: acc + beta^(i) / (tau^(i-1) lambda^(i-1))."""
+    return np.asarray(acc, dtype=np.float64) + np.asarray(beta, dtype=np.float64) / (
+        tau_prev * np.asarray(lam_prev, dtype=np.float64))
+
+
+def warm_start_vector(acc, count, lam, tau):
+    """beta0 = tau lambda * (acc / count): the estimate of E[beta / (tau lambda)]
+    rescaled by the scales the next draw is conditioned on."""
+    return tau * np.asarray(lam, dtype=np.float64) * (np.asarray(acc, dtype=np.float64) / count)

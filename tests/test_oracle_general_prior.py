@@ -122,3 +122,30 @@ def test_general_b_law():
     assert np.allclose(b0, bs[5], rtol=1e-14, atol=1e-14)
     mean_b = X.T @ (omega_ * z)
     assert S.passes(S.gaussian_tests(S.whiten_b(bs, mean_b, L)))
+
+
+def test_warm_start_estimator_recovers_the_mean():
+    """With draws from a fixed conditional, the rescaled running mean is the
+    sample mean of the draws, so beta0 -> the conditional mean mu and CG from
+    it needs fewer iterations than from zero."""
+    X, omega, z, d, m, Phi = _mixed(q=0)
+    p = Phi.shape[0]
+    rng = np.random.default_rng(21)
+    lam = np.sqrt(1.0 / np.where(d > 0, d, 1.0))  # tau = 1 scales (d = lambda^-2 here)
+    tau = 1.0
+    L = R.cholesky(Phi)
+    mean_b = X.T @ (omega * z)
+    mu = R.solve_chol(Phi, mean_b)
+    acc = np.zeros(p)
+    N = 400
+    draws = mu + np.linalg.solve(L.T, rng.standard_normal((p, N))).T
+    for k in range(N):
+        acc = R.warm_start_accumulate(acc, draws[k], lam, tau)
+    beta0 = R.warm_start_vector(acc, N, lam, tau)
+    assert np.allclose(beta0, draws.mean(axis=0), rtol=1e-12, atol=1e-14)
+    b = R.rhs_b_general(X, omega, z, d, rng.standard_normal(X.shape[0]), rng.standard_normal(p))
+    cold = R.pcg_solve_general(X, omega, d, m, b, tol=1e-8)
+    warm = R.pcg_solve_general(X, omega, d, m, b, beta0=beta0, tol=1e-8)
+    exact = R.solve_chol(Phi, b)
+    assert np.linalg.norm(warm.beta - exact) <= 1e-6 * np.linalg.norm(exact)
+    assert warm.iters <= cold.iters
