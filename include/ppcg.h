@@ -236,6 +236,20 @@ int ppcg_phi_diag(const ppcg_matrix* X, const void* omega, int32_t dtype,
                   const double* prior_prec, double* diag_out, hipStream_t stream);
 
 /*
+ * Initial vector of the CG sampler (Supplement S2, choice of initial vector:
+ * the rescaled running mean).  After draw i, acc += beta^(i) / (tau_prev
+ * lambda_prev), with the scales that draw was conditioned on; before the next
+ * draw, beta0 = tau lambda * (acc / count) with its scales, passed as beta0 of
+ * ppcg_draw_general.  acc: FP64 device array of p owned by the caller (zero
+ * it first); beta, lambda, beta0: p of `dtype`; count, tau > 0.  Asynchronous
+ * on `stream`; PPCG_EINVAL for bad arguments.
+ */
+int ppcg_warm_start_accumulate(double* acc, const void* beta, const void* lambda_prev,
+                               double tau_prev, int32_t dtype, int64_t p, hipStream_t stream);
+int ppcg_warm_start_vector(void* beta0, const double* acc, double count, const void* lambda,
+                           double tau, int32_t dtype, int64_t p, hipStream_t stream);
+
+/*
  * Adjoint of beta = Phi(lambda, tau)^-1 b for a loss L with g = dL/dbeta:
  * solves Phi a = g with the same preconditioned CG, then
  *   grad_b = a,  grad_loglambda_j = 2 d_j a_j beta_j,  grad_logtau = sum_j of those,

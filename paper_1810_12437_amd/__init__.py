@@ -19,7 +19,7 @@ __all__ = [
     "F64", "F32", "REL_PRECOND", "RMS_PRECOND_ABS", "REL_PLAIN",
     "STREAM_ETA", "STREAM_DELTA", "Matrix", "Batch", "Options", "Info", "Chain",
     "phi_matvec", "normals", "rhs", "solve", "draw", "solve_backward",
-    "solve_general", "draw_general", "phi_diag",
+    "solve_general", "draw_general", "phi_diag", "WarmStart",
     "PPCGSolve", "PPCGError", "PPCGUnavailable", "lib", "LIB_PATH", "EXPORTED_SYMBOLS",
 ]
 
@@ -42,6 +42,7 @@ EXPORTED_SYMBOLS = (
     "ppcg_batch_destroy",
     "ppcg_draw_batched", "ppcg_solve_batched",
     "ppcg_solve_general", "ppcg_draw_general", "ppcg_phi_diag",
+    "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
 )
 
 
@@ -112,6 +113,8 @@ def _declare(L):
     L.ppcg_draw_general.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _u64, _u64, _u64,
                                     ctypes.POINTER(Options), _vp, ctypes.POINTER(Info), _vp]
     L.ppcg_phi_diag.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
+    L.ppcg_warm_start_accumulate.argtypes = [_vp, _vp, _vp, _dbl, _i32, _i64, _vp]
+    L.ppcg_warm_start_vector.argtypes = [_vp, _vp, _dbl, _vp, _dbl, _i32, _i64, _vp]
     L.ppcg_solve_backward.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, ctypes.POINTER(Options),
                                       _vp, _vp, _vp, ctypes.POINTER(Info), _vp]
     L.ppcg_matrix_profile.argtypes = [_vp, _i32]
@@ -130,7 +133,7 @@ def _declare(L):
                  "ppcg_solve_batched", "ppcg_matrix_pass_bytes", "ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
                  "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
                  "ppcg_solve_backward", "ppcg_solve_general", "ppcg_draw_general",
-                 "ppcg_phi_diag"):
+                 "ppcg_phi_diag", "ppcg_warm_start_accumulate", "ppcg_warm_start_vector"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -505,6 +508,40 @@ def phi_diag(X, omega, prior_prec):
                              ctypes.c_void_p(out.data_ptr()), _stream())
     _check(rc, "ppcg_phi_diag")
     return out
+
+
+class WarmStart:
+    """Rescaled running mean of the draws (Supplement S2): add(beta, lam, tau)
+    after each draw with the scales it was drawn under; vector(lam, tau) gives
+    beta0 for the next draw under its scales (None before the first add)."""
+
+    def __init__(self, p, device="cuda"):
+        torch = _torch()
+        self.p = int(p)
+        self.count = 0
+        self.acc = torch.zeros(self.p, dtype=torch.float64, device=device)
+
+    def add(self, beta, lam, tau):
+        dt = _dtype_of(beta)
+        rc = lib().ppcg_warm_start_accumulate(ctypes.c_void_p(self.acc.data_ptr()),
+                                              _dev(beta, dt, self.p, "beta"),
+                                              _dev(lam, dt, self.p, "lambda"), float(tau), dt,
+                                              self.p, _stream())
+        _check(rc, "ppcg_warm_start_accumulate")
+        self.count += 1
+
+    def vector(self, lam, tau):
+        if self.count == 0:
+            return None
+        torch = _torch()
+        dt = _dtype_of(lam)
+        out = torch.empty(self.p, dtype=lam.dtype, device=lam.device)
+        rc = lib().ppcg_warm_start_vector(_dev(out, dt, self.p, "beta0"),
+                                          ctypes.c_void_p(self.acc.data_ptr()),
+                                          float(self.count), _dev(lam, dt, self.p, "lambda"),
+                                          float(tau), dt, self.p, _stream())
+        _check(rc, "ppcg_warm_start_vector")
+        return out
 
 
 def solve_backward(X, omega, lam, tau, beta, grad_beta, **opts):

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libppcg.so")
-SOURCES = ["ppcg_kernels.hip", "ppcg_host.hip", "ppcg_api.hip", "ppcg_batch.hip"]
+SOURCES = ["ppcg_kernels.hip", "ppcg_host.hip", "ppcg_api.hip", "ppcg_batch.hip",
+           "ppcg_warm.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

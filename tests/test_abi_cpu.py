@@ -163,3 +163,17 @@ def test_general_prior_entry_points_reject_bad_arguments():
     assert L.ppcg_draw_general(None, None, None, None, None, None, 0, 0, 0, None, None, None,
                                None) == pk.EINVAL
     assert L.ppcg_phi_diag(None, None, pk.F64, None, None, None) == pk.EINVAL
+
+
+def test_warm_start_entry_points_reject_bad_arguments():
+    """NULL arrays, p < 1, non-positive scales or an unknown dtype give
+    PPCG_EINVAL before any launch."""
+    L = pk.lib()
+    one = ctypes.c_void_p(1)  # never dereferenced: every call below fails its checks first
+    assert L.ppcg_warm_start_accumulate(None, one, one, 1.0, pk.F64, 4, None) == pk.EINVAL
+    assert L.ppcg_warm_start_accumulate(one, one, one, 0.0, pk.F64, 4, None) == pk.EINVAL
+    assert L.ppcg_warm_start_accumulate(one, one, one, 1.0, 7, 4, None) == pk.EINVAL
+    assert L.ppcg_warm_start_accumulate(one, one, one, 1.0, pk.F64, 0, None) == pk.EINVAL
+    assert L.ppcg_warm_start_vector(one, one, 0.0, one, 1.0, pk.F64, 4, None) == pk.EINVAL
+    assert L.ppcg_warm_start_vector(one, one, 2.0, one, float("nan"), pk.F64, 4, None) == pk.EINVAL
+    assert L.ppcg_warm_start_vector(one, None, 2.0, one, 1.0, pk.F32, 4, None) == pk.EINVAL
