@@ -170,7 +170,7 @@ int ppcg_rhs(const ppcg_matrix* X, const void* omega, const void* z,
 /*
  * Solves Phi beta = b (eq. linear_system_for_cg_sampler) by CG preconditioned
  * with M = tau^-2 Lambda^-2 (Section 2.4), starting from beta0 (NULL: zero,
- * Section 2.6).  omega: n; lambda, b, beta0, beta_out: p; all opt->dtype.
+ * Section 2.7).  omega: n; lambda, b, beta0, beta_out: p; all opt->dtype.
  * `opt` NULL means defaults for PPCG_F64.  `info` (host pointer, may be NULL)
  * receives iteration counts and residuals.  Blocks until beta_out is written.
  */
@@ -191,7 +191,7 @@ int ppcg_draw(const ppcg_matrix* X, const void* omega, const void* z,
               ppcg_info* info, hipStream_t stream);
 
 /*
- * General diagonal prior and preconditioner (Supplement S4.4): coefficients
+ * General diagonal prior and preconditioner (Supplement S4.3): coefficients
  * estimated without shrinkage (an intercept, effects of interest) take
  * independent N(0, sigma_j^2) priors, flat when sigma_j is infinite, so
  *   Phi = X^T Omega X + diag(prior_prec),   M^-1 = diag(precond_inv),
@@ -216,7 +216,7 @@ int ppcg_solve_general(const ppcg_matrix* X, const void* omega, const double* pr
  * diag(prior_prec), b = X^T Omega z + X^T Omega^1/2 eta +
  * diag(prior_prec)^1/2 delta (eta, delta from (seed, chain, draw_index) as in
  * ppcg_draw), then ppcg_solve_general from beta0 (NULL: zero; a warm start
- * such as the running mean of earlier draws, Section 2.6, saves iterations
+ * such as the running mean of earlier draws, Section 2.7, saves iterations
  * without changing the law of the draw).
  */
 int ppcg_draw_general(const ppcg_matrix* X, const void* omega, const void* z,
@@ -236,7 +236,7 @@ int ppcg_phi_diag(const ppcg_matrix* X, const void* omega, int32_t dtype,
                   const double* prior_prec, double* diag_out, hipStream_t stream);
 
 /*
- * Initial vector of the CG sampler (Supplement S2, choice of initial vector:
+ * Initial vector of the CG sampler (Supplement S4.1, choice of initial vector:
  * the rescaled running mean).  After draw i, acc += beta^(i) / (tau_prev
  * lambda_prev), with the scales that draw was conditioned on; before the next
  * draw, beta0 = tau lambda * (acc / count) with its scales, passed as beta0 of

@@ -266,7 +266,7 @@ def pcg_many(matvec_cols, B, m, tol=1e-10, criterion=REL_PRECOND, max_iter=None)
 def pcg_solve(X, omega, lam, tau, b, beta0=None, tol=1e-10,
               criterion=REL_PRECOND, max_iter=None, keep_iterates=False):
     """Prior-preconditioned CG on Phi beta = b using sparse matvecs only
-    (Sections 2.2-2.4; start beta0 = 0 by default, Section 2.6)."""
+    (Sections 2.2-2.4; start beta0 = 0 by default, Section 2.7)."""
     mv = lambda v: phi_matvec(X, omega, lam, tau, v)  # noqa: E731
     return pcg(mv, b, precond_inverse(lam, tau), beta0, tol, criterion,
                max_iter, keep_iterates)
@@ -322,7 +322,7 @@ def sampler_draw(X, omega, z, lam, tau, eta, delta, tol=1e-10,
     return b, pcg_solve(X, omega, lam, tau, b, None, tol, criterion, max_iter)
 
 
-# ---- general diagonal prior and preconditioner (Supplement S4.4) ----
+# ---- general diagonal prior and preconditioner (Supplement S4.3) ----
 # Coefficients estimated without shrinkage (an intercept, effects of
 # interest) get independent N(0, sigma_j^2) priors, sigma_j = infinity for a
 # flat prior: Phi = X^T Omega X + diag(d) with d_j = sigma_j^-2 (0 when flat)
@@ -369,7 +369,7 @@ def pcg_solve_general(X, omega, d, m, b, beta0=None, tol=1e-10,
     return pcg(mv, b, m, beta0, tol, criterion, max_iter)
 
 
-# ---- initial vector (Supplement S2: choice of initial vector) ----
+# ---- initial vector (Supplement S4.1: choice of initial vector) ----
 def warm_start_accumulate(acc, beta, lam_prev, tau_prev):
     """Running sum of the draws rescaled by the shrinkage scales they were
     drawn under: acc + beta^(i) / (tau^(i-1) lambda^(i-1))."""
@@ -381,3 +381,35 @@ def warm_start_vector(acc, count, lam, tau):
     """beta0 = tau lambda * (acc / count): the estimate of E[beta / (tau lambda)]
     rescaled by the scales the next draw is conditioned on."""
     return tau * np.asarray(lam, dtype=np.float64) * (np.asarray(acc, dtype=np.float64) / count)
+
+
+def unshrunk_prior_precond(sigma_inv2, draws_q, c, lam, tau):
+    """Prior precision d and preconditioner inverse m of Supplement S4.3 when
+    the leading q + 1 coefficients are unshrunk: d_j = sigma_j^-2 (0 for a
+    flat prior) and m_j = gamma_j^2 = (c eta_hat_j)^2 with eta_hat_j^2 the
+    sample variance (divisor N - 1) of that coefficient over the N earlier
+    draws in `draws_q` (N x (q + 1)); the rest d_j = tau^-2 lambda_j^-2 and
+    m_j = (tau lambda_j)^2.  `lam` has all p entries (its leading q + 1 are
+    not used)."""
+    sigma_inv2 = np.asarray(sigma_inv2, dtype=np.float64)
+    q1 = sigma_inv2.size
+    d = prior_precision(lam, tau)
+    m = precond_inverse(lam, tau)
+    if q1:
+        d[:q1] = sigma_inv2
+        m[:q1] = c * c * np.var(np.asarray(draws_q, dtype=np.float64), axis=0, ddof=1)
+    return d, m
+
+
+def jacobi_precond_inverse(X, omega, d):
+    """M^-1 of the Jacobi preconditioner M = diag(Phi_11, ..., Phi_pp)
+    (Section 3.3, the alternative the paper compares against)."""
+    return 1.0 / phi_diag(X, omega, d)
+
+
+def choose_preconditioner(iters_prior, iters_jacobi):
+    """The adaptive choice of Supplement S5: the preconditioner that reached
+    the stopping rule in fewer iterations on the same draw (one pass-pair
+    each, so iterations measure cost; the Jacobi diagonal's extra column pass
+    is why a tie keeps the prior preconditioner, the paper's first choice)."""
+    return "jacobi" if iters_jacobi < iters_prior else "prior"

@@ -461,7 +461,7 @@ def _f64(v, n, name):
 def solve_general(X, omega, prior_prec, b, precond_inv=None, beta0=None, **opts):
     """beta = Phi^-1 b with Phi = X^T Omega X + diag(prior_prec) by CG with
     M^-1 = diag(precond_inv) (default 1 / prior_prec); prior_prec and
-    precond_inv are float64 (Supplement S4.4).  Returns (beta, info dict)."""
+    precond_inv are float64 (Supplement S4.3).  Returns (beta, info dict)."""
     torch = _torch()
     dt = _dtype_of(b)
     o = make_options(dtype=dt, **opts)
@@ -511,7 +511,7 @@ def phi_diag(X, omega, prior_prec):
 
 
 class WarmStart:
-    """Rescaled running mean of the draws (Supplement S2): add(beta, lam, tau)
+    """Rescaled running mean of the draws (Supplement S4.1): add(beta, lam, tau)
     after each draw with the scales it was drawn under; vector(lam, tau) gives
     beta0 for the next draw under its scales (None before the first add)."""
 

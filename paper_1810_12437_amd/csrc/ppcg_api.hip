@@ -506,7 +506,7 @@ int ppcg_draw(const ppcg_matrix* Xc, const void* omega, const void* z, const voi
   return status;
 }
 
-// ---- general diagonal prior and preconditioner (Supplement S4.4) ----
+// ---- general diagonal prior and preconditioner (Supplement S4.3) ----
 static int prepare_general(ppcg_matrix* X, const void* omega, const double* prior_prec,
                            const double* precond_inv, int dtype, hipStream_t st) {
   PPCG_TRY_HIP(launch_prep_general(prior_prec, precond_inv, omega, dtype, X->n, X->p, X->d, X->m,

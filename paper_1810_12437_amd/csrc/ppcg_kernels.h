@@ -192,7 +192,7 @@ hipError_t launch_prep(const void* lambda, const void* omega, int dtype, double 
                        int64_t n, int64_t p, double* d, double* m, double* omega64,
                        hipStream_t st);
 
-// General diagonal prior (Supplement S4.4): d = prior_prec, m = precond_inv
+// General diagonal prior (Supplement S4.3): d = prior_prec, m = precond_inv
 // (NULL: 1 / prior_prec), omega64 as launch_prep.
 hipError_t launch_prep_general(const double* prior_prec, const double* precond_inv,
                                const void* omega, int dtype, int64_t n, int64_t p, double* d,

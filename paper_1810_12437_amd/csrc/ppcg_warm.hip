@@ -1,4 +1,4 @@
-// Initial vector of the CG sampler (Supplement S2, choice of initial vector):
+// Initial vector of the CG sampler (Supplement S4.1, choice of initial vector):
 // a running sum of the draws rescaled by the shrinkage scales they were drawn
 // under, and the next start beta0 = tau lambda * (sum / count).
 #include <hip/hip_runtime.h>

@@ -1,5 +1,5 @@
 """GPU parity of the general diagonal prior and preconditioner (Supplement
-S4.4): a flat-prior intercept column and N(0, sigma^2) coefficients beside
+S4.3): a flat-prior intercept column and N(0, sigma^2) coefficients beside
 shrunk ones, the Jacobi preconditioner from diag(Phi), and warm starts —
 against the oracle's Cholesky solution of the same b (1e-10 relative in FP64
 at tight tolerance, 1e-5 in the FP32 form)."""
@@ -174,7 +174,7 @@ def test_warm_start_vector_matches_oracle(dt):
 def test_warm_start_from_past_draws():
     """Draws from one conditional: the start vector is the sample mean of 16
     draws, whose squared Phi-norm distance to the conditional mean mu (the
-    target Supplement S2 sets for the start) has expectation p / 16 against p
+    target Supplement S4.1 sets for the start) has expectation p / 16 against p
     for the previous draw; CG from it reaches the Cholesky solution.  The
     iteration counts are reported: the paper finds the initial vector changes
     them by about 10% at most."""

@@ -1,5 +1,5 @@
 """Pins of the oracle's general diagonal prior and preconditioner (Supplement
-S4.4: coefficients without shrinkage get N(0, sigma_j^2) priors, flat when
+S4.3: coefficients without shrinkage get N(0, sigma_j^2) priors, flat when
 sigma_j is infinite, and preconditioner scales gamma_j of the caller's
 choice).  Checked against closed forms, the Cholesky solution, the
 eigenvalue bounds the supplement relies on, and the law of Prop 2.1."""
@@ -127,7 +127,7 @@ def test_general_b_law():
 def test_warm_start_estimator_recovers_the_mean():
     """With draws from a fixed conditional, the rescaled running mean is the
     sample mean of the draws, so beta0 -> the conditional mean mu, the target
-    Supplement S2 sets for the start: its squared Phi-norm distance to mu has
+    Supplement S4.1 sets for the start: its squared Phi-norm distance to mu has
     expectation p / N against p for the last draw, and CG from it converges."""
     X, omega, z, d, m, Phi = _mixed(q=0)
     p = Phi.shape[0]
@@ -152,3 +152,58 @@ def test_warm_start_estimator_recovers_the_mean():
     assert np.linalg.norm(cold.beta - exact) <= 1e-6 * np.linalg.norm(exact)
     err = lambda v: float((v - mu) @ Phi @ (v - mu))  # noqa: E731
     assert err(beta0) < 0.05 * err(draws[-1])
+
+
+def test_unshrunk_scales_by_hand_and_by_law():
+    """Supplement S4.3's gamma_j = c eta_hat_j: by hand on two draws (sample
+    variances 2 and 8 with divisor N - 1), and from many draws of a known
+    Gaussian the estimate approaches its variances; the shrunk block keeps
+    tau^-2 lambda^-2 and (tau lambda)^2."""
+    lam = np.array([7.0, 7.0, 0.5, 2.0])
+    tau = 0.1
+    d, m = R.unshrunk_prior_precond([0.0, 1.0 / 9.0], [[1.0, 10.0], [3.0, 14.0]], 2.0, lam, tau)
+    assert np.array_equal(d, [0.0, 1.0 / 9.0, 1.0 / (0.1 * 0.5) ** 2, 1.0 / (0.1 * 2.0) ** 2])
+    assert np.allclose(m, [4.0 * 2.0, 4.0 * 8.0, (0.1 * 0.5) ** 2, (0.1 * 2.0) ** 2], rtol=1e-15)
+    d0, m0 = R.unshrunk_prior_precond([], np.zeros((3, 0)), 2.0, lam, tau)
+    assert np.allclose(d0 * m0, 1.0, rtol=1e-15)
+    rng = np.random.default_rng(8)
+    sd = np.array([0.3, 2.0, 11.0])
+    draws = np.array([-3.0, 0.0, 40.0]) + sd * rng.standard_normal((20_000, 3))
+    _, m = R.unshrunk_prior_precond(np.zeros(3), draws, 1.0, np.ones(5), 1.0)
+    assert np.allclose(np.sqrt(m[:3]), sd, rtol=0.02)
+
+
+def test_jacobi_preconditioned_phi_has_unit_diagonal():
+    """M = diag(Phi): M^-1/2 Phi M^-1/2 has ones on its diagonal, with the
+    diagonal taken from the dense Phi."""
+    X, omega, z, d, m, Phi = _mixed(q=2)
+    mj = R.jacobi_precond_inverse(X, omega, d)
+    assert np.allclose(mj, 1.0 / np.diag(Phi), rtol=1e-14)
+    S_ = np.sqrt(mj)[:, None] * Phi * np.sqrt(mj)[None, :]
+    assert np.allclose(np.diag(S_), 1.0, rtol=1e-14)
+
+
+def test_preconditioner_choice_on_diagonal_systems():
+    """A design with one non-zero per row makes X^T Omega X diagonal: the
+    Jacobi preconditioner then makes Phi the identity, CG stops after one
+    iteration and the choice is Jacobi, while the prior preconditioner needs
+    as many iterations as Phi~ has distinct eigenvalues.  With X = 0 both
+    preconditioners equal Phi and tie, and a tie keeps the prior one."""
+    rng = np.random.default_rng(12)
+    n, p = 40, 8
+    cols = rng.integers(0, p, n)
+    X = sp.csr_matrix((np.ones(n), cols, np.arange(n + 1)), shape=(n, p))
+    omega = rng.gamma(1.0, 0.25, n) + 0.01
+    lam = np.exp(rng.standard_normal(p))
+    d = R.prior_precision(lam, 0.5)
+    b = rng.standard_normal(p)
+    jac = R.pcg_solve_general(X, omega, d, R.jacobi_precond_inverse(X, omega, d), b, tol=1e-12)
+    pri = R.pcg_solve_general(X, omega, d, 1.0 / d, b, tol=1e-12)
+    assert jac.iters == 1
+    assert pri.iters == np.unique(np.round(1.0 + np.bincount(cols, omega, p) / d, 12)).size
+    assert R.choose_preconditioner(pri.iters, jac.iters) == "jacobi"
+    Z = sp.csr_matrix((n, p))
+    jz = R.pcg_solve_general(Z, omega, d, R.jacobi_precond_inverse(Z, omega, d), b, tol=1e-12)
+    pz = R.pcg_solve_general(Z, omega, d, 1.0 / d, b, tol=1e-12)
+    assert jz.iters == pz.iters == 1
+    assert R.choose_preconditioner(pz.iters, jz.iters) == "prior"
