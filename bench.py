@@ -10,8 +10,10 @@ and 50 signal columns, relative preconditioned residual 1e-6.
 Prints one JSON line: draws/s of the headline form (FP64 vectors and
 scalars, the faster form at the 1e-5 accuracy bar), the FP32-vector form with
 its FP64 refinement beside it, the HBM roofline of the dominant kernel (the X
-pass, timed with HIP events on the solver's stream during the timed draws)
-and the CPU oracle timed on this host as a baseline.
+pass, timed with HIP events on the solver's stream during the timed draws),
+the general-prior forms on the same draws (prior preconditioner cold and
+warm-started, Jacobi, the adaptive switch) and the CPU oracle timed on this
+host as a baseline.
 
 ``--copy-calibration`` instead times a plain 512 MiB device copy: its
 FETCH_SIZE / WRITE_SIZE counters calibrate the pass kernel's counters.
@@ -69,6 +71,8 @@ def parse():
                     help="skip the accuracy check of the timed configuration")
     ap.add_argument("--cpu-draws", type=int, default=2,
                     help="complete oracle draws in the bounded CPU sample")
+    ap.add_argument("--no-precond", action="store_true",
+                    help="skip the prior / warm-start / Jacobi / switch comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--form", choices=("single", "batched", "shared"), default="single",
@@ -177,6 +181,73 @@ def cpu_baseline(P, tol, draws):
                    f"draws (Prop 2.1 b, PCG to relative preconditioned residual {tol:g}; "
                    f"{', '.join(map(str, iters))} iterations) in {el:.1f} s"),
     }
+
+
+def precond_forms(pk, torch, P, X, steps, warmup, tol):
+    """The general-prior entry points on the same workload and draws (FP64):
+    the prior preconditioner through ppcg_draw_general (cold, and warm-started
+    from the rescaled running mean of the draws before it), the Jacobi
+    preconditioner (its M^-1 recomputed every draw), and the adaptive switch
+    (a trial of both on its first draw).  Each with the relative error of
+    draw (SEED, 0, 0) against the oracle's stored solution."""
+    gold = os.path.join(ROOT, "tests", "golden", "c1_draw0_reference.npz")
+    ref = np.load(gold)["beta_f64"] if os.path.exists(gold) else None
+    om = torch.as_tensor(P.omega, device="cuda")
+    zz = torch.as_tensor(P.z, device="cuda")
+    la = torch.as_tensor(P.lam, device="cuda")
+    d, m = pk.unshrunk_setup(la, P.tau)
+    out = {}
+
+    def err(beta):
+        if ref is None:
+            return None
+        return float(np.linalg.norm(beta.cpu().numpy() - ref) / np.linalg.norm(ref))
+
+    def timed(name, one):
+        for w in range(warmup):
+            one(1000 + w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = [one(k) for k in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"draws_per_s": steps / el, "cg_iters_mean": float(np.mean(its))}
+
+    def prior(k):
+        _, i = pk.draw_general(X, om, zz, d, SEED, 0, k, precond_inv=m, tol=tol)
+        return i["iters"] + i["refine_iters"]
+
+    timed("prior", prior)
+    out["prior"]["rel_err_vs_oracle"] = err(pk.draw_general(X, om, zz, d, SEED, 0, 0,
+                                                            precond_inv=m, tol=tol)[0])
+    ws = pk.WarmStart(P.p)
+
+    def warm(k):
+        b0 = ws.vector(la, P.tau)
+        beta, i = pk.draw_general(X, om, zz, d, SEED, 0, k, precond_inv=m, beta0=b0, tol=tol)
+        ws.add(beta, la, P.tau)
+        return i["iters"] + i["refine_iters"]
+
+    timed("prior_warm_start", warm)
+
+    def jacobi(k):
+        mj = pk.jacobi_precond(X, om, d)
+        _, i = pk.draw_general(X, om, zz, d, SEED, 0, k, precond_inv=mj, tol=tol)
+        return i["iters"] + i["refine_iters"]
+
+    timed("jacobi", jacobi)
+    out["jacobi"]["rel_err_vs_oracle"] = err(pk.draw_general(
+        X, om, zz, d, SEED, 0, 0, precond_inv=pk.jacobi_precond(X, om, d), tol=tol)[0])
+    sw = pk.Switch(P.p, period=100)
+
+    def switch(k):
+        _, i = sw.draw(X, om, zz, d, SEED, 0, k, precond_inv=m, tol=tol)
+        return i["iters"] + i["refine_iters"]
+
+    timed("switch_period_100", switch)
+    out["switch_period_100"].update(sw.state())
+    sw.close()
+    return out
 
 
 def copy_calibration():
@@ -434,6 +505,11 @@ def main():
             "refined_draws": int(sum(i["refined"] for i in r32["infos"])),
             "rel_err_vs_oracle": rel.get("f32"),
         }
+    if not args.no_precond:
+        print(f"[bench] preconditioner forms ({args.warmup}+{args.steps} draws each)",
+              file=sys.stderr, flush=True)
+        out["preconditioner_forms"] = precond_forms(pk, torch, P, X, args.steps, args.warmup,
+                                                    args.tol)
     if not args.no_cpu:
         print(f"[bench] CPU oracle sample ({args.cpu_draws} draws)", file=sys.stderr,
               flush=True)

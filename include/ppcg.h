@@ -250,6 +250,77 @@ int ppcg_warm_start_vector(void* beta0, const double* acc, double count, const v
                            double tau, int32_t dtype, int64_t p, hipStream_t stream);
 
 /*
+ * Scales of unshrunk coefficients (Supplement S4.3).  The leading q1
+ * coefficients (an intercept, effects of interest) get N(0, sigma_j^2)
+ * priors (sigma_j^-2 = 0: flat) and preconditioner scales gamma_j =
+ * c eta_hat_j, eta_hat_j^2 the variance of beta_j over earlier draws.
+ *
+ * ppcg_moments_update: Welford's update of the running mean and sum of
+ * squared deviations of beta[0:q1) with the count-th draw (count = 1 for the
+ * first; zero both arrays before it).  mean, m2: FP64 device arrays of q1;
+ * beta: p (only q1 read) of `dtype`.
+ *
+ * ppcg_unshrunk_setup: writes prior_prec (d) and, if not NULL, precond_inv
+ * (m = M^-1) for ppcg_draw_general: d_j = sigma_inv2[j], m_j = c^2 m2[j] /
+ * (count - 1) for j < q1 (NaN where that variance is not positive, so a solve
+ * with it reports PPCG_EBREAKDOWN); d_j = (tau lambda_j)^-2, m_j = (tau
+ * lambda_j)^2 beyond.  q1 = 0 gives the shrinkage prior and preconditioner
+ * (sigma_inv2, m2 unused).  lambda: p of `dtype` (entries below q1 unused);
+ * sigma_inv2, m2: FP64 device arrays of q1; count >= 2 and c > 0 (the paper
+ * takes c >= 1) when precond_inv is wanted and q1 > 0.
+ *
+ * Both are asynchronous on `stream`; PPCG_EINVAL for bad arguments.
+ */
+int ppcg_moments_update(double* mean, double* m2, const void* beta, int32_t dtype, int64_t q1,
+                        int64_t count, hipStream_t stream);
+int ppcg_unshrunk_setup(double* prior_prec, double* precond_inv, const double* sigma_inv2,
+                        const double* m2, int64_t count, double c, const void* lambda, double tau,
+                        int32_t dtype, int64_t q1, int64_t p, hipStream_t stream);
+
+/*
+ * Jacobi preconditioner (the alternative of Sections 2.4 and 3.3): writes
+ * precond_inv = 1 / diag(Phi) = 1 / (X^T omega + prior_prec), one column
+ * pass over omega.  Arguments as ppcg_phi_diag; precond_inv: FP64 device
+ * array of p.  Asynchronous on `stream`.
+ */
+int ppcg_jacobi_precond(const ppcg_matrix* X, const void* omega, int32_t dtype,
+                        const double* prior_prec, double* precond_inv, hipStream_t stream);
+
+/*
+ * Adaptive choice between the prior and the Jacobi preconditioner
+ * (Supplement S5.3: compare the two every so many Gibbs iterations and keep
+ * the better).  A switch serves one chain of dimension p on one stream at a
+ * time and owns p-sized device workspace (the Jacobi M^-1 and a second
+ * draw).
+ *
+ * ppcg_draw_switch draws as ppcg_draw_general with the caller's prior
+ * preconditioner `precond_inv` (NULL: 1 / prior_prec) or with the Jacobi
+ * one, whichever the switch holds.  Its first draw and every period-th
+ * after it is a trial: the same draw (same b, same beta0) is solved under
+ * both, the one that met the stopping rule in fewer CG iterations (first
+ * phase plus refinement) is kept and its result returned; a tie, or a Jacobi
+ * solve that did not converge, keeps the prior preconditioner (the paper's
+ * first choice).  The Jacobi M^-1 is recomputed each draw it is used
+ * (omega changes between Gibbs steps).  Returns and blocks as
+ * ppcg_draw_general.
+ *
+ * ppcg_switch_state: the current choice (PPCG_PRECOND_*), the draws made
+ * and the two iteration counts of the last trial (-1 before the first);
+ * NULL outputs are skipped.
+ */
+#define PPCG_PRECOND_PRIOR 0
+#define PPCG_PRECOND_JACOBI 1
+typedef struct ppcg_switch ppcg_switch;
+int ppcg_switch_create(ppcg_switch** out, int64_t p, int32_t period);
+int ppcg_switch_destroy(ppcg_switch* S);
+int ppcg_switch_state(const ppcg_switch* S, int32_t* choice, int64_t* draws,
+                      int32_t* iters_prior, int32_t* iters_jacobi);
+int ppcg_draw_switch(ppcg_switch* S, const ppcg_matrix* X, const void* omega, const void* z,
+                     const double* prior_prec, const double* precond_inv, const void* beta0,
+                     uint64_t seed, uint64_t chain, uint64_t draw_index, const ppcg_options* opt,
+                     void* beta_out, ppcg_info* info, hipStream_t stream);
+
+/*
  * Adjoint of beta = Phi(lambda, tau)^-1 b for a loss L with g = dL/dbeta:
  * solves Phi a = g with the same preconditioned CG, then
  *   grad_b = a,  grad_loglambda_j = 2 d_j a_j beta_j,  grad_logtau = sum_j of those,

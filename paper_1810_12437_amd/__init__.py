@@ -19,7 +19,8 @@ __all__ = [
     "F64", "F32", "REL_PRECOND", "RMS_PRECOND_ABS", "REL_PLAIN",
     "STREAM_ETA", "STREAM_DELTA", "Matrix", "Batch", "Options", "Info", "Chain",
     "phi_matvec", "normals", "rhs", "solve", "draw", "solve_backward",
-    "solve_general", "draw_general", "phi_diag", "WarmStart",
+    "solve_general", "draw_general", "phi_diag", "WarmStart", "moments_update",
+    "unshrunk_setup", "jacobi_precond", "Switch", "PRECOND_PRIOR", "PRECOND_JACOBI",
     "PPCGSolve", "PPCGError", "PPCGUnavailable", "lib", "LIB_PATH", "EXPORTED_SYMBOLS",
 ]
 
@@ -43,6 +44,8 @@ EXPORTED_SYMBOLS = (
     "ppcg_draw_batched", "ppcg_solve_batched",
     "ppcg_solve_general", "ppcg_draw_general", "ppcg_phi_diag",
     "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
+    "ppcg_moments_update", "ppcg_unshrunk_setup", "ppcg_jacobi_precond",
+    "ppcg_switch_create", "ppcg_switch_destroy", "ppcg_switch_state", "ppcg_draw_switch",
 )
 
 
@@ -115,6 +118,16 @@ def _declare(L):
     L.ppcg_phi_diag.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
     L.ppcg_warm_start_accumulate.argtypes = [_vp, _vp, _vp, _dbl, _i32, _i64, _vp]
     L.ppcg_warm_start_vector.argtypes = [_vp, _vp, _dbl, _vp, _dbl, _i32, _i64, _vp]
+    L.ppcg_moments_update.argtypes = [_vp, _vp, _vp, _i32, _i64, _i64, _vp]
+    L.ppcg_unshrunk_setup.argtypes = [_vp, _vp, _vp, _vp, _i64, _dbl, _vp, _dbl, _i32, _i64,
+                                      _i64, _vp]
+    L.ppcg_jacobi_precond.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
+    L.ppcg_switch_create.argtypes = [ctypes.POINTER(_vp), _i64, _i32]
+    L.ppcg_switch_destroy.argtypes = [_vp]
+    L.ppcg_switch_state.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                                    ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+    L.ppcg_draw_switch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _u64, _u64, _vp,
+                                   _vp, _vp, _vp]
     L.ppcg_solve_backward.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, ctypes.POINTER(Options),
                                       _vp, _vp, _vp, ctypes.POINTER(Info), _vp]
     L.ppcg_matrix_profile.argtypes = [_vp, _i32]
@@ -133,7 +146,10 @@ def _declare(L):
                  "ppcg_solve_batched", "ppcg_matrix_pass_bytes", "ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
                  "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
                  "ppcg_solve_backward", "ppcg_solve_general", "ppcg_draw_general",
-                 "ppcg_phi_diag", "ppcg_warm_start_accumulate", "ppcg_warm_start_vector"):
+                 "ppcg_phi_diag", "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
+                 "ppcg_moments_update", "ppcg_unshrunk_setup", "ppcg_jacobi_precond",
+                 "ppcg_switch_create", "ppcg_switch_destroy", "ppcg_switch_state",
+                 "ppcg_draw_switch"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -542,6 +558,99 @@ class WarmStart:
                                           float(tau), dt, self.p, _stream())
         _check(rc, "ppcg_warm_start_vector")
         return out
+
+
+PRECOND_PRIOR, PRECOND_JACOBI = 0, 1
+
+
+def moments_update(mean, m2, beta, count):
+    """Welford update of the running mean / squared deviations of the leading
+    len(mean) coefficients with the count-th draw (Supplement S4.3)."""
+    dt = _dtype_of(beta)
+    q1 = mean.numel()
+    rc = lib().ppcg_moments_update(_f64(mean, q1, "mean"), _f64(m2, q1, "m2"),
+                                   _dev(beta, dt, beta.numel(), "beta"), dt, q1, int(count),
+                                   _stream())
+    _check(rc, "ppcg_moments_update")
+
+
+def unshrunk_setup(lam, tau, sigma_inv2=None, m2=None, count=0, c=1.0, want_precond=True):
+    """(prior_prec, precond_inv) for ppcg_draw_general: the leading
+    len(sigma_inv2) coefficients unshrunk with gamma_j^2 = c^2 m2_j/(count-1),
+    the rest tau^-2 lambda^-2 and (tau lambda)^2 (Supplement S4.3)."""
+    torch = _torch()
+    dt = _dtype_of(lam)
+    p = lam.numel()
+    q1 = 0 if sigma_inv2 is None else sigma_inv2.numel()
+    d = torch.empty(p, dtype=torch.float64, device=lam.device)
+    m = torch.empty_like(d) if want_precond else None
+    rc = lib().ppcg_unshrunk_setup(
+        ctypes.c_void_p(d.data_ptr()), None if m is None else ctypes.c_void_p(m.data_ptr()),
+        None if sigma_inv2 is None else _f64(sigma_inv2, q1, "sigma_inv2"),
+        None if m2 is None else _f64(m2, q1, "m2"), int(count), float(c),
+        _dev(lam, dt, p, "lambda"), float(tau), dt, q1, p, _stream())
+    _check(rc, "ppcg_unshrunk_setup")
+    return d, m
+
+
+def jacobi_precond(X, omega, prior_prec):
+    """M^-1 = 1 / diag(Phi), the Jacobi preconditioner (float64)."""
+    torch = _torch()
+    dt = _dtype_of(omega)
+    out = torch.empty(X.p, dtype=torch.float64, device=omega.device)
+    rc = lib().ppcg_jacobi_precond(X.handle, _dev(omega, dt, X.n, "omega"), dt,
+                                   _f64(prior_prec, X.p, "prior_prec"),
+                                   ctypes.c_void_p(out.data_ptr()), _stream())
+    _check(rc, "ppcg_jacobi_precond")
+    return out
+
+
+class Switch:
+    """Adaptive prior / Jacobi preconditioner choice (Supplement S5.3): every
+    period-th draw solves the same draw under both and keeps the one with
+    fewer CG iterations."""
+
+    def __init__(self, p, period=100):
+        self.handle = ctypes.c_void_p()
+        _check(lib().ppcg_switch_create(ctypes.byref(self.handle), int(p), int(period)),
+               "ppcg_switch_create")
+        self.p = int(p)
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ppcg_switch_destroy(h)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state(self):
+        c, n, ip, ij = _i32(), _i64(), _i32(), _i32()
+        _check(lib().ppcg_switch_state(self.handle, ctypes.byref(c), ctypes.byref(n),
+                                       ctypes.byref(ip), ctypes.byref(ij)), "ppcg_switch_state")
+        return {"choice": "jacobi" if c.value == PRECOND_JACOBI else "prior", "draws": n.value,
+                "iters_prior": ip.value, "iters_jacobi": ij.value}
+
+    def draw(self, X, omega, z, prior_prec, seed, chain=0, draw_index=0, precond_inv=None,
+             beta0=None, **opts):
+        torch = _torch()
+        dt = _dtype_of(omega)
+        o = make_options(dtype=dt, **opts)
+        beta = torch.empty(X.p, dtype=omega.dtype, device=omega.device)
+        info = Info()
+        rc = lib().ppcg_draw_switch(
+            self.handle, X.handle, _dev(omega, dt, X.n, "omega"), _dev(z, dt, X.n, "z"),
+            _f64(prior_prec, X.p, "prior_prec"),
+            None if precond_inv is None else _f64(precond_inv, X.p, "precond_inv"),
+            None if beta0 is None else _dev(beta0, dt, X.p, "beta0"), int(seed), int(chain),
+            int(draw_index), ctypes.byref(o), _dev(beta, dt, X.p, "beta"), ctypes.byref(info),
+            _stream())
+        _check(rc, "ppcg_draw_switch", solver=True)
+        return beta, info.as_dict()
 
 
 def solve_backward(X, omega, lam, tau, beta, grad_beta, **opts):

@@ -177,3 +177,30 @@ def test_warm_start_entry_points_reject_bad_arguments():
     assert L.ppcg_warm_start_vector(one, one, 0.0, one, 1.0, pk.F64, 4, None) == pk.EINVAL
     assert L.ppcg_warm_start_vector(one, one, 2.0, one, float("nan"), pk.F64, 4, None) == pk.EINVAL
     assert L.ppcg_warm_start_vector(one, None, 2.0, one, 1.0, pk.F32, 4, None) == pk.EINVAL
+
+
+def test_gibbs_helpers_reject_bad_arguments():
+    """Moments, unshrunk set-up, Jacobi and switch entry points check their
+    arguments before any launch; a switch is created and destroyed without a
+    device only when its arguments are bad."""
+    L = pk.lib()
+    one = ctypes.c_void_p(1)  # never dereferenced: every call below fails its checks first
+    assert L.ppcg_moments_update(None, one, one, pk.F64, 3, 1, None) == pk.EINVAL
+    assert L.ppcg_moments_update(one, one, one, pk.F64, 0, 1, None) == pk.EINVAL
+    assert L.ppcg_moments_update(one, one, one, pk.F64, 3, 0, None) == pk.EINVAL
+    assert L.ppcg_unshrunk_setup(one, one, one, one, 1, 2.0, one, 1.0, pk.F64, 2, 5,
+                                 None) == pk.EINVAL  # count < 2
+    assert L.ppcg_unshrunk_setup(one, one, one, one, 5, 0.0, one, 1.0, pk.F64, 2, 5,
+                                 None) == pk.EINVAL  # c <= 0
+    assert L.ppcg_unshrunk_setup(one, one, None, one, 5, 2.0, one, 1.0, pk.F64, 2, 5,
+                                 None) == pk.EINVAL  # no sigma
+    assert L.ppcg_unshrunk_setup(one, None, one, None, 5, 2.0, one, 1.0, pk.F64, 6, 5,
+                                 None) == pk.EINVAL  # q1 > p
+    assert L.ppcg_jacobi_precond(None, one, pk.F64, one, one, None) == pk.EINVAL
+    h = ctypes.c_void_p()
+    assert L.ppcg_switch_create(ctypes.byref(h), 0, 100) == pk.EINVAL
+    assert L.ppcg_switch_create(ctypes.byref(h), 10, 0) == pk.EINVAL
+    assert L.ppcg_switch_destroy(None) == pk.EINVAL
+    assert L.ppcg_switch_state(None, None, None, None, None) == pk.EINVAL
+    assert L.ppcg_draw_switch(None, None, None, None, None, None, None, 0, 0, 0, None, None,
+                              None, None) == pk.EINVAL

@@ -203,3 +203,100 @@ def test_warm_start_from_past_draws():
         f"{e_prev:.1f} (p = {P.p}); iters cold {cold['iters']} warm {warm['iters']}")
     assert e_mean < 0.25 * e_prev
     assert rel(beta.cpu().numpy(), exact) <= 1e-6
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_unshrunk_scales_match_oracle(dt):
+    """Running moments of the leading q + 1 coefficients over 6 draws, then
+    d and M^-1 of Supplement S4.3, against the oracle's sample variance; a
+    coefficient that never moved gets NaN (a solve with it breaks down)."""
+    rng = np.random.default_rng(31)
+    p, q1, N = 700, 5, 6
+    draws = rng.standard_normal((N, p)) * np.array([0.2, 1.0, 3.0, 10.0, 0.0] + [1.0] * (p - 5))
+    draws[:, :q1] += np.array([5.0, -1.0, 0.0, 30.0, 2.0])
+    lam = np.exp(rng.standard_normal(p))
+    if dt == torch.float32:
+        draws, lam = np.float32(draws).astype(np.float64), np.float32(lam).astype(np.float64)
+    mean = torch.zeros(q1, dtype=torch.float64, device=DEV)
+    m2 = torch.zeros_like(mean)
+    for k in range(N):
+        pk.moments_update(mean, m2, t64(draws[k]).to(dt), k + 1)
+    sig = np.array([0.0, 0.25, 1e-2, 0.0, 1.0])
+    d, m = pk.unshrunk_setup(t64(lam).to(dt), 0.03, sigma_inv2=t64(sig), m2=m2, count=N, c=2.0)
+    d_ref, m_ref = R.unshrunk_prior_precond(sig, draws[:, :q1], 2.0, lam, 0.03)
+    got_d, got_m = d.cpu().numpy(), m.cpu().numpy()
+    assert np.allclose(mean.cpu().numpy(), draws[:, :q1].mean(axis=0), rtol=1e-13, atol=1e-13)
+    assert np.allclose(got_d, d_ref, rtol=1e-15, atol=0)
+    assert np.isnan(got_m[4]) and m_ref[4] == 0.0
+    assert np.allclose(got_m[:4], m_ref[:4], rtol=1e-12, atol=0)
+    assert np.allclose(got_m[q1:], m_ref[q1:], rtol=1e-15, atol=0)
+    d0, m0 = pk.unshrunk_setup(t64(lam).to(dt), 0.03)
+    assert np.allclose(d0.cpu().numpy(), R.prior_precision(lam, 0.03), rtol=1e-15, atol=0)
+    assert np.allclose(m0.cpu().numpy(), R.precond_inverse(lam, 0.03), rtol=1e-15, atol=0)
+
+
+def test_jacobi_precond_matches_oracle():
+    P, X, Xs, d, m, Phi = setup(seed=12)
+    got = pk.jacobi_precond(X, t64(P.omega), t64(d)).cpu().numpy()
+    ref = R.jacobi_precond_inverse(Xs, P.omega, d)
+    assert rel(got, ref) <= 1e-13
+
+
+def duplicated_pairs(n=3000, p=400, pairs=100, seed=5):
+    """Binary design whose first 2 * pairs columns come in identical pairs,
+    weakly shrunk (tau = 1, lambda log-uniform in [1, 10]); the rest strongly
+    shrunk.  Jacobi scaling leaves eigenvalues near d / (2 a) for each pair,
+    the prior preconditioner none below 1."""
+    rng = np.random.default_rng(seed)
+    dense = rng.random((n, p)) < 0.02
+    for k in range(pairs):
+        col = rng.random(n) < rng.uniform(0.05, 0.3)
+        dense[:, 2 * k] = col
+        dense[:, 2 * k + 1] = col
+    Xs = sp.csr_matrix(dense.astype(np.float64))
+    omega = rng.gamma(1.0, 0.25, n) + 0.01
+    z = rng.standard_normal(n)
+    lam = np.full(p, 1e-3)
+    lam[:2 * pairs] = np.exp(rng.uniform(0.0, np.log(10.0), 2 * pairs))
+    d = R.prior_precision(lam, 1.0)
+    X = pk.Matrix(n, p, Xs.indptr.astype(np.int64), Xs.indices.astype(np.int32))
+    return X, Xs, omega, z, d
+
+
+@pytest.mark.parametrize("case", ["jacobi_wins", "prior_wins"])
+def test_switch_choice_and_draws(case):
+    """The switch's trial picks the preconditioner the oracle's CG needs fewer
+    iterations with (cases chosen with a wide margin), returns that draw (it
+    matches Cholesky), and the next draws use the kept choice until the next
+    trial."""
+    if case == "jacobi_wins":
+        P = synth.scaled_problem(3000, 400, seed=5, tau=2e-2)
+        X = pk.Matrix.from_problem(P)
+        Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+        d = R.prior_precision(P.lam, P.tau)
+        omega, z = P.omega, P.z
+        Phi = R.phi_dense_general(Xs, omega, d)
+    else:
+        X, Xs, omega, z, d = duplicated_pairs()
+        Phi = R.phi_dense_general(Xs, omega, d)
+    n, p = Xs.shape
+    bref = np.random.default_rng(3).standard_normal(p)
+    ip = R.pcg_solve_general(Xs, omega, d, 1.0 / d, bref, tol=1e-8).iters
+    ij = R.pcg_solve_general(Xs, omega, d, R.jacobi_precond_inverse(Xs, omega, d), bref,
+                             tol=1e-8).iters
+    want = R.choose_preconditioner(ip, ij)
+    S = pk.Switch(p, period=3)
+    for k in range(4):
+        beta, info = S.draw(X, t64(omega), t64(z), t64(d), 7, 0, k, tol=1e-12)
+        st = S.state()
+        eta, delta = H.eta_delta(7, 0, k, n, p)
+        exact = R.solve_chol(Phi, R.rhs_b_general(Xs, omega, z, d, eta, delta))
+        e = rel(beta.cpu().numpy(), exact)
+        say(f"[switch {case}] draw {k}: {st} iters {info['iters']} rel err {e:.2e} "
+            f"(oracle at 1e-8: prior {ip}, jacobi {ij})")
+        assert st["choice"] == want and st["draws"] == k + 1
+        assert info["status"] == pk.OK and e <= (1e-10 if case == "jacobi_wins" else 1e-7)
+        if k in (0, 3):   # trials
+            chosen = st["iters_jacobi"] if want == "jacobi" else st["iters_prior"]
+            assert info["iters"] + info["refine_iters"] == chosen
+    S.close()
