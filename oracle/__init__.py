@@ -12,6 +12,8 @@ ppcg_ref   Phi (dense and matrix-free), Prop 2.1 right-hand side, Cholesky
            solve and draw, preconditioned CG, adjoint gradient.
 philox_ref Philox4x64-10 counter-based generator and the Box-Muller normals
            the sampler draws eta and delta from.
+pg_ref     Polya-Gamma PG(1, c) draws (Devroye's exact sampler) and the
+           pseudo-response of the Gibbs cycle's omega update.
 stats_ref  Chi-square tests of draws against N(mu, Phi^-1) and N(m, Phi).
 theory_ref The convergence bounds of Section 2 (used as test pins).
 
@@ -19,4 +21,4 @@ Every function names the passage of the paper it follows.  Parity status of
 each function (what pins it to something other than itself) is listed in the
 test modules ``tests/test_oracle_*.py``.
 """
-from . import philox_ref, ppcg_ref, stats_ref, theory_ref  # noqa: F401
+from . import pg_ref, philox_ref, ppcg_ref, stats_ref, theory_ref  # noqa: F401
