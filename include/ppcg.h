@@ -287,6 +287,32 @@ int ppcg_jacobi_precond(const ppcg_matrix* X, const void* omega, int32_t dtype,
                         const double* prior_prec, double* precond_inv, hipStream_t stream);
 
 /*
+ * Polya-Gamma omega update of the Gibbs cycle (Supplement S1, step 3, and
+ * eq. pg_augmented_likelihood).
+ *
+ * ppcg_pg_update: psi = X beta (one FP64 row pass), omega_i ~ PG(1, psi_i)
+ * and z_i = (y_i - 1/2) / omega_i, ready for ppcg_draw / ppcg_draw_general.
+ * beta: p of `dtype`; y: n device bytes, 0 or 1; omega_out, z_out: n of
+ * `dtype`.  Uses the handle's n-sized workspace, so it is ordered with the
+ * handle's other calls on `stream`.  Asynchronous.
+ *
+ * ppcg_pg_sample: omega_i ~ PG(1, c_i) for given FP64 tilts c (device, n),
+ * FP64 output.  Asynchronous.
+ *
+ * Draws are exact (Devroye's alternating-series sampler, as in Polson, Scott
+ * & Windle 2013): PG(1, c) = J*(1, |c|/2) / 4.  Element i uses its own
+ * Philox4x64-10 stream: uniform k is word k % 4 of the block with counter
+ * (i, 2 | (k / 4) << 8, chain, draw_index) and key (seed, 0), mapped to
+ * ((w >> 11) + 1/2) 2^-53; stream word 2 sits beside eta (0) and delta (1).
+ * PPCG_EINVAL for bad arguments.
+ */
+int ppcg_pg_update(const ppcg_matrix* X, const void* beta, const uint8_t* y, uint64_t seed,
+                   uint64_t chain, uint64_t draw_index, int32_t dtype, void* omega_out,
+                   void* z_out, hipStream_t stream);
+int ppcg_pg_sample(const double* c, int64_t n, uint64_t seed, uint64_t chain,
+                   uint64_t draw_index, double* omega_out, hipStream_t stream);
+
+/*
  * Adaptive choice between the prior and the Jacobi preconditioner
  * (Supplement S5.3: compare the two every so many Gibbs iterations and keep
  * the better).  A switch serves one chain of dimension p on one stream at a

@@ -21,6 +21,7 @@ __all__ = [
     "phi_matvec", "normals", "rhs", "solve", "draw", "solve_backward",
     "solve_general", "draw_general", "phi_diag", "WarmStart", "moments_update",
     "unshrunk_setup", "jacobi_precond", "Switch", "PRECOND_PRIOR", "PRECOND_JACOBI",
+    "pg_sample", "pg_update",
     "PPCGSolve", "PPCGError", "PPCGUnavailable", "lib", "LIB_PATH", "EXPORTED_SYMBOLS",
 ]
 
@@ -46,6 +47,7 @@ EXPORTED_SYMBOLS = (
     "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
     "ppcg_moments_update", "ppcg_unshrunk_setup", "ppcg_jacobi_precond",
     "ppcg_switch_create", "ppcg_switch_destroy", "ppcg_switch_state", "ppcg_draw_switch",
+    "ppcg_pg_update", "ppcg_pg_sample",
 )
 
 
@@ -128,6 +130,8 @@ def _declare(L):
                                     ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
     L.ppcg_draw_switch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _u64, _u64, _vp,
                                    _vp, _vp, _vp]
+    L.ppcg_pg_update.argtypes = [_vp, _vp, _vp, _u64, _u64, _u64, _i32, _vp, _vp, _vp]
+    L.ppcg_pg_sample.argtypes = [_vp, _i64, _u64, _u64, _u64, _vp, _vp]
     L.ppcg_solve_backward.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, ctypes.POINTER(Options),
                                       _vp, _vp, _vp, ctypes.POINTER(Info), _vp]
     L.ppcg_matrix_profile.argtypes = [_vp, _i32]
@@ -149,7 +153,7 @@ def _declare(L):
                  "ppcg_phi_diag", "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
                  "ppcg_moments_update", "ppcg_unshrunk_setup", "ppcg_jacobi_precond",
                  "ppcg_switch_create", "ppcg_switch_destroy", "ppcg_switch_state",
-                 "ppcg_draw_switch"):
+                 "ppcg_draw_switch", "ppcg_pg_update", "ppcg_pg_sample"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -651,6 +655,37 @@ class Switch:
             _stream())
         _check(rc, "ppcg_draw_switch", solver=True)
         return beta, info.as_dict()
+
+
+def pg_sample(c, seed, chain=0, draw_index=0):
+    """omega_i ~ PG(1, c_i) for a float64 CUDA vector of tilts (Supplement S1,
+    step 3); float64 output."""
+    torch = _torch()
+    n = c.numel()
+    out = torch.empty(n, dtype=torch.float64, device=c.device)
+    rc = lib().ppcg_pg_sample(_f64(c, n, "c"), n, int(seed), int(chain), int(draw_index),
+                              ctypes.c_void_p(out.data_ptr()), _stream())
+    _check(rc, "ppcg_pg_sample")
+    return out
+
+
+def pg_update(X, beta, y, seed, chain=0, draw_index=0):
+    """The Gibbs cycle's omega update: omega_i ~ PG(1, (X beta)_i) and the
+    pseudo-response z_i = (y_i - 1/2) / omega_i, in beta's dtype; y is a
+    uint8 CUDA vector of 0/1 outcomes.  Returns (omega, z)."""
+    torch = _torch()
+    dt = _dtype_of(beta)
+    if not isinstance(y, torch.Tensor) or not y.is_cuda or y.dtype != torch.uint8 or \
+            y.numel() != X.n or not y.is_contiguous():
+        raise TypeError(f"y must be a contiguous uint8 CUDA vector of length {X.n}")
+    omega = torch.empty(X.n, dtype=beta.dtype, device=beta.device)
+    z = torch.empty_like(omega)
+    rc = lib().ppcg_pg_update(X.handle, _dev(beta, dt, X.p, "beta"),
+                              ctypes.c_void_p(y.data_ptr()), int(seed), int(chain),
+                              int(draw_index), dt, ctypes.c_void_p(omega.data_ptr()),
+                              ctypes.c_void_p(z.data_ptr()), _stream())
+    _check(rc, "ppcg_pg_update")
+    return omega, z
 
 
 def solve_backward(X, omega, lam, tau, beta, grad_beta, **opts):

@@ -506,6 +506,27 @@ int ppcg_draw(const ppcg_matrix* Xc, const void* omega, const void* z, const voi
   return status;
 }
 
+// ---- Polya-Gamma omega update (Supplement S1, step 3) ----
+int ppcg_pg_update(const ppcg_matrix* Xc, const void* beta, const uint8_t* y, uint64_t seed,
+                   uint64_t chain, uint64_t draw_index, int32_t dtype, void* omega_out,
+                   void* z_out, hipStream_t st) {
+  ppcg_matrix* X = const_cast<ppcg_matrix*>(Xc);
+  if (!X || !beta || !y || !omega_out || !z_out || !valid_dtype(dtype)) return PPCG_EINVAL;
+  // psi = X beta in FP64 (the FP32 form converts beta first), into the
+  // n-sized workspace, then one thread per row draws omega and forms z.
+  const double* b64 = reinterpret_cast<const double*>(beta);
+  if (dtype == PPCG_F32) {
+    PPCG_TRY_HIP(launch_convert_to_f64(beta, dtype, X->p, X->beta64, st));
+    b64 = X->beta64;
+  }
+  PPCG_TRY_HIP(row_pass<double>(X, comb_vec<double>(b64), nullptr, nullptr, st));
+  PPCG_TRY_HIP(launch_combine<double, double>(comb_out<double>(X->rows[0], nullptr), X->n,
+                                              X->y64, st));
+  PPCG_TRY_HIP(launch_pg_omega(X->y64, y, X->n, seed, chain, draw_index, dtype, omega_out, z_out,
+                               st));
+  return PPCG_OK;
+}
+
 // ---- general diagonal prior and preconditioner (Supplement S4.3) ----
 static int prepare_general(ppcg_matrix* X, const void* omega, const double* prior_prec,
                            const double* precond_inv, int dtype, hipStream_t st) {

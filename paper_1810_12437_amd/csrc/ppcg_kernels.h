@@ -217,6 +217,10 @@ hipError_t launch_phi_diag(const Combine<double>& c, const double* d, int64_t p,
 hipError_t launch_normals(uint64_t seed, uint64_t stream_id, uint64_t chain, uint64_t draw,
                           int64_t count, double* out, hipStream_t st);
 
+// omega_i ~ PG(1, psi_i) (and, with y, z_i = (y_i - 1/2) / omega_i) in `dtype`.
+hipError_t launch_pg_omega(const double* psi, const uint8_t* y, int64_t n, uint64_t seed,
+                           uint64_t chain, uint64_t draw, int dtype, void* omega_out, void* z_out,
+                           hipStream_t st);
 hipError_t launch_convert_to_f64(const void* in, int dtype, int64_t count, double* out,
                                  hipStream_t st);
 hipError_t launch_convert_from_f64(const double* in, int dtype, int64_t count, void* out,

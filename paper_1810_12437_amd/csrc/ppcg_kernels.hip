@@ -16,6 +16,7 @@
 // results are bitwise reproducible.  Reductions of the p-vector phases are
 // fixed-order too.
 #include "ppcg_kernels.h"
+#include "ppcg_philox.h"
 
 #include <hip/hip_ext.h>
 
@@ -1038,27 +1039,8 @@ template hipError_t launch_combine<double, double>(const Combine<double>&, int64
                                                    hipStream_t);
 
 // ------------------------------------------------------------------------
-// Philox4x64-10 and Box-Muller normals
+// Box-Muller normals from Philox4x64-10 blocks
 // ------------------------------------------------------------------------
-struct U64x4 {
-  uint64_t x0, x1, x2, x3;
-};
-
-__device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
-  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += W0;
-      k1 += W1;
-    }
-    const uint64_t hi0 = __umul64hi(M0, c.x0), lo0 = M0 * c.x0;
-    const uint64_t hi1 = __umul64hi(M1, c.x2), lo1 = M1 * c.x2;
-    c = U64x4{hi1 ^ c.x1 ^ k0, lo1, hi0 ^ c.x3 ^ k1, lo0};
-  }
-  return c;
-}
 
 // Four N(0,1) values of counter block i of stream `stream_id`.
 __device__ __forceinline__ void normals4(uint64_t seed, uint64_t stream_id, uint64_t chain,

@@ -204,3 +204,11 @@ def test_gibbs_helpers_reject_bad_arguments():
     assert L.ppcg_switch_state(None, None, None, None, None) == pk.EINVAL
     assert L.ppcg_draw_switch(None, None, None, None, None, None, None, 0, 0, 0, None, None,
                               None, None) == pk.EINVAL
+
+
+def test_pg_entry_points_reject_bad_arguments():
+    L = pk.lib()
+    one = ctypes.c_void_p(1)  # never dereferenced: every call below fails its checks first
+    assert L.ppcg_pg_update(None, one, one, 0, 0, 0, pk.F64, one, one, None) == pk.EINVAL
+    assert L.ppcg_pg_sample(None, 5, 0, 0, 0, one, None) == pk.EINVAL
+    assert L.ppcg_pg_sample(one, -1, 0, 0, 0, one, None) == pk.EINVAL
