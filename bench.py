@@ -12,8 +12,9 @@ scalars, the faster form at the 1e-5 accuracy bar), the FP32-vector form with
 its FP64 refinement beside it, the HBM roofline of the dominant kernel (the X
 pass, timed with HIP events on the solver's stream during the timed draws),
 the general-prior forms on the same draws (prior preconditioner cold and
-warm-started, Jacobi, the adaptive switch) and the CPU oracle timed on this
-host as a baseline.
+warm-started, Jacobi, the adaptive switch), Gibbs steps with the device
+Polya-Gamma omega update, and the CPU oracle timed on this host as a
+baseline.
 
 ``--copy-calibration`` instead times a plain 512 MiB device copy: its
 FETCH_SIZE / WRITE_SIZE counters calibrate the pass kernel's counters.
@@ -53,9 +54,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "9fff0b1047b3e0a01582e1f300297177f38dbb5b9a53b15e1d9d8665e6c58e1d",
+    "sources_sha256": "c936472a580aa486d8dd9e45bd189b0ea775d2bad71386898e1b4cf10f43ee38",
     # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
-    "bytes_per_launch": 120865396,
+    "bytes_per_launch": 120225063,
 }
 
 
@@ -73,6 +74,8 @@ def parse():
                     help="complete oracle draws in the bounded CPU sample")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the prior / warm-start / Jacobi / switch comparison")
+    ap.add_argument("--no-gibbs", action="store_true",
+                    help="skip the Gibbs steps with the device Polya-Gamma update")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--form", choices=("single", "batched", "shared"), default="single",
@@ -247,6 +250,59 @@ def precond_forms(pk, torch, P, X, steps, warmup, tol):
     timed("switch_period_100", switch)
     out["switch_period_100"].update(sw.state())
     sw.close()
+    return out
+
+
+def gibbs_forms(pk, torch, P, X, steps, warmup, tol):
+    """Gibbs steps on the same design: y ~ Bernoulli(logistic(X beta_true))
+    with the 50 signal columns at 1 (seeded), then per step omega ~ PG(1,
+    X beta) and z = (y - 1/2)/omega on the device (Supplement S1, step 3)
+    followed by the beta draw (step 4) with lambda and tau held at the
+    workload's values (their updates depend on the shrinkage prior).  Timed
+    from beta = 0 after `warmup` steps; reported per form: steps/s, mean CG
+    iterations, and the PG update alone (its share of a step)."""
+    rng = np.random.default_rng(SEED + 1)
+    beta_true = np.zeros(P.p)
+    beta_true[:50] = 1.0
+    import scipy.sparse as sp
+    Xs = sp.csr_matrix((np.ones(P.nnz), P.col_idx, P.row_ptr), shape=(P.n, P.p))
+    psi = Xs @ beta_true
+    y = torch.as_tensor((rng.random(P.n) < 1.0 / (1.0 + np.exp(-psi))).astype(np.uint8),
+                        device="cuda")
+    la = torch.as_tensor(P.lam, device="cuda")
+    d, m = pk.unshrunk_setup(la, P.tau)
+    out = {"y_mean": float(y.float().mean().item())}
+
+    def run(name, draw):
+        beta = torch.zeros(P.p, dtype=torch.float64, device="cuda")
+        for w in range(warmup):
+            om, z = pk.pg_update(X, beta, y, SEED, 0, 10_000 + w)
+            beta, _ = draw(om, z, 10_000 + w)
+        torch.cuda.synchronize()
+        its = []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            om, z = pk.pg_update(X, beta, y, SEED, 0, k)
+            beta, info = draw(om, z, k)
+            its.append(info["iters"] + info["refine_iters"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"steps_per_s": steps / el, "cg_iters_mean": float(np.mean(its))}
+        return beta
+
+    beta = run("prior", lambda om, z, k: pk.draw(X, om, z, la, P.tau, SEED, 0, k, tol=tol))
+    sw = pk.Switch(P.p, period=100)
+    run("switch_period_100",
+        lambda om, z, k: sw.draw(X, om, z, d, SEED, 0, k, precond_inv=m, tol=tol))
+    out["switch_period_100"].update(sw.state())
+    sw.close()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for k in range(steps):
+        pk.pg_update(X, beta, y, SEED, 0, k)
+    ev[1].record()
+    ev[1].synchronize()
+    out["pg_update_ms"] = ev[0].elapsed_time(ev[1]) / steps
     return out
 
 
@@ -510,6 +566,10 @@ def main():
               file=sys.stderr, flush=True)
         out["preconditioner_forms"] = precond_forms(pk, torch, P, X, args.steps, args.warmup,
                                                     args.tol)
+    if not args.no_gibbs:
+        print(f"[bench] Gibbs steps with the Polya-Gamma update ({args.warmup}+{args.steps} "
+              "per form)", file=sys.stderr, flush=True)
+        out["gibbs_step"] = gibbs_forms(pk, torch, P, X, args.steps, args.warmup, args.tol)
     if not args.no_cpu:
         print(f"[bench] CPU oracle sample ({args.cpu_draws} draws)", file=sys.stderr,
               flush=True)
