@@ -134,6 +134,17 @@ int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
 int ppcg_matrix_destroy(ppcg_matrix* X);
 
 /* Sizes of a handle (any output pointer may be NULL). */
+/*
+ * The same handle from the column-major (CSC) index arrays of X: col_ptr
+ * (p + 1, int64) and row_idx (nnz, int32, strictly increasing within each
+ * column), on the host or the device as `mem` says.  Validation and
+ * errors as ppcg_matrix_create; the row orientation is built from them.
+ * For designs generated or stored column by column.
+ */
+int ppcg_matrix_create_csc(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
+                           const int64_t* col_ptr, const int32_t* row_idx, const void* values,
+                           int32_t mem, hipStream_t stream);
+
 int ppcg_matrix_shape(const ppcg_matrix* X, int64_t* n, int64_t* p, int64_t* nnz);
 
 /*
@@ -326,7 +337,11 @@ int ppcg_pg_sample(const double* c, int64_t n, uint64_t seed, uint64_t chain,
  * both, the one that met the stopping rule in fewer CG iterations (first
  * phase plus refinement) is kept and its result returned; a tie, or a Jacobi
  * solve that did not converge, keeps the prior preconditioner (the paper's
- * first choice).  The Jacobi M^-1 is recomputed each draw it is used
+ * first choice).  The Jacobi solve runs first and the prior one is stopped
+ * at its count (it can win only within it), so a trial costs at most about
+ * twice the cheaper solve; the prior count reported is then at most the
+ * Jacobi count plus one phase's refinement.  The Jacobi M^-1 is recomputed
+ * each draw it is used
  * (omega changes between Gibbs steps).  Returns and blocks as
  * ppcg_draw_general.
  *

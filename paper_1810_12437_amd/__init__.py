@@ -47,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
     "ppcg_moments_update", "ppcg_unshrunk_setup", "ppcg_jacobi_precond",
     "ppcg_switch_create", "ppcg_switch_destroy", "ppcg_switch_state", "ppcg_draw_switch",
-    "ppcg_pg_update", "ppcg_pg_sample",
+    "ppcg_pg_update", "ppcg_pg_sample", "ppcg_matrix_create_csc",
 )
 
 
@@ -104,6 +104,8 @@ def _declare(L):
     L.ppcg_version.argtypes = []
     L.ppcg_version.restype = ctypes.c_char_p
     L.ppcg_matrix_create.argtypes = [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _vp, _i32, _vp]
+    L.ppcg_matrix_create_csc.argtypes = [ctypes.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _vp,
+                                         _i32, _vp]
     L.ppcg_matrix_destroy.argtypes = [_vp]
     L.ppcg_matrix_shape.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
     L.ppcg_phi_matvec.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, _i32, _vp]
@@ -148,7 +150,7 @@ def _declare(L):
                                      ctypes.POINTER(Info), _vp]
     for name in ("ppcg_batch_create", "ppcg_batch_create_shared", "ppcg_batch_destroy", "ppcg_draw_batched",
                  "ppcg_solve_batched", "ppcg_matrix_pass_bytes", "ppcg_matrix_profile", "ppcg_matrix_stats", "ppcg_matrix_create", "ppcg_matrix_destroy", "ppcg_matrix_shape",
-                 "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
+                 "ppcg_matrix_create_csc", "ppcg_phi_matvec", "ppcg_normals", "ppcg_rhs", "ppcg_solve", "ppcg_draw",
                  "ppcg_solve_backward", "ppcg_solve_general", "ppcg_draw_general",
                  "ppcg_phi_diag", "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
                  "ppcg_moments_update", "ppcg_unshrunk_setup", "ppcg_jacobi_precond",
@@ -250,6 +252,25 @@ class Matrix:
         _check(rc, "ppcg_matrix_create")
         self.nnz = nnz
         self._h = h
+
+    @classmethod
+    def from_csc(cls, n, p, col_ptr, row_idx):
+        """The handle from host CSC index arrays (col_ptr int64 [p+1], row_idx
+        int32 [nnz], rows strictly increasing within a column)."""
+        self = cls.__new__(cls)
+        self.n, self.p = int(n), int(p)
+        cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+        ri = np.ascontiguousarray(row_idx, dtype=np.int32)
+        nnz = int(ri.size)
+        h = ctypes.c_void_p()
+        rc = lib().ppcg_matrix_create_csc(ctypes.byref(h), self.n, self.p, nnz,
+                                          cp.ctypes.data_as(ctypes.c_void_p),
+                                          ri.ctypes.data_as(ctypes.c_void_p) if nnz else None,
+                                          None, MEM_HOST, _stream())
+        _check(rc, "ppcg_matrix_create_csc")
+        self.nnz = nnz
+        self._h = h
+        return self
 
     @property
     def handle(self):

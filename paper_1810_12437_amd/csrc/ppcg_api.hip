@@ -237,6 +237,86 @@ int dispatch_solve(ppcg_matrix* X, const void* omega, int dtype, bool have_beta0
 
 }  // namespace
 
+// The handle from both orientations' index arrays (validated, on the host).
+static int build_handle(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
+                        const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                        const std::vector<int64_t>& cp, const std::vector<int32_t>& ri) {
+  ppcg_matrix* X = new (std::nothrow) ppcg_matrix();
+  if (!X) return PPCG_ENOMEM;
+  auto fail = [&](int rc) {
+    X->mem.release();
+    if (X->h_sc) (void)hipHostFree(X->h_sc);
+    delete X;
+    return rc;
+  };
+  X->n = n;
+  X->p = p;
+  X->nnz = nnz;
+  if (hipGetDevice(&X->device) != hipSuccess) return fail(PPCG_EHIP);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, X->device) !=
+          hipSuccess || ncu < 1)
+    ncu = 256;
+  X->ncu = ncu;
+  if (setup_pass_kernels() != hipSuccess) return fail(PPCG_EHIP);
+
+  // Panel-blocked index-only tables of both orientations, for FP64 and
+  // FP32 gathered values (the panel width depends on the value size),
+  // built on four host threads, then uploaded.
+  {
+    PanelBuild Bt[4];
+    auto job = [&](int q) {
+      const int elem = (q / 2) == 0 ? 8 : 4;
+      if (q % 2 == 0)
+        build_panels(rp, ci, n, p, elem, ncu, Bt[q]);
+      else
+        build_panels(cp, ri, p, n, elem, ncu, Bt[q]);
+    };
+    bool threaded = true;
+    std::vector<std::thread> th;
+    try {
+      for (int q = 1; q < 4; ++q) th.emplace_back(job, q);
+    } catch (...) {
+      threaded = false;
+    }
+    job(0);
+    for (auto& t : th) t.join();
+    if (!threaded)
+      for (int q = 1 + (int)th.size(); q < 4; ++q) job(q);
+    for (int q = 0; q < 4; ++q) {
+      Orient& o = (q % 2 == 0) ? X->rows[q / 2] : X->cols[q / 2];
+      int rc = upload_orient(X->mem, Bt[q], (q / 2) == 0 ? 8 : 4, 1, o);
+      if (rc) return fail(rc);
+      Bt[q] = PanelBuild();
+    }
+  }
+
+  const size_t N = (size_t)n, P = (size_t)p;
+  bool ok = X->mem.alloc(&X->qx64, P) == hipSuccess && X->mem.alloc(&X->y64, N) == hipSuccess &&
+            X->mem.alloc(&X->omega64, N) == hipSuccess &&
+            X->mem.alloc(&X->d, P) == hipSuccess && X->mem.alloc(&X->m, P) == hipSuccess &&
+            X->mem.alloc(&X->b64, P) == hipSuccess && X->mem.alloc(&X->beta64, P) == hipSuccess &&
+            X->mem.alloc(&X->r64, P) == hipSuccess && X->mem.alloc(&X->s64, 2 * P) == hipSuccess &&
+            X->mem.alloc(&X->qx32, P) == hipSuccess && X->mem.alloc(&X->s32, 2 * P) == hipSuccess &&
+            X->mem.alloc(&X->z64, P) == hipSuccess &&
+            X->mem.alloc(&X->p1[0], (size_t)X->rows[0].pass.nwg) == hipSuccess &&
+            X->mem.alloc(&X->p2[0], (size_t)X->cols[0].pass.nwg) == hipSuccess &&
+            X->mem.alloc(&X->p1[1], (size_t)X->rows[1].pass.nwg) == hipSuccess &&
+            X->mem.alloc(&X->p2[1], (size_t)X->cols[1].pass.nwg) == hipSuccess &&
+            X->mem.alloc(&X->part, (size_t)kMaxRedBlocks * 4) == hipSuccess &&
+            X->mem.alloc(&X->sc, 1) == hipSuccess;
+  if (!ok) return fail(PPCG_ENOMEM);
+  if (hipMemset(X->sc, 0, sizeof(DevScal)) != hipSuccess) return fail(PPCG_EHIP);
+  if (hipHostMalloc(reinterpret_cast<void**>(&X->h_sc), sizeof(DevScal), 0) != hipSuccess) {
+    X->h_sc = nullptr;
+    return fail(PPCG_ENOMEM);
+  }
+  std::memset(X->h_sc, 0, sizeof(DevScal));
+  if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);
+  *out = X;
+  return PPCG_OK;
+}
+
 extern "C" {
 
 void ppcg_options_default(ppcg_options* opt, int32_t dtype) {
@@ -279,85 +359,33 @@ int ppcg_matrix_create(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
 
     std::vector<int64_t> rp, cp;
     std::vector<int32_t> ci, ri;
-    {
-      const int rc = read_binary_csr(n, p, nnz, row_ptr, col_idx, mem, stream, rp, ci, cp, ri);
-      if (rc) return rc;
-    }
+    const int rc = read_binary_csr(n, p, nnz, row_ptr, col_idx, mem, stream, rp, ci, cp, ri);
+    if (rc) return rc;
+    return build_handle(out, n, p, nnz, rp, ci, cp, ri);
+  } catch (const std::bad_alloc&) {
+    return PPCG_ENOMEM;
+  } catch (...) {
+    return PPCG_EINVAL;
+  }
+}
 
-    ppcg_matrix* X = new (std::nothrow) ppcg_matrix();
-    if (!X) return PPCG_ENOMEM;
-    auto fail = [&](int rc) {
-      X->mem.release();
-      if (X->h_sc) (void)hipHostFree(X->h_sc);
-      delete X;
-      return rc;
-    };
-    X->n = n;
-    X->p = p;
-    X->nnz = nnz;
-    if (hipGetDevice(&X->device) != hipSuccess) return fail(PPCG_EHIP);
-    int ncu = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, X->device) !=
-            hipSuccess || ncu < 1)
-      ncu = 256;
-    X->ncu = ncu;
-    if (setup_pass_kernels() != hipSuccess) return fail(PPCG_EHIP);
-
-    // Panel-blocked index-only tables of both orientations, for FP64 and
-    // FP32 gathered values (the panel width depends on the value size),
-    // built on four host threads, then uploaded.
-    {
-      PanelBuild Bt[4];
-      auto job = [&](int q) {
-        const int elem = (q / 2) == 0 ? 8 : 4;
-        if (q % 2 == 0)
-          build_panels(rp, ci, n, p, elem, ncu, Bt[q]);
-        else
-          build_panels(cp, ri, p, n, elem, ncu, Bt[q]);
-      };
-      bool threaded = true;
-      std::vector<std::thread> th;
-      try {
-        for (int q = 1; q < 4; ++q) th.emplace_back(job, q);
-      } catch (...) {
-        threaded = false;
-      }
-      job(0);
-      for (auto& t : th) t.join();
-      if (!threaded)
-        for (int q = 1 + (int)th.size(); q < 4; ++q) job(q);
-      for (int q = 0; q < 4; ++q) {
-        Orient& o = (q % 2 == 0) ? X->rows[q / 2] : X->cols[q / 2];
-        int rc = upload_orient(X->mem, Bt[q], (q / 2) == 0 ? 8 : 4, 1, o);
-        if (rc) return fail(rc);
-        Bt[q] = PanelBuild();
-      }
-    }
-
-    const size_t N = (size_t)n, P = (size_t)p;
-    bool ok = X->mem.alloc(&X->qx64, P) == hipSuccess && X->mem.alloc(&X->y64, N) == hipSuccess &&
-              X->mem.alloc(&X->omega64, N) == hipSuccess &&
-              X->mem.alloc(&X->d, P) == hipSuccess && X->mem.alloc(&X->m, P) == hipSuccess &&
-              X->mem.alloc(&X->b64, P) == hipSuccess && X->mem.alloc(&X->beta64, P) == hipSuccess &&
-              X->mem.alloc(&X->r64, P) == hipSuccess && X->mem.alloc(&X->s64, 2 * P) == hipSuccess &&
-              X->mem.alloc(&X->qx32, P) == hipSuccess && X->mem.alloc(&X->s32, 2 * P) == hipSuccess &&
-              X->mem.alloc(&X->z64, P) == hipSuccess &&
-              X->mem.alloc(&X->p1[0], (size_t)X->rows[0].pass.nwg) == hipSuccess &&
-              X->mem.alloc(&X->p2[0], (size_t)X->cols[0].pass.nwg) == hipSuccess &&
-              X->mem.alloc(&X->p1[1], (size_t)X->rows[1].pass.nwg) == hipSuccess &&
-              X->mem.alloc(&X->p2[1], (size_t)X->cols[1].pass.nwg) == hipSuccess &&
-              X->mem.alloc(&X->part, (size_t)kMaxRedBlocks * 4) == hipSuccess &&
-              X->mem.alloc(&X->sc, 1) == hipSuccess;
-    if (!ok) return fail(PPCG_ENOMEM);
-    if (hipMemset(X->sc, 0, sizeof(DevScal)) != hipSuccess) return fail(PPCG_EHIP);
-    if (hipHostMalloc(reinterpret_cast<void**>(&X->h_sc), sizeof(DevScal), 0) != hipSuccess) {
-      X->h_sc = nullptr;
-      return fail(PPCG_ENOMEM);
-    }
-    std::memset(X->h_sc, 0, sizeof(DevScal));
-    if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);
-    *out = X;
-    return PPCG_OK;
+int ppcg_matrix_create_csc(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
+                           const int64_t* col_ptr, const int32_t* row_idx, const void* values,
+                           int32_t mem, hipStream_t stream) {
+  try {
+    if (!out) return PPCG_EINVAL;
+    *out = nullptr;
+    if (n < 1 || p < 1 || nnz < 0 || values != nullptr || !col_ptr) return PPCG_EINVAL;
+    if (nnz > 0 && !row_idx) return PPCG_EINVAL;
+    if (n >= INT32_MAX || p >= INT32_MAX || nnz >= ((int64_t)INT32_MAX) * 1024) return PPCG_EINVAL;
+    if (mem != PPCG_MEM_HOST && mem != PPCG_MEM_DEVICE) return PPCG_EINVAL;
+    // The CSC of X is the CSR of X^T: the same reader validates it and builds
+    // the other orientation by its counting sort.
+    std::vector<int64_t> rp, cp;
+    std::vector<int32_t> ci, ri;
+    const int rc = read_binary_csr(p, n, nnz, col_ptr, row_idx, mem, stream, cp, ri, rp, ci);
+    if (rc) return rc;
+    return build_handle(out, n, p, nnz, rp, ci, cp, ri);
   } catch (const std::bad_alloc&) {
     return PPCG_ENOMEM;
   } catch (...) {

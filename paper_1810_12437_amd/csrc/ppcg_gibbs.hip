@@ -218,20 +218,30 @@ int ppcg_draw_switch(ppcg_switch* S, const ppcg_matrix* X, const void* omega, co
     ++S->draws;
     return rc;
   }
-  // Trial: the same draw (same b, same start) under both preconditioners.
-  const int rp = ppcg_draw_general(X, omega, z, prior_prec, precond_inv, beta0, seed, chain,
-                                   draw_index, opt, beta_out, &local[0], stream);
-  if (rp == PPCG_EINVAL || rp == PPCG_ENOMEM || rp == PPCG_EHIP) return rp;
+  // Trial: the same draw (same b, same start) under both preconditioners,
+  // Jacobi first; the prior solve is then stopped at the Jacobi count, since
+  // it can win only within it (an unbounded prior solve can run to p
+  // iterations where it does not converge).
   const int rj = ppcg_draw_general(X, omega, z, prior_prec, S->m_jacobi, beta0, seed, chain,
                                    draw_index, opt, S->beta_alt, &local[1], stream);
   if (rj == PPCG_EINVAL || rj == PPCG_ENOMEM || rj == PPCG_EHIP) return rj;
-  const int32_t ip = local[0].iters + local[0].refine_iters;
   const int32_t ij = local[1].iters + local[1].refine_iters;
+  ppcg_options capped;
+  if (opt)
+    capped = *opt;
+  else
+    ppcg_options_default(&capped, PPCG_F64);
+  if (rj == PPCG_OK) capped.max_iter = ij > 0 ? ij : 1;
+  const int rp = ppcg_draw_general(X, omega, z, prior_prec, precond_inv, beta0, seed, chain,
+                                   draw_index, &capped, beta_out, &local[0], stream);
+  if (rp == PPCG_EINVAL || rp == PPCG_ENOMEM || rp == PPCG_EHIP) return rp;
+  const int32_t ip = local[0].iters + local[0].refine_iters;
   S->trial_iters[0] = ip;
   S->trial_iters[1] = ij;
-  // Fewer iterations to the same stopping rule wins; a tie, or a Jacobi
-  // solve that did not converge, keeps the prior preconditioner.
-  const bool jacobi = rj == PPCG_OK && (rp != PPCG_OK || ij < ip);
+  // Fewer iterations to the same stopping rule wins; a tie keeps the prior
+  // preconditioner, and so does a Jacobi solve that did not converge when
+  // the prior one did.
+  const bool jacobi = rj == PPCG_OK ? !(rp == PPCG_OK && ip <= ij) : false;
   S->choice = jacobi ? PPCG_PRECOND_JACOBI : PPCG_PRECOND_PRIOR;
   if (jacobi) {
     const size_t bytes = (size_t)p * (dtype == PPCG_F64 ? sizeof(double) : sizeof(float));

@@ -117,6 +117,77 @@ def column_law_design(n: int, p: int, rng: np.random.Generator,
     return _csr_from_pairs(n, p, rows, cols)
 
 
+def column_law_csc(n: int, p: int, rng: np.random.Generator,
+                   dmin: float = 1e-4, dmax: float = 0.2):
+    """CSC index arrays (col_ptr, row_idx) under the same log-uniform
+    column-density law, for large designs.
+
+    A Binomial(n, d_j) count of distinct, uniformly chosen rows is the same
+    law as i.i.d. Bernoulli(d_j) entries down the column, so each column's
+    rows are drawn as running sums of Geometric(d_j) gaps: sorted and
+    distinct by construction, O(nnz) work.  Each column draws
+    ceil(n d_j + 8 sqrt(n d_j) + 16) gaps, which reach row n except with
+    probability below 1e-14 per column (an error if one does not).
+    """
+    dens = np.exp(rng.uniform(math.log(dmin), math.log(dmax), size=p))
+    mu = n * dens
+    m = np.ceil(mu + 8.0 * np.sqrt(mu) + 16.0).astype(np.int64)
+    starts = np.zeros(p + 1, dtype=np.int64)
+    np.cumsum(m, out=starts[1:])
+    pos = np.cumsum(rng.geometric(np.repeat(dens, m)))
+    ends = pos[starts[1:] - 1]
+    base = np.concatenate([[0], ends[:-1]])
+    rows = pos - np.repeat(base, m) - 1
+    del pos
+    if np.any(rows[starts[1:] - 1] < n):
+        raise RuntimeError("a column's gaps ended before row n; draw with another seed")
+    keep = rows < n
+    cnt = np.add.reduceat(keep, starts[:-1]).astype(np.int64)
+    rows = rows[keep].astype(np.int32)
+    col_ptr = np.zeros(p + 1, dtype=np.int64)
+    np.cumsum(cnt, out=col_ptr[1:])
+    return col_ptr, rows
+
+
+@dataclasses.dataclass
+class CscProblem:
+    """A large workload held column-major (X = CSC index arrays)."""
+    name: str
+    n: int
+    p: int
+    col_ptr: np.ndarray  # int64 [p+1]
+    row_idx: np.ndarray  # int32 [nnz], increasing within each column
+    omega: np.ndarray
+    z: np.ndarray
+    lam: np.ndarray
+    tau: float
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_ptr[-1])
+
+
+def large_problem(seed: int = 1812) -> CscProblem:
+    """n = 5e5, p = 5e4 under the column-density law, config-0 vector laws
+    (omega ~ Gamma(1, 0.25) + 0.01, z ~ N(0, 1), lambda ~ half-Cauchy),
+    tau = 0.05; the sequence's later steps redraw omega and lambda with
+    ``sequence_vectors``."""
+    rng = np.random.default_rng(seed)
+    n, p = 500_000, 50_000
+    cp, ri = column_law_csc(n, p, rng)
+    om, z, lam = _vectors(n, p, rng)
+    return CscProblem("large", n, p, cp, ri, om, z, lam, 0.05)
+
+
+def sequence_vectors(n: int, p: int, step: int, seed: int = 1816):
+    """omega, lambda of step `step` of the Gibbs-style sequence (config-0
+    laws, redrawn per step); z is held."""
+    rng = np.random.default_rng([seed, step])
+    omega = rng.gamma(1.0, 0.25, size=n) + 0.01
+    lam = np.maximum(np.abs(rng.standard_cauchy(size=p)), 1e-300)
+    return omega, lam
+
+
 def _vectors(n: int, p: int, rng: np.random.Generator, n_forced: int = 0):
     omega = rng.gamma(1.0, 0.25, size=n) + 0.01
     z = rng.standard_normal(n)
@@ -136,8 +207,9 @@ def make_problem(name: str, seed: int | None = None) -> Problem:
 
     c0: n=2000, p=500, Bernoulli(0.05) design, tau=0.05.
     c1: n=1e5, p=2e4, column-density law, 50 forced lambdas, tau=1e-3.
-    c2: n=5e5, p=5e4, column-density law, tau=0.05 (one step of the sequence;
-        draw the step's omega/lambda with ``seed``).
+    c2: n=5e5, p=5e4, column-density law, tau=0.05, through the CSR path
+        (slow at this size: ``large_problem`` builds the same law column-major
+        in O(nnz)).
     c4small: n=2000, p=400, the c1 laws at 1/50 scale (adjoint checks).
     """
     base = {"c0": 1810, "c1": 1811, "c2": 1812, "c4small": 1814}[name]

@@ -212,3 +212,41 @@ def test_pg_entry_points_reject_bad_arguments():
     assert L.ppcg_pg_update(None, one, one, 0, 0, 0, pk.F64, one, one, None) == pk.EINVAL
     assert L.ppcg_pg_sample(None, 5, 0, 0, 0, one, None) == pk.EINVAL
     assert L.ppcg_pg_sample(one, -1, 0, 0, 0, one, None) == pk.EINVAL
+
+
+def _create_csc(n, p, cp, ri):
+    L = pk.lib()
+    h = ctypes.c_void_p()
+    cp = np.ascontiguousarray(cp, dtype=np.int64)
+    ri = np.ascontiguousarray(ri, dtype=np.int32)
+    return L.ppcg_matrix_create_csc(ctypes.byref(h), n, p, int(ri.size),
+                                    cp.ctypes.data_as(ctypes.c_void_p),
+                                    ri.ctypes.data_as(ctypes.c_void_p) if ri.size else None,
+                                    None, pk.MEM_HOST, None)
+
+
+@needs_lib
+@pytest.mark.parametrize("case", ["ok", "offset0", "tail", "range", "unsorted", "dup", "sizes"])
+def test_create_csc_validates_columns(case):
+    """Column-major input is checked as strictly as row-major: offsets from 0
+    to nnz, rows in range and strictly increasing within a column; valid input
+    stops at the device check without a GPU."""
+    import torch
+    cp, ri, n, p = [0, 1, 3, 3], [1, 0, 1], 2, 3
+    if case == "offset0":
+        cp = [1, 1, 3, 3]
+    elif case == "tail":
+        cp = [0, 1, 2, 2]
+    elif case == "range":
+        ri = [1, 0, 2]
+    elif case == "unsorted":
+        ri = [1, 1, 0]
+    elif case == "dup":
+        ri = [1, 0, 0]
+    elif case == "sizes":
+        n = 0
+    rc = _create_csc(n, p, cp, ri)
+    if case != "ok":
+        assert rc == pk.EINVAL
+    else:
+        assert rc == (pk.OK if torch.cuda.is_available() else pk.ENODEV)
