@@ -23,7 +23,10 @@ with its own omega, z, lambda, tau and stream), every X pass serving all 8.
 ``--form batched`` instead measures the batched form: 32 independent chains
 with n log-uniform in [2e4, 2e5], p in [5e3, 4e4], tau in [1e-4, 1e-2] (the
 same column law), one batched draw of all chains per step, against the same
-chains drawn one at a time.
+chains drawn one at a time.  ``--form large`` runs the 200-step Gibbs-style
+sequence on the n = 5e5, p = 5e4 design (FP32 with refinement, omega and
+lambda redrawn per step, adaptive preconditioner) and times its passes where
+the index streams exceed the MALL.
 """
 from __future__ import annotations
 
@@ -63,7 +66,8 @@ TRAFFIC = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 200 for --form large, the sequence length)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -78,9 +82,10 @@ def parse():
                     help="skip the Gibbs steps with the device Polya-Gamma update")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 512 MiB device copy (counter calibration)")
-    ap.add_argument("--form", choices=("single", "batched", "shared"), default="single",
+    ap.add_argument("--form", choices=("single", "batched", "shared", "large"), default="single",
                     help="single: the n=1e5 p=2e4 draw (default); batched: 32 uneven chains; "
-                         "shared: 8 chains on the n=1e5 p=2e4 design")
+                         "shared: 8 chains on the n=1e5 p=2e4 design; large: the 200-step "
+                         "sequence on the n=5e5 p=5e4 design")
     return ap.parse_args()
 
 
@@ -469,8 +474,112 @@ def run_shared(args):
     print(json.dumps(out), flush=True)
 
 
+def run_large(args):
+    """The Gibbs-style sequence on the large design (n = 5e5, p = 5e4, 6.6e8
+    non-zeros; tau = 0.05): 200 steps (``--steps``), each with omega and
+    lambda redrawn from the config-0 laws (all steps' vectors resident in HBM
+    before the timed region), FP32 vectors with the FP64 refinement restart,
+    relative preconditioned residual ``--tol``, through the adaptive switch
+    (period 100).  The pass kernels are timed with HIP events over the whole
+    sequence; at this size the index streams (1.3 GB per orientation) cannot
+    sit in the 256 MB MALL, so the pass rate is an HBM figure.  A 100-
+    iteration prior-preconditioned FP64 solve is timed beside it (the prior
+    preconditioner does not converge within p iterations on this law)."""
+    import torch
+
+    import paper_1810_12437_amd as pk
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    steps = args.steps
+    t0 = time.perf_counter()
+    P = synth.large_problem()
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] large design nnz={P.nnz} in {t_gen:.1f} s; building the handle",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    X = pk.Matrix.from_csc(P.n, P.p, P.col_ptr, P.row_idx)
+    t_build = time.perf_counter() - t0
+    om_all = torch.empty((steps, P.n), dtype=torch.float32, device="cuda")
+    la_all = torch.empty((steps, P.p), dtype=torch.float32, device="cuda")
+    for k in range(steps):
+        om, la = synth.sequence_vectors(P.n, P.p, k)
+        om_all[k].copy_(torch.as_tensor(om))
+        la_all[k].copy_(torch.as_tensor(la))
+    z = torch.as_tensor(P.z, device="cuda").float()
+    sw = pk.Switch(P.p, period=100)
+    for w in range(args.warmup):
+        d, m = pk.unshrunk_setup(la_all[w % steps], P.tau)
+        sw.draw(X, om_all[w % steps], z, d, SEED, 1, w, precond_inv=m, tol=args.tol)
+    sw.close()
+    sw = pk.Switch(P.p, period=100)
+    torch.cuda.synchronize()
+    print(f"[bench] timing the {steps}-step sequence", file=sys.stderr, flush=True)
+    X.profile(True)
+    infos, choices = [], []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        d, m = pk.unshrunk_setup(la_all[k], P.tau)
+        _, info = sw.draw(X, om_all[k], z, d, SEED, 0, k, precond_inv=m, tol=args.tol)
+        infos.append(info)
+        if k % 100 == 0:
+            choices.append(sw.state())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = X.stats()
+    X.profile(False)
+    sw.close()
+    its = np.array([i["iters"] + i["refine_iters"] for i in infos], dtype=np.float64)
+    c32, s32 = X.pass_bytes(pk.F32)
+    t_pass = pass_time_ms(st)
+    seq = {
+        "steps": steps, "draws_per_s": steps / el, "ms_per_step": 1e3 * el / steps,
+        "cg_iters_mean": float(its.mean()), "cg_iters_min": float(its.min()),
+        "cg_iters_max": float(its.max()), "refined_draws": int(sum(i["refined"] for i in infos)),
+        "not_converged": int(sum(i["status"] != pk.OK for i in infos)),
+        "max_true_resid_over_tol": float(max(i["resid_true"] for i in infos)),
+        "trials": choices,
+        "pass_us": 1e3 * t_pass, "pass_launches": st["csr_launches"] + st["csc_launches"],
+        "pass_gbps": 0.5 * (c32 + s32) / (t_pass * 1e-3) / 1e9,
+    }
+    seq["pass_frac"] = seq["pass_gbps"] / HBM_PEAK_GBPS
+    # the prior preconditioner's passes in FP64, 100 iterations of draw 0
+    t = lambda a: torch.as_tensor(a, device="cuda")  # noqa: E731
+    X.profile(True)
+    _, info = pk.draw(X, t(P.omega), t(P.z), t(P.lam), P.tau, SEED, 0, 0, tol=args.tol,
+                      max_iter=100)
+    torch.cuda.synchronize()
+    st = X.stats()
+    X.profile(False)
+    c64, s64 = X.pass_bytes(pk.F64)
+    t64 = pass_time_ms(st)
+    prior = {"status": info["status"], "iters": info["iters"],
+             "resid_true_over_tol": info["resid_true"], "pass_us": 1e3 * t64,
+             "pass_gbps": 0.5 * (c64 + s64) / (t64 * 1e-3) / 1e9,
+             "row_pass_us": 1e3 * st["csr_ms"] / max(st["csr_launches"], 1),
+             "col_pass_us": 1e3 * st["csc_ms"] / max(st["csc_launches"], 1),
+             "bytes_per_launch": 0.5 * (c64 + s64)}
+    prior["pass_frac"] = prior["pass_gbps"] / HBM_PEAK_GBPS
+    out = {
+        "metric": "Gibbs-style sequence draws/sec, n=5e5 p=5e4, FP32 + FP64 refinement",
+        "value": seq["draws_per_s"], "unit": "draws/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": seq["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ("n=5e5 p=5e4 binary X, column densities log-uniform "
+                                "[1e-4, 0.2], tau=0.05, omega ~ Gamma(1, 0.25) + 0.01 and "
+                                "lambda ~ half-Cauchy redrawn per step; adaptive "
+                                f"prior/Jacobi preconditioner; relative residual {args.tol:g}"),
+                   "nnz": P.nnz, "n": P.n, "p": P.p, "tau": P.tau},
+        "generate_s": t_gen, "handle_build_s": t_build,
+        "sequence": seq, "prior_fp64_100_iterations": prior,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.steps is None:
+        args.steps = 200 if args.form == "large" else 20
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the sampler's "
               "data-parallel path is measured on a single MI355X (a multi-GPU run would "
@@ -484,6 +593,9 @@ def main():
         return
     if args.form == "shared":
         run_shared(args)
+        return
+    if args.form == "large":
+        run_large(args)
         return
     import torch
 
