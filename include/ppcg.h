@@ -90,7 +90,9 @@ typedef struct ppcg_options {
   int32_t check_every;/* host convergence check period in iterations (0: default) */
   double loop_factor; /* the recursion runs to loop_factor * tol before the FP64
                          check (0: default, 0.5 for F32 and 1 for F64)         */
-  int32_t reserved[4];
+  int32_t no_graph;   /* batched loops: 0 (default) replays each check batch as a
+                         captured HIP graph; 1 launches its kernels directly   */
+  int32_t reserved[3];
 } ppcg_options;
 
 typedef struct ppcg_info {

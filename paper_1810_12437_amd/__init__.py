@@ -67,7 +67,7 @@ class Options(ctypes.Structure):
         ("max_iter", ctypes.c_int32), ("refine", ctypes.c_int32),
         ("tol", ctypes.c_double), ("true_resid", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("loop_factor", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 4),
+        ("no_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -416,7 +416,7 @@ class Batch:
 
 
 def make_options(dtype=F64, tol=1e-6, criterion=REL_PRECOND, max_iter=0, refine=-1,
-                 true_resid=1, check_every=0, loop_factor=0.0):
+                 true_resid=1, check_every=0, loop_factor=0.0, no_graph=0):
     o = Options()
     lib().ppcg_options_default(ctypes.byref(o), int(dtype))
     o.tol = float(tol)
@@ -426,6 +426,7 @@ def make_options(dtype=F64, tol=1e-6, criterion=REL_PRECOND, max_iter=0, refine=
     o.true_resid = int(true_resid)
     o.check_every = int(check_every)
     o.loop_factor = float(loop_factor)
+    o.no_graph = int(no_graph)
     return o
 
 

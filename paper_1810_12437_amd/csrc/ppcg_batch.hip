@@ -98,7 +98,14 @@ struct ppcg_batch {
           *lp_blk_local = nullptr;
   int32_t lp_nwg[2] = {}, lp_nblk = 0;
   std::vector<char> lp_active;
+  int64_t lp_version = 0;  // bumped whenever the loop maps change
   std::vector<int32_t> chain_nwg[2], chain_nblk;
+  // the CG loop's check batch captured as a HIP graph, one per loop parity at
+  // the batch start, valid for (lp_version, check_every, element size)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec[2] = {};
+  int64_t g_version = -1;
+  int32_t g_every = 0, g_elem = 0;
   // shared form: every chain on one design, K interleaved vectors per pass
   bool shared = false;
   int32_t K = 1;
@@ -364,6 +371,7 @@ int set_loop_chains(ppcg_batch* B, const std::vector<char>& act) {
   }
   B->lp_nblk = (int32_t)bj.size();
   B->lp_active = act;
+  ++B->lp_version;
   return PPCG_OK;
 }
 
@@ -411,8 +419,77 @@ int interleave(ppcg_batch* B, double* const* src_of_chain, int64_t dim, T* dst,
   return PPCG_OK;
 }
 
+// One check batch of CG iterations (row pass, column pass, step each) for
+// the chains of the current loop maps; parity alternates per iteration.
+template <typename T>
+int enqueue_batch(ppcg_batch* B, int every, int parity, hipStream_t st) {
+  for (int i = 0; i < every; ++i, parity ^= 1) {
+    if (B->shared) {
+      const int rc = shared_loop_passes<T>(B, parity, st);
+      if (rc) return rc;
+    } else {
+      PPCG_TRY_HIP(launch_panel_pass_batched<T>(
+          reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobRow]), B->lp_wg_job[kJobRow],
+          B->lp_wg_local[kJobRow], B->lp_nwg[kJobRow], kPassDir, parity, st));
+      PPCG_TRY_HIP(launch_panel_pass_batched<T>(
+          reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobCol]), B->lp_wg_job[kJobCol],
+          B->lp_wg_local[kJobCol], B->lp_nwg[kJobCol], kPassDot, parity, st));
+    }
+    PPCG_TRY_HIP(launch_cg_step_batched<T>(reinterpret_cast<const VecJob<T>*>(B->vjobs),
+                                           B->lp_blk_job, B->lp_blk_local, B->lp_nblk, parity,
+                                           st));
+  }
+  return PPCG_OK;
+}
+
+void drop_graphs(ppcg_batch* B) {
+  for (hipGraphExec_t& g : B->gexec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
+// The check batch as a graph: captured on the batch's own stream (the
+// caller's may be the legacy default stream, which cannot be captured) the
+// first time a (maps, batch length, element size, start parity) combination
+// is used, then replayed on the caller's stream.  Kernel arguments are
+// fixed for that combination: the maps live in device buffers rewritten
+// only between batches, and the kernels' own arrival counters reset
+// themselves.  Nothing but kernel launches is captured.
+template <typename T>
+int launch_batch_graph(ppcg_batch* B, int every, int parity, hipStream_t st) {
+  if (B->g_version != B->lp_version || B->g_every != every || B->g_elem != (int32_t)sizeof(T)) {
+    drop_graphs(B);
+    B->g_version = B->lp_version;
+    B->g_every = every;
+    B->g_elem = (int32_t)sizeof(T);
+  }
+  if (!B->cap) PPCG_TRY_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+  hipGraphExec_t& exec = B->gexec[parity & 1];
+  if (!exec) {
+    PPCG_TRY_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_batch<T>(B, every, parity, B->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->cap, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    PPCG_TRY_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      exec = nullptr;
+      return PPCG_EHIP;
+    }
+  }
+  PPCG_TRY_HIP(hipGraphLaunch(exec, st));
+  return PPCG_OK;
+}
+
 // CG iterations of every chain until all report done; the launches cover
-// only the chains still iterating at the last check.
+// only the chains still iterating at the last check.  Each check batch is a
+// replay of its captured graph unless the options ask for direct launches.
 template <typename T>
 int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
   std::vector<char> act(B->nch);
@@ -429,21 +506,10 @@ int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
     if (!any) return PPCG_OK;
     int rc = set_loop_chains(B, act);
     if (rc) return rc;
-    for (int i = 0; i < o.check_every; ++i, parity ^= 1) {
-      if (B->shared) {
-        if ((rc = shared_loop_passes<T>(B, parity, st))) return rc;
-      } else {
-        PPCG_TRY_HIP(launch_panel_pass_batched<T>(
-            reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobRow]), B->lp_wg_job[kJobRow],
-            B->lp_wg_local[kJobRow], B->lp_nwg[kJobRow], kPassDir, parity, st));
-        PPCG_TRY_HIP(launch_panel_pass_batched<T>(
-            reinterpret_cast<const PanelJob<T>*>(B->jobs[kJobCol]), B->lp_wg_job[kJobCol],
-            B->lp_wg_local[kJobCol], B->lp_nwg[kJobCol], kPassDot, parity, st));
-      }
-      PPCG_TRY_HIP(launch_cg_step_batched<T>(reinterpret_cast<const VecJob<T>*>(B->vjobs),
-                                             B->lp_blk_job, B->lp_blk_local, B->lp_nblk, parity,
-                                             st));
-    }
+    rc = o.no_graph ? enqueue_batch<T>(B, o.check_every, parity, st)
+                    : launch_batch_graph<T>(B, o.check_every, parity, st);
+    if (rc) return rc;
+    parity ^= o.check_every & 1;
   }
 }
 
@@ -837,6 +903,8 @@ int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64
 int ppcg_batch_destroy(ppcg_batch* B) {
   if (!B) return PPCG_OK;
   (void)hipDeviceSynchronize();
+  drop_graphs(B);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
   B->mem.release();
   if (B->h_sc) (void)hipHostFree(B->h_sc);
   delete B;
