@@ -383,10 +383,11 @@ int ppcg_solve_backward(const ppcg_matrix* X, const void* omega,
  * Kernel timing of the two X passes of the CG iteration (v -> omega .* X v
  * and w -> X^T w, the products Section 2.2 says dominate each iteration's
  * cost).  With `enable` != 0 the handle has the dispatch of both passes of one
- * iteration in each convergence-check batch (the middle one, when it runs)
+ * iteration in every fourth convergence-check batch of a solve phase,
+ * starting with its first (the batch's middle iteration, when it runs)
  * stamp HIP events on the caller's stream and accumulates their elapsed
- * times: a sample of the loop's launches, since event-stamped dispatches slow
- * the loop.  Enabling resets the totals.  Host-only bookkeeping; PPCG_EINVAL
+ * times: a sample of the loop's launches, since event-stamped dispatches
+ * leave the device idle for microseconds each.  Enabling resets the totals.  Host-only bookkeeping; PPCG_EINVAL
  * for a NULL handle.
  */
 int ppcg_matrix_profile(ppcg_matrix* X, int32_t enable);

@@ -79,7 +79,12 @@ int sync_scal(ppcg_matrix* X, hipStream_t st) {
   return PPCG_OK;
 }
 
-// Runs CG iterations until the device reports done; returns via h_sc.
+// Runs CG iterations until the device reports done; returns via h_sc[0].
+// The host checks the device's flag after every check_every iterations
+// (a batch).  From the second check on the next batch is already queued
+// when the host waits for a batch's flag (read back into the other pinned
+// slot), so the device does not idle while the host checks; once done, the
+// queued batch exits launch by launch.
 template <typename T>
 int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t st) {
   const int ti = prec_index<T>();
@@ -104,23 +109,26 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
   dot.p2 = X->p2[ti];
   const int32_t n1 = X->rows[ti].pass.nwg, n2 = X->cols[ti].pass.nwg;
   const bool prof = X->profile != 0;
-  // Profiling times both passes of one iteration per check batch (the middle
-  // one): event-stamped dispatches cost the loop about a tenth of its rate,
-  // so only one in check_every carries them.
+  // Profiling times both passes of one iteration (the middle one) in every
+  // kProfileEvery-th batch: event-stamped dispatches leave the device idle
+  // for several microseconds each, so few iterations carry them.
+  constexpr int kProfileEvery = 4;
   const int sample = o.check_every / 2;
-  if (prof && X->ev.size() < 4) {
-    while (X->ev.size() < 4) {
-      hipEvent_t e;
-      PPCG_TRY_HIP(hipEventCreate(&e));
-      X->ev.push_back(e);
-    }
+  while (prof && X->ev.size() < 8) {
+    hipEvent_t e;
+    PPCG_TRY_HIP(hipEventCreate(&e));
+    X->ev.push_back(e);
   }
   int parity = 0;
   int32_t it = 0;  // iteration of this phase (the start kernel left iteration 0's scalars)
-  for (;;) {
-    const int32_t it_batch = it;
+  int64_t batch = 0;
+  int32_t start[2] = {0, 0};
+  bool stamped[2] = {false, false};
+  auto enqueue = [&](int slot) -> int {
+    start[slot] = it;
+    stamped[slot] = prof && batch % kProfileEvery == 0;
     for (int i = 0; i < o.check_every; ++i, parity ^= 1, ++it) {
-      hipEvent_t* e = (prof && i == sample) ? &X->ev[0] : nullptr;
+      hipEvent_t* e = (stamped[slot] && i == sample) ? &X->ev[4 * slot] : nullptr;
       // row pass: finishes the previous step, forms s (buffer 1 - parity)
       // from z and the old s
       dir.it = it;
@@ -131,20 +139,46 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
       PPCG_TRY_HIP(launch_cg_step<T>(w, s, X->p, parity, true, qsrc, X->d, X->m, X->beta64,
                                      X->r64, X->z64, X->p1[ti], n1, X->p2[ti], n2, X->p, st));
     }
-    PPCG_TRY_HIP(hipMemcpyAsync(X->h_sc, X->sc, sizeof(DevScal), hipMemcpyDeviceToHost, st));
-    PPCG_TRY_HIP(hipStreamSynchronize(st));
+    PPCG_TRY_HIP(hipMemcpyAsync(&X->h_sc[slot], X->sc, sizeof(DevScal), hipMemcpyDeviceToHost,
+                                st));
+    PPCG_TRY_HIP(hipEventRecord(X->chk[slot], st));
+    ++batch;
+    return PPCG_OK;
+  };
+  // Waits for a batch's flag; true once the device reported done.
+  auto check = [&](int slot, bool& is_done) -> int {
+    PPCG_TRY_HIP(hipEventSynchronize(X->chk[slot]));
+    const DevScal& h = X->h_sc[slot];
     // The sampled iteration counts only if its passes ran: once the rule
     // holds, the row pass of iteration iters and all later ones exit at once.
-    if (prof && (!X->h_sc->done || it_batch + sample < X->h_sc->iters)) {
+    if (stamped[slot] && (!h.done || start[slot] + sample < h.iters)) {
       float a = 0.f, b = 0.f;
-      PPCG_TRY_HIP(hipEventElapsedTime(&a, X->ev[0], X->ev[1]));
-      PPCG_TRY_HIP(hipEventElapsedTime(&b, X->ev[2], X->ev[3]));
+      PPCG_TRY_HIP(hipEventElapsedTime(&a, X->ev[4 * slot], X->ev[4 * slot + 1]));
+      PPCG_TRY_HIP(hipEventElapsedTime(&b, X->ev[4 * slot + 2], X->ev[4 * slot + 3]));
       X->pass_ms[0] += a;
       X->pass_ms[1] += b;
       X->pass_cnt[0] += 1;
       X->pass_cnt[1] += 1;
     }
-    if (X->h_sc->done) return PPCG_OK;
+    is_done = h.done != 0;
+    return PPCG_OK;
+  };
+  bool fin = false;
+  int rc = enqueue(0);
+  if (!rc) rc = check(0, fin);
+  if (rc || fin) return rc;
+  int cur = 1;
+  if ((rc = enqueue(cur))) return rc;
+  for (;;) {
+    if ((rc = enqueue(cur ^ 1))) return rc;
+    if ((rc = check(cur, fin))) return rc;
+    if (fin) {
+      // the queued batch exits launch by launch; the scalars no longer change
+      PPCG_TRY_HIP(hipStreamSynchronize(st));
+      X->h_sc[0] = X->h_sc[cur];
+      return PPCG_OK;
+    }
+    cur ^= 1;
   }
 }
 
@@ -245,6 +279,8 @@ static int build_handle(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
   if (!X) return PPCG_ENOMEM;
   auto fail = [&](int rc) {
     X->mem.release();
+    for (hipEvent_t e : X->chk)
+      if (e) (void)hipEventDestroy(e);
     if (X->h_sc) (void)hipHostFree(X->h_sc);
     delete X;
     return rc;
@@ -307,11 +343,13 @@ static int build_handle(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
             X->mem.alloc(&X->sc, 1) == hipSuccess;
   if (!ok) return fail(PPCG_ENOMEM);
   if (hipMemset(X->sc, 0, sizeof(DevScal)) != hipSuccess) return fail(PPCG_EHIP);
-  if (hipHostMalloc(reinterpret_cast<void**>(&X->h_sc), sizeof(DevScal), 0) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&X->h_sc), 2 * sizeof(DevScal), 0) != hipSuccess) {
     X->h_sc = nullptr;
     return fail(PPCG_ENOMEM);
   }
-  std::memset(X->h_sc, 0, sizeof(DevScal));
+  std::memset(X->h_sc, 0, 2 * sizeof(DevScal));
+  for (hipEvent_t& e : X->chk)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(PPCG_EHIP);
   if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);
   *out = X;
   return PPCG_OK;
@@ -426,6 +464,8 @@ int ppcg_matrix_destroy(ppcg_matrix* X) {
   if (!X) return PPCG_OK;
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : X->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : X->chk)
+    if (e) (void)hipEventDestroy(e);
   X->mem.release();
   if (X->h_sc) (void)hipHostFree(X->h_sc);
   delete X;

@@ -64,7 +64,8 @@ struct ppcg_matrix {
   double *p1[2] = {}, *p2[2] = {};        // workgroup partials of the passes, per table
   double* part = nullptr;
   ppcg::DevScal* sc = nullptr;
-  ppcg::DevScal* h_sc = nullptr;  // pinned host mirror
+  ppcg::DevScal* h_sc = nullptr;  // pinned host mirror: [0] the result, [0..1] check slots
+  hipEvent_t chk[2] = {};         // one per check slot: that batch's flags are on the host
   // pass timing (ppcg_matrix_profile)
   int profile = 0;
   std::vector<hipEvent_t> ev;  // 4 per iteration of a check batch
