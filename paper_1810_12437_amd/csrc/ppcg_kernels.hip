@@ -211,6 +211,23 @@ __device__ __forceinline__ ChunkDesc read_desc(const ChunkDesc* p, int c) {
   return D;
 }
 
+// A pointer that may have been read from memory (a batched job) is generic
+// to the compiler; these views address global memory explicitly, so that
+// its loads are global (vector memory only) or, for read-only workgroup-
+// uniform tables, scalar.
+template <typename V>
+__device__ __forceinline__ const __attribute__((address_space(1))) V* gview(const V* p) {
+  return (const __attribute__((address_space(1))) V*)p;
+}
+template <typename V>
+__device__ __forceinline__ __attribute__((address_space(1))) V* gview_mut(V* p) {
+  return (__attribute__((address_space(1))) V*)p;
+}
+__device__ __forceinline__ int32_t read_table(const int32_t* p, int64_t i) {
+  typedef const __attribute__((address_space(4))) int32_t ConstI32;
+  return ((ConstI32*)p)[i];
+}
+
 // Load cursor of a wavefront's index stream: window k of chunk c.  Every
 // step issues the same three loads (the window's two halves and the output
 // slot of its chunk for this lane), with in-bounds stand-ins for lanes that
@@ -283,10 +300,10 @@ __device__ __forceinline__ void stream_issue(const PanelPass& t, int c_end, int 
     first = L.k == 0;
     if (++L.k == L.windows && ++L.c < c_end) stream_open(t, read_desc(t.chunks, L.c), L.c, lane, L);
   }
-  a = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(t.idx + ea));
-  b = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(t.idx + eb));
+  a = __builtin_nontemporal_load(gview(reinterpret_cast<const u16x8*>(t.idx + ea)));
+  b = __builtin_nontemporal_load(gview(reinterpret_cast<const u16x8*>(t.idx + eb)));
   // the chunk's output slot rides with its first window only
-  if (first) slot = t.seg_out[si];
+  if (first) slot = gview(t.seg_out)[si];
   have = (have & ~(1u << bit)) | ((h ? 1u : 0u) << bit);
 }
 
@@ -378,7 +395,7 @@ __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T (&acc)
     if (slot >= 0) {
 #pragma unroll
       for (int r = 0; r < K; ++r) {
-        part_out[(int64_t)slot * K + r] = out_scale ? acc[r] * scl[r] : acc[r];
+        gview_mut(part_out)[(int64_t)slot * K + r] = out_scale ? acc[r] * scl[r] : acc[r];
         if constexpr (dotting) p2acc[r] += (double)sd[r] * (double)acc[r];
       }
     }
@@ -394,9 +411,9 @@ __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T (&acc)
 #pragma unroll
     for (int r = 0; r < K; ++r) {
       if (kind == kChunkLong)
-        part_out[(int64_t)slot * K + r] = out_scale ? acc[r] * scl[r] : acc[r];
+        gview_mut(part_out)[(int64_t)slot * K + r] = out_scale ? acc[r] * scl[r] : acc[r];
       else
-        piece_out[(int64_t)piece * K + r] = acc[r];
+        gview_mut(piece_out)[(int64_t)piece * K + r] = acc[r];
       if constexpr (dotting) p2acc[r] += (double)sd[r] * (double)acc[r];
     }
   }
@@ -443,11 +460,11 @@ __device__ __forceinline__ bool assemble_dir_fast(const double* zp, const double
   for (int u = 0; u < kAsmPairs; ++u) {
     pi[u] = asm_pair(u, tid, rb, nb, npairs);
     const int at = pi[u] >= 0 ? 2 * pi[u] : 0;
-    zv[u] = *reinterpret_cast<const f64x2*>(zp + at);
-    sv[u] = *reinterpret_cast<const f64x2*>(sp + at);
+    zv[u] = *gview(reinterpret_cast<const f64x2*>(zp + at));
+    sv[u] = *gview(reinterpret_cast<const f64x2*>(sp + at));
   }
   const int last = wlen - 1;  // the odd entry, when wlen is odd
-  const double zt = zp[last], st = sp[last];
+  const double zt = gview(zp)[last], st = gview(sp)[last];
   auto form = [&](double z, double so) { return bc == 0.0 ? z : z + bc * so; };
 #pragma unroll
   for (int u = 0; u < kAsmPairs / 2; ++u) {
@@ -482,10 +499,10 @@ __device__ __forceinline__ bool assemble_copy_fast(const double* src, int wlen, 
 #pragma unroll
   for (int u = 0; u < kAsmPairs; ++u) {
     pi[u] = asm_pair(u, tid, rb, nb, npairs);
-    v[u] = *reinterpret_cast<const f64x2*>(src + (pi[u] >= 0 ? 2 * pi[u] : 0));
+    v[u] = *gview(reinterpret_cast<const f64x2*>(src + (pi[u] >= 0 ? 2 * pi[u] : 0)));
   }
   const int last = wlen - 1;
-  const double vt = src[last];
+  const double vt = gview(src)[last];
   prime();
 #pragma unroll
   for (int u = 0; u < kAsmPairs; ++u)
@@ -514,9 +531,9 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   // What the start needs, requested together: this wavefront's chunk range
   // and first descriptor, the panel, the stop flag(s) and the direction's
   // ratio.
-  int c = t.wave_c[kPWaves * w + wave];
-  const int c_end = t.wave_c[kPWaves * w + wave + 1];
-  const int panel = t.wg_panel[w];
+  int c = read_table(t.wave_c, kPWaves * w + wave);
+  const int c_end = read_table(t.wave_c, kPWaves * w + wave + 1);
+  const int panel = read_table(t.wg_panel, w);
   ChunkDesc D0{};
   if (c < c_end) D0 = read_desc(t.chunks, c);
   // direction ratio per vector (a vector whose chain has stopped keeps s = z:
@@ -526,11 +543,11 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   if constexpr (MODE == kPassDir) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-      const DevScal& S = dir.sc[(int64_t)r * dir.scstride];
+      const auto& S = gview(dir.sc)[(int64_t)r * dir.scstride];
       bc[r] = S.done ? 0.0 : S.betacg;
     }
     if (K == 1 && dir.sp != nullptr && dir.it > 0) {
-      const double* P = dir.sp + (int64_t)(1 - parity) * 2 * kMaxRedBlocks;
+      const auto* P = gview(dir.sp + (int64_t)(1 - parity) * 2 * kMaxRedBlocks);
       for (int q = lane; q < dir.nsb; q += 64) {
         fin_a += P[2 * q];
         fin_b += P[2 * q + 1];
@@ -539,7 +556,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   }
   if (done != nullptr) {
     bool all = true;
-    for (int i = 0; i < ndone; ++i) all = all && done[(int64_t)i * dstride] != 0;
+    for (int i = 0; i < ndone; ++i) all = all && gview(done)[(int64_t)i * dstride] != 0;
     if (all) return;
   }
   if constexpr (MODE == kPassDir && K == 1) {
@@ -549,7 +566,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       } else {
         // totals in the order of the step kernel's own reduction
         const double rho_new = wave_total(fin_a), rr = wave_total(fin_b);
-        DevScal* sc = dir.sc;
+        auto* sc = gview_mut(dir.sc);
         const double rho_old = sc->rho_par[1 - parity];
         bc[0] = rho_new / rho_old;
         const double meas = sc->criterion == kCritRelPlain ? rr : rho_new;
@@ -747,7 +764,8 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
           slot = rs[q];
 #pragma unroll
           for (int r = 0; r < K; ++r) {
-            scl[r] = (out_scale != nullptr && slot >= 0) ? out_scale[(int64_t)slot * K + r] : T(1);
+            scl[r] = (out_scale != nullptr && slot >= 0) ? gview(out_scale)[(int64_t)slot * K + r]
+                                                         : T(1);
             sd[r] = T(0);
           }
           if constexpr (dotting) {
@@ -755,7 +773,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
                 ck_kind(cinfo) == kChunkPiece ? cseg : (slot >= 0 ? slot - pofs : -1);
             if (jd >= 0) {
 #pragma unroll
-              for (int r = 0; r < K; ++r) sd[r] = sdot[jd * K + r];
+              for (int r = 0; r < K; ++r) sd[r] = gview(sdot)[jd * K + r];
             }
           }
         }
@@ -781,12 +799,12 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   if constexpr (MODE == kPassDir && kFastPanel<T, K>) {
     if (assembled) {
       // the workgroup's own entries of the new direction, from the panel
-      const int64_t o0 = t.wg_s0[w], o1 = t.wg_s1[w];
+      const int64_t o0 = read_table(t.wg_s0, w), o1 = read_table(t.wg_s1, w);
       T* s_new = dir.s + (int64_t)(1 - parity) * dir.sstride;
       for (int64_t j = o0 + threadIdx.x; j < o1; j += kPThreads) {
         const double v = xl[j - g0];
-        s_new[j] = v;
-        p1acc[0] += dir.d[j] * v * v;
+        gview_mut(s_new)[j] = v;
+        p1acc[0] += gview(dir.d)[j] * v * v;
       }
     }
   }
@@ -812,8 +830,8 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
         a += red[(q * K + r) * 2 + 0];
         b += red[(q * K + r) * 2 + 1];
       }
-      if constexpr (MODE == kPassDir) dir.p1[(int64_t)w * K + r] = a;
-      if constexpr (dotting) dot.p2[(int64_t)w * K + r] = b;
+      if constexpr (MODE == kPassDir) gview_mut(dir.p1)[(int64_t)w * K + r] = a;
+      if constexpr (dotting) gview_mut(dot.p2)[(int64_t)w * K + r] = b;
     }
   }
 }
