@@ -81,10 +81,9 @@ int sync_scal(ppcg_matrix* X, hipStream_t st) {
 
 // Runs CG iterations until the device reports done; returns via h_sc[0].
 // The host checks the device's flag after every check_every iterations
-// (a batch).  From the second check on the next batch is already queued
-// when the host waits for a batch's flag (read back into the other pinned
-// slot), so the device does not idle while the host checks; once done, the
-// queued batch exits launch by launch.
+// (a batch).  From the second check on the next batch is normally already
+// queued when the host waits for a batch's flag (read back into the other
+// pinned slot), so the device does not idle while the host checks.
 template <typename T>
 int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t st) {
   const int ti = prec_index<T>();
@@ -163,21 +162,35 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
     is_done = h.done != 0;
     return PPCG_OK;
   };
+  // The batch after the one being checked is queued ahead unless the last
+  // two checks' decay of the rule measure says the checked batch's
+  // successor will probably finish the solve: then a batch queued ahead
+  // would only run launches that exit at once.
+  auto ratio = [&](int slot) {
+    const DevScal& h = X->h_sc[slot];
+    return h.loop2 > 0.0 ? h.meas / h.loop2 : 0.0;
+  };
   bool fin = false;
   int rc = enqueue(0);
   if (!rc) rc = check(0, fin);
   if (rc || fin) return rc;
+  double m_prev = ratio(0);
   int cur = 1;
   if ((rc = enqueue(cur))) return rc;
+  bool ahead = true;
   for (;;) {
-    if ((rc = enqueue(cur ^ 1))) return rc;
+    if (ahead && (rc = enqueue(cur ^ 1))) return rc;
     if ((rc = check(cur, fin))) return rc;
     if (fin) {
-      // the queued batch exits launch by launch; the scalars no longer change
-      PPCG_TRY_HIP(hipStreamSynchronize(st));
+      // a batch queued ahead exits launch by launch; the scalars no longer change
+      if (ahead) PPCG_TRY_HIP(hipStreamSynchronize(st));
       X->h_sc[0] = X->h_sc[cur];
       return PPCG_OK;
     }
+    if (!ahead && (rc = enqueue(cur ^ 1))) return rc;
+    const double m = ratio(cur);
+    ahead = !(m_prev > 0.0 && m < m_prev && m * (m / m_prev) <= 1.0);
+    m_prev = m;
     cur ^= 1;
   }
 }
