@@ -311,10 +311,10 @@ def gibbs_forms(pk, torch, P, X, steps, warmup, tol):
     return out
 
 
-def copy_calibration():
+def copy_rate():
+    """Best of 5 timed 512 MiB device-to-device copies: (ms, GB/s read + written)."""
     import torch
 
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -327,10 +327,17 @@ def copy_calibration():
         b.synchronize()
         ms.append(a.elapsed_time(b))
     best = min(ms)
+    del src, dst
+    return best, 2 * COPY_BYTES / (best * 1e-3) / 1e9
+
+
+def copy_calibration():
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    best, gbps = copy_rate()
     print(json.dumps({"copy_calibration": {"bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES,
-                                           "best_ms": best,
-                                           "gbps": 2 * COPY_BYTES / (best * 1e-3) / 1e9}}),
-          flush=True)
+                                           "best_ms": best, "gbps": gbps}}), flush=True)
 
 
 def run_batched(args):
@@ -543,6 +550,9 @@ def run_large(args):
         "pass_gbps": 0.5 * (c32 + s32) / (t_pass * 1e-3) / 1e9,
     }
     seq["pass_frac"] = seq["pass_gbps"] / HBM_PEAK_GBPS
+    _, copy_gbps = copy_rate()
+    seq["copy_gbps"] = copy_gbps
+    seq["pass_frac_of_copy"] = seq["pass_gbps"] / copy_gbps
     # the prior preconditioner's passes in FP64, 100 iterations of draw 0
     t = lambda a: torch.as_tensor(a, device="cuda")  # noqa: E731
     X.profile(True)
@@ -560,6 +570,7 @@ def run_large(args):
              "col_pass_us": 1e3 * st["csc_ms"] / max(st["csc_launches"], 1),
              "bytes_per_launch": 0.5 * (c64 + s64)}
     prior["pass_frac"] = prior["pass_gbps"] / HBM_PEAK_GBPS
+    prior["pass_frac_of_copy"] = prior["pass_gbps"] / copy_gbps
     out = {
         "metric": "Gibbs-style sequence draws/sec, n=5e5 p=5e4, FP32 + FP64 refinement",
         "value": seq["draws_per_s"], "unit": "draws/s", "n_gpus": 1, "steps": steps,
@@ -617,6 +628,7 @@ def main():
     t_pass = pass_time_ms(st)
     bytes_per_launch = 0.5 * (csr_b + csc_b)
     achieved = bytes_per_launch / (t_pass * 1e-3) / 1e9
+    _, copy_gbps = copy_rate()  # achievable bandwidth on this device, after the timed draws
     iter_bytes = csr_b + csc_b + vec_bytes(P.p, 8)
     cg_gbps = iter_bytes * iters.sum() / el / 1e9
     traffic = None
@@ -657,6 +669,7 @@ def main():
             "launches": st["csr_launches"] + st["csc_launches"],
             "bytes_per_launch": bytes_per_launch,
             "int32_csr_csc_equiv_gbps": 0.5 * (csr_i32 + csc_i32) / (t_pass * 1e-3) / 1e9,
+            "copy_gbps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
         },
     }
     if not args.no_f32:
