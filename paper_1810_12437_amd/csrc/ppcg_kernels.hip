@@ -836,6 +836,18 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   }
 }
 
+// The dispatcher deals workgroups to the eight XCDs in turn (block b runs on
+// XCD b % 8), while logical workgroups are numbered panel by panel: giving
+// each XCD a contiguous run of logical workgroups keeps each XCD's L2 on one
+// or two panels of the gathered vector instead of all of them.  A bijection
+// when the grid is a multiple of 8 (else the identity).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_logical_wg() {
+  const int b = (int)blockIdx.x, nwg = (int)gridDim.x;
+  if (nwg % kXcds) return b;
+  return (b % kXcds) * (nwg / kXcds) + b / kXcds;
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin,
                                                      T* __restrict__ part_out,
@@ -844,7 +856,7 @@ __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin
                                                      const int32_t* __restrict__ done,
                                                      DirIn<T> dir, DotOut<T> dot, int parity) {
   panel_body<T, 1, MODE>(t, xin, part_out, piece_out, out_scale, done, 1, 0, dir, dot, parity,
-                         (int)blockIdx.x);
+                         xcd_logical_wg());
 }
 
 template <typename T, int MODE>
@@ -868,7 +880,7 @@ __global__ __launch_bounds__(kPThreads) void k_panel_k(PanelPass t, Combine<T> x
                                                        int dstride, DirIn<T> dir, DotOut<T> dot,
                                                        int parity) {
   panel_body<T, K, MODE>(t, xin, part_out, piece_out, out_scale, done, K, dstride, dir, dot,
-                         parity, (int)blockIdx.x);
+                         parity, xcd_logical_wg());
 }
 
 static size_t pass_lds_bytes() { return (size_t)kPanelBytes; }
