@@ -1416,6 +1416,18 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
                                              VGrid g, int parity = 0) {
   DevScal* sc = w.sc;
   if (sc->done) return;
+  // This thread's first element, requested before the grid total below
+  // (it does not depend on alpha): its loads overlap the partials' loads.
+  const int64_t j0 = (int64_t)g.bid * kWG + threadIdx.x;
+  double s0 = 0.0, q0 = 0.0, d0 = 0.0, r0 = 0.0, m0 = 0.0;
+  if (j0 < p) {
+    s0 = (double)s[j0 * es];
+    q0 = (double)combine_at(qsrc, j0);
+    d0 = d[j0];
+    r0 = r[j0];
+    m0 = m[j0];
+  }
+  const double rho = sc->rho;
   // <s, Phi s> = <s, d s> + <s, X^T u>: the same fixed-order total in every
   // block, all threads loading at once (the partials come from other XCDs)
   __shared__ double sq_sh;
@@ -1437,15 +1449,16 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
     }
     return;
   }
-  const double alpha = sc->rho / sq;
+  const double alpha = rho / sq;
   double v[2] = {0.0, 0.0};  // <r, M^-1 r>, <r, r>
-  for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
-    const double sj = (double)s[j * es];
-    const double qj = (double)combine_at(qsrc, j) + d[j] * sj;
+  for (int64_t j = j0; j < p; j += (int64_t)g.nblk * kWG) {
+    const bool first = j == j0;
+    const double sj = first ? s0 : (double)s[j * es];
+    const double qj = (first ? q0 : (double)combine_at(qsrc, j)) + (first ? d0 : d[j]) * sj;
     beta[j] += alpha * sj;
-    const double rj = r[j] - alpha * qj;
+    const double rj = (first ? r0 : r[j]) - alpha * qj;
     r[j] = rj;
-    const double zj = m[j] * rj;
+    const double zj = (first ? m0 : m[j]) * rj;
     z[j * zes] = zj;
     v[0] += rj * zj;
     v[1] += rj * rj;
