@@ -17,9 +17,15 @@ sampler of Devroye (2009) as described by Polson, Scott & Windle, Section 4:
 * Proposal: exp(-z^2 x / 2) a_0(x), a mixture of an exponential with rate
   K = pi^2 / 8 + z^2 / 2 on (t, inf) (mass p = pi / (2 K) exp(-K t)) and an
   inverse Gaussian IG(1/z, 1) truncated to (0, t] (mass q = 2 exp(-z)
-  P_IG(X <= t)).
+  P_IG(X <= t)); the exponential part is taken with probability p / (p + q),
+  evaluated from log p and log q (both masses underflow at large z).
 * Acceptance: with V uniform, Y = V a_0(X) is compared against the partial
   sums of the series (lower bounds after odd terms, upper after even ones).
+  Both sides are divided by a_0(X) > 0, which leaves every decision the
+  same and keeps the test defined where a_0 itself underflows (tilts |c|
+  beyond ~2000): V against 1 - a_1/a_0 + a_2/a_0 - ..., with
+      x <= t:  a_n/a_0 = (2n + 1) exp(-2 n (n + 1) / x)
+      x >  t:  a_n/a_0 = (2n + 1) exp(-n (n + 1) pi^2 x / 2).
 
 Random numbers: element i's k-th uniform is word k mod 4 of the Philox4x64-10
 block with counter (i, 2 | (k div 4) << 8, chain, draw) and key (seed, 0),
@@ -77,6 +83,14 @@ def a_n(n, x):
     return math.pi * h * math.exp(-h * h * math.pi ** 2 * x / 2.0)
 
 
+def a_ratio(n, x):
+    """a_n(x) / a_0(x), the series term relative to the leading one."""
+    k = float(n * (n + 1))
+    if x <= T_SPLIT:
+        return (2 * n + 1) * math.exp(-2.0 * k / x)
+    return (2 * n + 1) * math.exp(-k * math.pi ** 2 * x / 2.0)
+
+
 def mixture_masses(z):
     """(p, q): masses of the exponential and truncated inverse Gaussian parts
     of the proposal.  q = 2 exp(-z) [Phi((z t - 1)/sqrt t) + exp(2 z)
@@ -89,6 +103,22 @@ def mixture_masses(z):
     q = (math.exp(-z) * float(erfc((1.0 - z * t) / r))
          + float(erfcx((1.0 + z * t) / r)) * math.exp(-z * z * t / 2.0 - 1.0 / (2.0 * t)))
     return p, q
+
+
+def right_probability(z):
+    """p / (p + q), the chance of the exponential part, from the masses'
+    logarithms: 1 / (1 + exp(log q - log p)), log q the log-sum of its two
+    terms, so that it stays defined where p and q both underflow."""
+    t = T_SPLIT
+    K = math.pi ** 2 / 8.0 + z * z / 2.0
+    lp = math.log(math.pi / (2.0 * K)) - K * t
+    r = math.sqrt(2.0 * t)
+    l1 = -z + math.log(float(erfc((1.0 - z * t) / r)))
+    l2 = math.log(float(erfcx((1.0 + z * t) / r))) - z * z * t / 2.0 - 1.0 / (2.0 * t)
+    hi, lo = (l1, l2) if l1 >= l2 else (l2, l1)
+    lq = hi + math.log1p(math.exp(lo - hi))
+    d = lq - lp
+    return 0.0 if d > 700.0 else 1.0 / (1.0 + math.exp(d))
 
 
 def truncated_ig(z, u):
@@ -125,24 +155,24 @@ def pg1_draw(c, u):
     z = 0.5 * abs(float(c))
     t = T_SPLIT
     K = math.pi ** 2 / 8.0 + z * z / 2.0
-    p, q = mixture_masses(z)
+    right = right_probability(z)
     x = t
     for _ in range(CAP):
-        if u() < p / (p + q):
+        if u() < right:
             x = t - math.log(u()) / K
         else:
             x = truncated_ig(z, u)
-        s = a_n(0, x)
-        y = u() * s
+        s = 1.0  # partial sums over a_0(x)
+        y = u()
         accepted = False
         for n in range(1, CAP):
             if n & 1:
-                s -= a_n(n, x)
+                s -= a_ratio(n, x)
                 if y < s:
                     accepted = True
                     break
             else:
-                s += a_n(n, x)
+                s += a_ratio(n, x)
                 if y > s:
                     break
         if accepted:

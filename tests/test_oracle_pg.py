@@ -27,7 +27,9 @@ def pg_var(c):
     c sech^2(c/2)) / (4 c^3); 1/24 at c = 0 (series below |c| = 1e-2)."""
     if abs(c) < 1e-2:
         return 1 / 24 - c * c / 240
-    return (2 * math.tanh(c / 2) - c / math.cosh(c / 2) ** 2) / (4 * c ** 3)
+    e = math.exp(-abs(c))
+    sech2 = 4.0 * e / (1.0 + e) ** 2  # sech^2(c/2) without overflow
+    return (2 * math.tanh(c / 2) - c * sech2) / (4 * c ** 3)
 
 
 def pg_laplace(c, s):
@@ -112,3 +114,27 @@ def test_pg_update_pseudo_response_by_hand():
         assert z[i] == (y[i] - 0.5) / omega[i]
     o2, z2, _ = G.pg_update(X, beta, y, 9, 1, 4, idx=[2, 0])
     assert np.array_equal(o2, omega[[2, 0]]) and np.array_equal(z2, z[[2, 0]])
+
+
+def test_series_ratio_matches_the_terms_and_survives_underflow():
+    """a_n / a_0 from its closed form equals the quotient of the terms where
+    both are representable, and stays finite where a_0 underflows; extreme
+    tilts then draw quickly with the closed-form mean."""
+    for x in (0.05, 0.3, 0.64, 0.9, 3.0):
+        for n in range(1, 6):
+            a0 = G.a_n(0, x)
+            assert math.isclose(G.a_ratio(n, x), G.a_n(n, x) / a0, rel_tol=1e-12, abs_tol=1e-300)
+    assert G.a_n(0, 2e-4) == 0.0 and G.a_ratio(1, 2e-4) == 0.0
+    c = 1e4
+    w = draws(c, n=2000, seed=5)
+    assert abs(w.mean() - pg_mean(c)) <= 5 * math.sqrt(pg_var(c) / 2000)
+
+
+def test_right_probability_equals_the_mass_ratio():
+    """The log-space weight of the exponential part equals p / (p + q) from
+    the masses themselves wherever those are representable, and tends to 0
+    (the inverse-Gaussian part) at large tilts."""
+    for z in (0.0, 0.3, 1.0, 1.5625, 3.0, 10.0, 40.0):
+        p, q = G.mixture_masses(z)
+        assert math.isclose(G.right_probability(z), p / (p + q), rel_tol=1e-12)
+    assert G.right_probability(5000.0) == 0.0
