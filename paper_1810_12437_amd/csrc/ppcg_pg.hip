@@ -6,8 +6,8 @@
 // sampler (as described by Polson, Scott & Windle 2013, Section 4): a proposal
 // mixing an exponential on (t, inf) and an inverse Gaussian truncated to
 // (0, t], t = 0.64, accepted against the partial sums of the J* density's
-// series.  One thread per element; element i draws its uniforms from its own
-// Philox4x64-10 stream (counter (i, 2 | (k / 4) << 8, chain, draw), key
+// series (both divided by its leading term).  One thread per element;
+// element i draws its uniforms from its own Philox4x64-10 stream (counter (i, 2 | (k / 4) << 8, chain, draw), key
 // (seed, 0), word k % 4 as ((w >> 11) + 1/2) 2^-53), so every element is a
 // pure function of (seed, chain, draw, i, psi_i).  Every loop is capped at 64
 // rounds (reached with probability far below 1e-100): each wave exits.
@@ -45,14 +45,28 @@ struct PgUniforms {
   }
 };
 
-// Term n of the alternating series of the J*(1, 0) density.
-__device__ double series_term(int n, double x) {
-  const double h = n + 0.5;
-  if (x <= kT) {
-    const double r = 2.0 / (kPi * x);
-    return kPi * h * (r * sqrt(r)) * exp(-2.0 * h * h / x);
-  }
-  return kPi * h * exp(-h * h * (kPi * kPi) * x / 2.0);
+// Term n of the alternating series of the J*(1, 0) density divided by its
+// leading term: (2n + 1) exp(-2 n (n + 1) / x) up to t, (2n + 1)
+// exp(-n (n + 1) pi^2 x / 2) beyond.  The acceptance test divided by a_0 > 0
+// takes the same decisions and stays defined where a_0 underflows.
+__device__ double series_ratio(int n, double x) {
+  const double k = (double)(n * (n + 1));
+  if (x <= kT) return (2 * n + 1) * exp(-2.0 * k / x);
+  return (2 * n + 1) * exp(-k * (kPi * kPi) * x / 2.0);
+}
+
+// p / (p + q), the chance of the exponential part of the proposal, from the
+// masses' logarithms (both underflow at large z): p = pi/(2K) exp(-K t),
+// q = exp(-z) erfc((1 - z t)/sqrt(2t)) + erfcx((1 + z t)/sqrt(2t))
+// exp(-z^2 t/2 - 1/(2t)).
+__device__ double right_probability(double z, double K) {
+  const double lp = log(kPi / (2.0 * K)) - K * kT;
+  const double r = sqrt(2.0 * kT);
+  const double l1 = -z + log(erfc((1.0 - z * kT) / r));
+  const double l2 = log(erfcx((1.0 + z * kT) / r)) - z * z * kT / 2.0 - 1.0 / (2.0 * kT);
+  const double hi = l1 >= l2 ? l1 : l2, lo = l1 >= l2 ? l2 : l1;
+  const double d = hi + log1p(exp(lo - hi)) - lp;
+  return d > 700.0 ? 0.0 : 1.0 / (1.0 + exp(d));
 }
 
 // IG(1/z, 1) restricted to (0, t]; z < 1/t (z = 0 included) through the
@@ -88,31 +102,25 @@ __device__ double truncated_ig(double z, PgUniforms& u) {
 __device__ double pg1(double c, PgUniforms& u) {
   const double z = 0.5 * fabs(c);
   const double K = kPi * kPi / 8.0 + z * z / 2.0;
-  // Masses of the two proposal parts: p = pi/(2K) exp(-K t) and
-  // q = 2 exp(-z) P_IG(X <= t), its large-z term through erfcx.
-  const double pm = kPi / (2.0 * K) * exp(-K * kT);
-  const double r = sqrt(2.0 * kT);
-  const double qm = exp(-z) * erfc((1.0 - z * kT) / r) +
-                    erfcx((1.0 + z * kT) / r) * exp(-z * z * kT / 2.0 - 1.0 / (2.0 * kT));
-  const double right = pm / (pm + qm);
+  const double right = right_probability(z, K);
   double x = kT;
   for (int a = 0; a < kCap; ++a) {
     if (u() < right)
       x = kT - log(u()) / K;
     else
       x = truncated_ig(z, u);
-    double s = series_term(0, x);
-    const double y = u() * s;
+    double s = 1.0;  // partial sums over a_0(x)
+    const double y = u();
     bool accepted = false;
     for (int n = 1; n < kCap; ++n) {
       if (n & 1) {
-        s -= series_term(n, x);
+        s -= series_ratio(n, x);
         if (y < s) {
           accepted = true;
           break;
         }
       } else {
-        s += series_term(n, x);
+        s += series_ratio(n, x);
         if (y > s) break;
       }
     }

@@ -25,11 +25,13 @@ def say(*a):
 
 def test_pg_sample_matches_oracle():
     """3000 tilts spanning 0, both signs, the two inverse-Gaussian branches
-    (|c|/2 below and above 1/0.64) and |c| up to 300, over a ragged tail."""
+    (|c|/2 below and above 1/0.64), |c| up to 300 and two beyond the range
+    where the series' leading term underflows (1e4, -3e3), over a ragged
+    tail."""
     rng = np.random.default_rng(4)
-    c = np.concatenate([[0.0, -0.0, 3.125, -3.125, 300.0, -300.0, 1e-300],
+    c = np.concatenate([[0.0, -0.0, 3.125, -3.125, 300.0, -300.0, 1e-300, 1e4, -3e3],
                         rng.standard_normal(1000) * 0.5, rng.standard_normal(1000) * 6.0,
-                        rng.uniform(-300, 300, 993)])
+                        rng.uniform(-300, 300, 991)])
     got = pk.pg_sample(torch.as_tensor(c, device=DEV), 123, 4, 9).cpu().numpy()
     ref = G.pg_draws(123, 4, 9, c)
     err = np.abs(got - ref) / ref
