@@ -12,7 +12,8 @@ scalars, the faster form at the 1e-5 accuracy bar), the FP32-vector form with
 its FP64 refinement beside it, the HBM roofline of the dominant kernel (the X
 pass, timed with HIP events on the solver's stream during the timed draws),
 the general-prior forms on the same draws (prior preconditioner cold and
-warm-started, Jacobi, the adaptive switch), Gibbs steps with the device
+warm-started, Jacobi, the adaptive switch), the adjoint form against plain
+solves of the same systems, Gibbs steps with the device
 Polya-Gamma omega update, and the CPU oracle timed on this host as a
 baseline.
 
@@ -309,6 +310,43 @@ def gibbs_forms(pk, torch, P, X, steps, warmup, tol):
     ev[1].synchronize()
     out["pg_update_ms"] = ev[0].elapsed_time(ev[1]) / steps
     return out
+
+
+def adjoint_forms(pk, torch, P, X, steps, warmup, tol):
+    """The adjoint form on the same workload (FP64): a = Phi^-1 g for the loss
+    sum_j w_j beta_j^2 (g = 2 w beta, w ~ U(0, 1)) and the gradients with
+    respect to b, log lambda and log tau, against plain solves of the same
+    systems; each timed over `steps` right-hand sides after `warmup`."""
+    rng = np.random.default_rng(SEED + 2)
+    om = torch.as_tensor(P.omega, device="cuda")
+    la = torch.as_tensor(P.lam, device="cuda")
+    w = torch.as_tensor(rng.uniform(0.0, 1.0, P.p), device="cuda")
+    bs = [torch.as_tensor(rng.standard_normal(P.p), device="cuda") for _ in range(warmup + steps)]
+
+    def timed(one):
+        for k in range(warmup):
+            one(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = [one(k) for k in range(warmup, warmup + steps)]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, its
+
+    betas = {}
+
+    def forward(k):
+        betas[k], info = pk.solve(X, om, la, P.tau, bs[k], tol=tol)
+        return info["iters"]
+
+    def backward(k):
+        _, _, _, info = pk.solve_backward(X, om, la, P.tau, betas[k], 2.0 * w * betas[k], tol=tol)
+        return info["iters"]
+
+    el_f, its_f = timed(forward)
+    el_b, its_b = timed(backward)
+    return {"backward_per_s": steps / el_b, "backward_cg_iters_mean": float(np.mean(its_b)),
+            "solve_per_s": steps / el_f, "solve_cg_iters_mean": float(np.mean(its_f)),
+            "backward_vs_solve": el_f / el_b}
 
 
 def copy_rate():
@@ -691,6 +729,10 @@ def main():
               file=sys.stderr, flush=True)
         out["preconditioner_forms"] = precond_forms(pk, torch, P, X, args.steps, args.warmup,
                                                     args.tol)
+    if not args.no_precond:
+        print(f"[bench] adjoint form ({args.warmup}+{args.steps} solves)", file=sys.stderr,
+              flush=True)
+        out["adjoint_form"] = adjoint_forms(pk, torch, P, X, args.steps, args.warmup, args.tol)
     if not args.no_gibbs:
         print(f"[bench] Gibbs steps with the Polya-Gamma update ({args.warmup}+{args.steps} "
               "per form)", file=sys.stderr, flush=True)
