@@ -446,43 +446,61 @@ __device__ __forceinline__ int asm_pair(int u, int tid, int rb, int nb, int npai
 // and stored by thread 0.  (The workgroup's own entries go to s_new after
 // the pass, from LDS.)  Returns false (nothing done) when the panel is not
 // 16-byte aligned or shorter than two entries.
-template <typename PRIME>
-__device__ __forceinline__ bool assemble_dir_fast(const double* zp, const double* sp, double bc,
-                                                  int wlen, int w, double* xl, PRIME& prime) {
+// The loads of the FP64 direction panel, held in registers so that they are
+// in flight while the pass finishes the previous step (the ratio bc is not
+// needed until the stores).  False (nothing loaded) when the panel is not
+// 16-byte aligned or shorter than two entries.
+struct DirFast {
+  f64x2 zv[kAsmPairs], sv[kAsmPairs];
+  int pi[kAsmPairs];
+  double zt, st;
+};
+__device__ __forceinline__ bool dir_fast_load(DirFast& L, const double* zp, const double* sp,
+                                              int wlen, int w) {
   const int npairs = wlen >> 1;
   if (npairs < 1 || !aligned16(zp) || !aligned16(sp)) return false;
   const int nb = (npairs + kPThreads - 1) / kPThreads;
   const int rb = w % nb;
   const int tid = threadIdx.x;
-  f64x2 zv[kAsmPairs], sv[kAsmPairs];
-  int pi[kAsmPairs];
 #pragma unroll
   for (int u = 0; u < kAsmPairs; ++u) {
-    pi[u] = asm_pair(u, tid, rb, nb, npairs);
-    const int at = pi[u] >= 0 ? 2 * pi[u] : 0;
-    zv[u] = *gview(reinterpret_cast<const f64x2*>(zp + at));
-    sv[u] = *gview(reinterpret_cast<const f64x2*>(sp + at));
+    L.pi[u] = asm_pair(u, tid, rb, nb, npairs);
+    const int at = L.pi[u] >= 0 ? 2 * L.pi[u] : 0;
+    L.zv[u] = *gview(reinterpret_cast<const f64x2*>(zp + at));
+    L.sv[u] = *gview(reinterpret_cast<const f64x2*>(sp + at));
   }
   const int last = wlen - 1;  // the odd entry, when wlen is odd
-  const double zt = gview(zp)[last], st = gview(sp)[last];
+  L.zt = gview(zp)[last];
+  L.st = gview(sp)[last];
+  return true;
+}
+
+// s = z + bc s_old from the loaded pairs into the panel: the first half's
+// entries go to LDS, the ring is primed, then the second half; an odd last
+// entry is stored by thread 0.  (The workgroup's own entries go to s_new
+// after the pass, from LDS.)
+template <typename PRIME>
+__device__ __forceinline__ void dir_fast_store(const DirFast& L, double bc, int wlen, double* xl,
+                                               PRIME& prime) {
+  const int tid = threadIdx.x;
+  const int last = wlen - 1;
   auto form = [&](double z, double so) { return bc == 0.0 ? z : z + bc * so; };
 #pragma unroll
   for (int u = 0; u < kAsmPairs / 2; ++u) {
-    if (pi[u] >= 0) {
-      xl[2 * pi[u]] = form(zv[u].x, sv[u].x);
-      xl[2 * pi[u] + 1] = form(zv[u].y, sv[u].y);
+    if (L.pi[u] >= 0) {
+      xl[2 * L.pi[u]] = form(L.zv[u].x, L.sv[u].x);
+      xl[2 * L.pi[u] + 1] = form(L.zv[u].y, L.sv[u].y);
     }
   }
   prime();
 #pragma unroll
   for (int u = kAsmPairs / 2; u < kAsmPairs; ++u) {
-    if (pi[u] >= 0) {
-      xl[2 * pi[u]] = form(zv[u].x, sv[u].x);
-      xl[2 * pi[u] + 1] = form(zv[u].y, sv[u].y);
+    if (L.pi[u] >= 0) {
+      xl[2 * L.pi[u]] = form(L.zv[u].x, L.sv[u].x);
+      xl[2 * L.pi[u] + 1] = form(L.zv[u].y, L.sv[u].y);
     }
   }
-  if ((wlen & 1) && tid == 0) xl[last] = form(zt, st);
-  return true;
+  if ((wlen & 1) && tid == 0) xl[last] = form(L.zt, L.st);
 }
 
 // Panel copied from src (FP64, one vector), the same way.
@@ -539,25 +557,62 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   // direction ratio per vector (a vector whose chain has stopped keeps s = z:
   // its sums are unused)
   double bc[K];
-  double fin_a = 0.0, fin_b = 0.0;  // the previous step's partials (pass-side finish)
   if constexpr (MODE == kPassDir) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
       const auto& S = gview(dir.sc)[(int64_t)r * dir.scstride];
       bc[r] = S.done ? 0.0 : S.betacg;
     }
-    if (K == 1 && dir.sp != nullptr && dir.it > 0) {
-      const auto* P = gview(dir.sp + (int64_t)(1 - parity) * 2 * kMaxRedBlocks);
-      for (int q = lane; q < dir.nsb; q += 64) {
-        fin_a += P[2 * q];
-        fin_b += P[2 * q + 1];
-      }
-    }
   }
   if (done != nullptr) {
     bool all = true;
     for (int i = 0; i < ndone; ++i) all = all && gview(done)[(int64_t)i * dstride] != 0;
     if (all) return;
+  }
+  // The previous step's partials (pass-side finish), requested now and
+  // summed after the panel's loads are issued: up to kFinRegs pairs per lane
+  // in registers (clamped in-bounds reads, zeros past the end), more by a
+  // loop.  Either way each lane adds its pairs in index order.
+  constexpr int kFinRegs = 4;
+  double fa[kFinRegs], fb[kFinRegs];
+  double fin_a = 0.0, fin_b = 0.0;
+  bool fin_regs = false;
+  if constexpr (MODE == kPassDir) {
+    if (K == 1 && dir.sp != nullptr && dir.it > 0) {
+      const auto* P = gview(dir.sp + (int64_t)(1 - parity) * 2 * kMaxRedBlocks);
+      if (dir.nsb <= 64 * kFinRegs) {
+        fin_regs = true;
+#pragma unroll
+        for (int i = 0; i < kFinRegs; ++i) {
+          const int q = lane + 64 * i;
+          const int qc = q < dir.nsb ? q : dir.nsb - 1;
+          const double va = P[2 * qc], vb = P[2 * qc + 1];
+          fa[i] = q < dir.nsb ? va : 0.0;
+          fb[i] = q < dir.nsb ? vb : 0.0;
+        }
+      } else {
+        for (int q = lane; q < dir.nsb; q += 64) {
+          fin_a += P[2 * q];
+          fin_b += P[2 * q + 1];
+        }
+      }
+    }
+  }
+  const int64_t g0 = (int64_t)panel * t.W;
+  const int64_t rem = t.gdim - g0;
+  const int wlen = (int)(rem < t.W ? rem : t.W);
+  DirFast dfl;
+  bool dfl_ok = false;
+  if constexpr (MODE == kPassDir && kFastPanel<T, K>) {
+    const T* s_old = dir.s + (int64_t)parity * dir.sstride;
+    dfl_ok = dir_fast_load(dfl, dir.z + g0, s_old + g0, wlen, w);
+  }
+  if (fin_regs) {
+#pragma unroll
+    for (int i = 0; i < kFinRegs; ++i) {
+      fin_a += fa[i];
+      fin_b += fb[i];
+    }
   }
   if constexpr (MODE == kPassDir && K == 1) {
     if (dir.sp != nullptr) {
@@ -619,9 +674,6 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
     for (int q = 0; q < kRing; ++q) stream_issue(t, c_end, lane, ld, ra[q], rb[q], rs[q], rh, q);
   };
 
-  const int64_t g0 = (int64_t)panel * t.W;
-  const int64_t rem = t.gdim - g0;
-  const int wlen = (int)(rem < t.W ? rem : t.W);
   // The panel of the gathered vector(s), assembled once per workgroup; entry
   // W holds the zeros the padding indices point to.  Eight loads in flight
   // per thread before the LDS stores.  Every workgroup reads the same
@@ -640,8 +692,10 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
     // FP64, one vector: every thread's 16-byte loads issued at once, then
     // the ring's first windows, then the LDS stores.
     if constexpr (MODE == kPassDir) {
-      const T* s_old = dir.s + (int64_t)parity * dir.sstride;
-      assembled = assemble_dir_fast(dir.z + g0, s_old + g0, bc0, wlen, w, xl, prime);
+      if (dfl_ok) {
+        dir_fast_store(dfl, bc0, wlen, xl, prime);
+        assembled = true;
+      }
     } else if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr &&
                xin.es == 1) {
       assembled = assemble_copy_fast(xin.part + g0, wlen, w, xl, prime);
