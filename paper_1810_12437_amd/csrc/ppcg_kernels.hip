@@ -469,7 +469,10 @@ __device__ __forceinline__ bool dir_fast_load(DirFast& L, const double* zp, cons
     L.zv[u] = *gview(reinterpret_cast<const f64x2*>(zp + at));
     L.sv[u] = *gview(reinterpret_cast<const f64x2*>(sp + at));
   }
-  const int last = wlen - 1;  // the odd entry, when wlen is odd
+  // The odd entry, when wlen is odd (thread 0 stores it): a per-lane address
+  // (entry 0 elsewhere), so that these are vector loads in flight with the
+  // pairs rather than scalar loads waited for at once.
+  const int last = tid == 0 ? wlen - 1 : 0;
   L.zt = gview(zp)[last];
   L.st = gview(sp)[last];
   return true;
@@ -530,14 +533,14 @@ __device__ __forceinline__ bool assemble_copy_fast(const double* src, int wlen, 
 }
 
 // Workgroup w of one X pass over K interleaved vectors (K = 1: one vector).
-// The pass is skipped when all ndone flags done[i * dstride] are set.  With
+// The pass is skipped when all K flags done[i * dstride] are set.  With
 // dir.z set the gathered panel is the new CG direction (DirIn); with dot.s
 // set the workgroup also sums its outputs against s (DotOut).
 template <typename T, int K, int MODE>
 __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>& xin,
                                            T* __restrict__ part_out, T* __restrict__ piece_out,
                                            const T* __restrict__ out_scale,
-                                           const int32_t* __restrict__ done, int ndone,
+                                           const int32_t* __restrict__ done,
                                            int dstride, const DirIn<T>& dir,
                                            const DotOut<T>& dot, int parity, int w) {
   constexpr bool dotting = MODE == kPassDot;
@@ -546,28 +549,32 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
-  // What the start needs, requested together: this wavefront's chunk range
-  // and first descriptor, the panel, the stop flag(s) and the direction's
-  // ratio.
+  // What the start needs, requested together: this wavefront's chunk range,
+  // the panel, the stop flag(s) and the direction's ratio; then the loads
+  // that depend on them.  The stop flags are tested only once every load of
+  // the start is in flight (each of them is in bounds either way), so a
+  // launch that runs waits for one round trip of dependent loads, not three.
   int c = read_table(t.wave_c, kPWaves * w + wave);
   const int c_end = read_table(t.wave_c, kPWaves * w + wave + 1);
   const int panel = read_table(t.wg_panel, w);
-  ChunkDesc D0{};
-  if (c < c_end) D0 = read_desc(t.chunks, c);
+  // (loads without branches, so that none is waited for before the
+  // descriptor's; no flags: the table stands in, read at offset 0)
+  const int32_t* fp = done != nullptr ? done : t.wave_c;
+  const int64_t fs = done != nullptr ? dstride : 0;
+  int32_t flag[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) flag[i] = gview(fp)[(int64_t)i * fs];
   // direction ratio per vector (a vector whose chain has stopped keeps s = z:
-  // its sums are unused)
-  double bc[K];
+  // its sums are unused), formed once the flags are tested
+  int32_t sdone[K];
+  double sbc[K], bc[K];
   if constexpr (MODE == kPassDir) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
       const auto& S = gview(dir.sc)[(int64_t)r * dir.scstride];
-      bc[r] = S.done ? 0.0 : S.betacg;
+      sdone[r] = S.done;
+      sbc[r] = S.betacg;
     }
-  }
-  if (done != nullptr) {
-    bool all = true;
-    for (int i = 0; i < ndone; ++i) all = all && gview(done)[(int64_t)i * dstride] != 0;
-    if (all) return;
   }
   // The previous step's partials (pass-side finish), requested now and
   // summed after the panel's loads are issued: up to kFinRegs pairs per lane
@@ -586,9 +593,8 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
         for (int i = 0; i < kFinRegs; ++i) {
           const int q = lane + 64 * i;
           const int qc = q < dir.nsb ? q : dir.nsb - 1;
-          const double va = P[2 * qc], vb = P[2 * qc + 1];
-          fa[i] = q < dir.nsb ? va : 0.0;
-          fb[i] = q < dir.nsb ? vb : 0.0;
+          fa[i] = P[2 * qc];  // (the stand-ins past the end are dropped in the sum)
+          fb[i] = P[2 * qc + 1];
         }
       } else {
         for (int q = lane; q < dir.nsb; q += 64) {
@@ -607,11 +613,24 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
     const T* s_old = dir.s + (int64_t)parity * dir.sstride;
     dfl_ok = dir_fast_load(dfl, dir.z + g0, s_old + g0, wlen, w);
   }
+  ChunkDesc D0{};
+  if (c < c_end) D0 = read_desc(t.chunks, c);
+  if (done != nullptr) {
+    bool all = true;
+#pragma unroll
+    for (int i = 0; i < K; ++i) all = all && flag[i] != 0;
+    if (all) return;
+  }
+  if constexpr (MODE == kPassDir) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) bc[r] = sdone[r] ? 0.0 : sbc[r];
+  }
   if (fin_regs) {
 #pragma unroll
     for (int i = 0; i < kFinRegs; ++i) {
-      fin_a += fa[i];
-      fin_b += fb[i];
+      const bool in = lane + 64 * i < dir.nsb;
+      fin_a += in ? fa[i] : 0.0;
+      fin_b += in ? fb[i] : 0.0;
     }
   }
   if constexpr (MODE == kPassDir && K == 1) {
@@ -909,7 +928,7 @@ __global__ __launch_bounds__(kPThreads) void k_panel(PanelPass t, Combine<T> xin
                                                      const T* __restrict__ out_scale,
                                                      const int32_t* __restrict__ done,
                                                      DirIn<T> dir, DotOut<T> dot, int parity) {
-  panel_body<T, 1, MODE>(t, xin, part_out, piece_out, out_scale, done, 1, 0, dir, dot, parity,
+  panel_body<T, 1, MODE>(t, xin, part_out, piece_out, out_scale, done, 0, dir, dot, parity,
                          xcd_logical_wg());
 }
 
@@ -919,7 +938,7 @@ __global__ __launch_bounds__(kPThreads) void k_panel_b(const PanelJob<T>* __rest
                                                        const int32_t* __restrict__ wg_local,
                                                        int parity) {
   const PanelJob<T>& J = jobs[wg_job[blockIdx.x]];
-  panel_body<T, 1, MODE>(J.t, J.x, J.part_out, J.piece_out, J.out_scale, J.done, 1, 0, J.dir,
+  panel_body<T, 1, MODE>(J.t, J.x, J.part_out, J.piece_out, J.out_scale, J.done, 0, J.dir,
                          J.dot, parity, wg_local[blockIdx.x]);
 }
 
@@ -933,7 +952,7 @@ __global__ __launch_bounds__(kPThreads) void k_panel_k(PanelPass t, Combine<T> x
                                                        const int32_t* __restrict__ done,
                                                        int dstride, DirIn<T> dir, DotOut<T> dot,
                                                        int parity) {
-  panel_body<T, K, MODE>(t, xin, part_out, piece_out, out_scale, done, K, dstride, dir, dot,
+  panel_body<T, K, MODE>(t, xin, part_out, piece_out, out_scale, done, dstride, dir, dot,
                          parity, xcd_logical_wg());
 }
 
@@ -1469,9 +1488,19 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
                                              const double* p2, int n2, int ps, int64_t p,
                                              VGrid g, int parity = 0) {
   DevScal* sc = w.sc;
-  if (sc->done) return;
-  // This thread's first element, requested before the grid total below
-  // (it does not depend on alpha): its loads overlap the partials' loads.
+  // The passes' partials and this thread's first element are requested
+  // before the stop flag is tested (every read is in bounds either way) and
+  // before the grid total below (the element does not depend on alpha), so
+  // that all these loads are in flight together.
+  // <s, Phi s> = <s, d s> + <s, X^T u>: the same fixed-order total in every
+  // block, all threads loading at once (the partials come from other XCDs);
+  // one partial of each pass per thread when they fit, a loop otherwise.
+  const bool fit = n1 <= kWG && n2 <= kWG;
+  double pa = 0.0, pb = 0.0;
+  if (fit) {
+    if ((int)threadIdx.x < n1) pa = p1[(int64_t)threadIdx.x * ps];
+    if ((int)threadIdx.x < n2) pb = p2[(int64_t)threadIdx.x * ps];
+  }
   const int64_t j0 = (int64_t)g.bid * kWG + threadIdx.x;
   double s0 = 0.0, q0 = 0.0, d0 = 0.0, r0 = 0.0, m0 = 0.0;
   if (j0 < p) {
@@ -1481,14 +1510,18 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
     r0 = r[j0];
     m0 = m[j0];
   }
-  const double rho = sc->rho;
-  // <s, Phi s> = <s, d s> + <s, X^T u>: the same fixed-order total in every
-  // block, all threads loading at once (the partials come from other XCDs)
-  __shared__ double sq_sh;
-  {
-    double a[1] = {0.0};
+  double a[1] = {0.0};
+  if (fit) {
+    a[0] += pa;
+    a[0] += pb;
+  } else {
     for (int q = threadIdx.x; q < n1; q += kWG) a[0] += p1[(int64_t)q * ps];
     for (int q = threadIdx.x; q < n2; q += kWG) a[0] += p2[(int64_t)q * ps];
+  }
+  if (sc->done) return;
+  const double rho = sc->rho;
+  __shared__ double sq_sh;
+  {
     block_sum<1>(a);
     if (threadIdx.x == 0) sq_sh = a[0];
   }
