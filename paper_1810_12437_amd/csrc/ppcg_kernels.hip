@@ -439,13 +439,6 @@ __device__ __forceinline__ int asm_pair(int u, int tid, int rb, int nb, int npai
   return (u < nb && pl < npairs) ? pl : -1;
 }
 
-// Panel of s = z + bc s_old (FP64; zp, sp at the panel's first entry): pair
-// i is entries 2i, 2i+1.  All loads are issued (stand-ins past the end)
-// before any is waited for: the first half's sums go to LDS, the ring is
-// primed, then the second half.  An odd last entry is read by every thread
-// and stored by thread 0.  (The workgroup's own entries go to s_new after
-// the pass, from LDS.)  Returns false (nothing done) when the panel is not
-// 16-byte aligned or shorter than two entries.
 // The loads of the FP64 direction panel, held in registers so that they are
 // in flight while the pass finishes the previous step (the ratio bc is not
 // needed until the stores).  False (nothing loaded) when the panel is not
