@@ -58,9 +58,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "033755a96b99be41a8cb9ec6e59528923ea0424267acd6cea562d5b1449d409d",
+    "sources_sha256": "9c99e4f97b08a2889b4fd5a0f5876b2732ba422e2f8025497af77252864990c6",
     # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
-    "bytes_per_launch": 118537977,
+    "bytes_per_launch": 118766380,
 }
 
 
