@@ -87,7 +87,10 @@ typedef struct ppcg_options {
                          rule, restart once from it; -1: default (1 for F32, 0 for F64) */
   double tol;         /* tolerance of the stopping rule (default 1e-6)           */
   int32_t true_resid; /* 1 (default): recompute b - Phi beta in FP64 at the end     */
-  int32_t check_every;/* host convergence check period in iterations (0: default) */
+  int32_t check_every;/* host convergence check period in iterations (0: default 16);
+                         a batch queued when the decay of the rule measure
+                         predicts the end within one period is shortened to
+                         the predicted remainder plus one iteration          */
   double loop_factor; /* the recursion runs to loop_factor * tol before the FP64
                          check (0: default, 0.5 for F32 and 1 for F64)         */
   int32_t no_graph;   /* batched loops: 0 (default) replays each check batch as a
