@@ -228,6 +228,29 @@ def test_profile_samples_leave_draw_unchanged(problem_cache):
     assert st["csr_ms"] > 0.0 and st["csc_ms"] > 0.0
 
 
+@pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
+def test_check_period_leaves_draw_unchanged(f32):
+    """The host's check batches (their period, the shortened batch queued when
+    the end is predicted within one period, a batch not queued ahead) only
+    decide when the host looks: the device stops at the same iteration, so
+    the draw is the same bits for every period."""
+    P = synth.scaled_problem(6000, 1200, seed=77, tau=0.05)  # ~200 FP64 iterations
+    X = pk.Matrix.from_problem(P)
+    cast = t32 if f32 else t64
+    runs = []
+    for every in (1, 3, 7, 16, 40):
+        beta, info = pk.draw(X, cast(P.omega), cast(P.z), cast(P.lam), P.tau, 5, 1, 2,
+                             tol=1e-6 if f32 else 1e-9, check_every=every)
+        runs.append((every, beta, info))
+        say(f"[check period] f32={f32} every={every} iters={info['iters']}"
+            f"+{info['refine_iters']} status={info['status']}")
+    _, b0, i0 = runs[0]
+    assert i0["status"] == 0 and i0["iters"] > 40
+    for every, b, i in runs[1:]:
+        assert torch.equal(b, b0), every
+        assert (i["iters"], i["refine_iters"]) == (i0["iters"], i0["refine_iters"]), every
+
+
 @pytest.mark.parametrize("n,p", [(4000, 900), (20000, 3000)])
 def test_draw_f32_matches_f64_oracle(n, p):
     P = synth.scaled_problem(n, p, seed=n + p)
