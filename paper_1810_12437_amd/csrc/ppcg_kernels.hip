@@ -545,8 +545,8 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   // What the start needs, requested together: this wavefront's chunk range,
   // the panel, the stop flag(s) and the direction's ratio; then the loads
   // that depend on them.  The stop flags are tested only once every load of
-  // the start is in flight (each of them is in bounds either way), so a
-  // launch that runs waits for one round trip of dependent loads, not three.
+  // the start is in flight (each of them is in bounds either way), so that
+  // no load of a launch that runs waits behind the test.
   int c = read_table(t.wave_c, kPWaves * w + wave);
   const int c_end = read_table(t.wave_c, kPWaves * w + wave + 1);
   const int panel = read_table(t.wg_panel, w);
