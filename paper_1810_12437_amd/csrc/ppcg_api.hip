@@ -151,7 +151,7 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
     PPCG_TRY_HIP(hipEventSynchronize(X->chk[slot]));
     const DevScal& h = X->h_sc[slot];
     // The sampled iteration counts only if its passes ran: once the rule
-    // holds, the row pass of iteration iters and all later ones exit at once.
+    // holds, the row pass of iteration iters and all later ones return early.
     if (stamped[slot] && (!h.done || start[slot] + sample < h.iters)) {
       float a = 0.f, b = 0.f;
       PPCG_TRY_HIP(hipEventElapsedTime(&a, X->ev[4 * slot], X->ev[4 * slot + 1]));
