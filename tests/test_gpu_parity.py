@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances ("parity bar"):
+Tolerances:
 * FP64 form: 1e-10 relative (l2) in beta against the oracle's PCG on the same
   inputs and the same eta/delta stream; products and b to 1e-12.
 * FP32 form: 1e-5 relative in beta against the FP64 oracle on the
