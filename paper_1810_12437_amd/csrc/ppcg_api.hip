@@ -137,11 +137,11 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
                                e ? e[1] : nullptr, &dir, parity));
       PPCG_TRY_HIP(col_pass<T>(X, omegaT, nullptr, done, st, e ? e[2] : nullptr,
                                e ? e[3] : nullptr, &dot, parity));
+      // the batch's last step also writes the scalars into the readback slot
       PPCG_TRY_HIP(launch_cg_step<T>(w, s, X->p, parity, true, qsrc, X->d, X->m, X->beta64,
-                                     X->r64, X->z64, X->p1[ti], n1, X->p2[ti], n2, X->p, st));
+                                     X->r64, X->z64, X->p1[ti], n1, X->p2[ti], n2, X->p, st,
+                                     i + 1 == nb ? &X->h_sc[slot] : nullptr));
     }
-    PPCG_TRY_HIP(hipMemcpyAsync(&X->h_sc[slot], X->sc, sizeof(DevScal), hipMemcpyDeviceToHost,
-                                st));
     PPCG_TRY_HIP(hipEventRecord(X->chk[slot], st));
     ++batch;
     return PPCG_OK;

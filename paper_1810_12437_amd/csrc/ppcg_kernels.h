@@ -260,11 +260,15 @@ hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* q
 // 1 - parity of s).  With pass_finish the kernel stops at the per-block
 // partials of rho' and <r, r> (in w.part + parity * 2 * kMaxRedBlocks) and the
 // next row pass finishes the step (DirIn.sp); otherwise its last block does.
+// With pass_finish and snap set, the kernel also copies the scalars to snap
+// (host memory mapped for the device, e.g. a pinned readback slot) once they
+// are final for this launch, in place of a copy operation after it.
 template <typename T>
 hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity, bool pass_finish,
                           const Combine<T>& qsrc, const double* d, const double* m,
                           double* beta, double* r, double* z, const double* p1, int32_t n1,
-                          const double* p2, int32_t n2, int64_t p, hipStream_t st);
+                          const double* p2, int32_t n2, int64_t p, hipStream_t st,
+                          DevScal* snap = nullptr);
 
 // One X pass over K in {2, 4, 8} interleaved vectors ([dim][K] inputs and
 // outputs; part_out[(k * out_dim + id) * K + r]); skipped when the K flags

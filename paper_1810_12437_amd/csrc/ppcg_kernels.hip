@@ -1471,6 +1471,15 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
   }
 }
 
+// The scalars copied word by word to snap by one thread, after that
+// thread's own writes to them (so its loads see them).
+__device__ __forceinline__ void snapshot_scal(const DevScal* sc, DevScal* snap) {
+  static_assert(sizeof(DevScal) % 8 == 0, "DevScal is copied in 8-byte words");
+  const uint64_t* a = reinterpret_cast<const uint64_t*>(sc);
+  uint64_t* b = reinterpret_cast<uint64_t*>(snap);
+  for (int i = 0; i < (int)(sizeof(DevScal) / 8); ++i) b[i] = a[i];
+}
+
 // One CG step after the two passes (see launch_cg_step).  p1 / p2 hold the
 // passes' workgroup partials (n1 and n2 of them, stride ps).
 template <typename T, bool PassFinish = false>
@@ -1479,8 +1488,9 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
                                              const double* m, double* beta, double* r,
                                              double* z, int zes, const double* p1, int n1,
                                              const double* p2, int n2, int ps, int64_t p,
-                                             VGrid g, int parity = 0) {
+                                             VGrid g, int parity = 0, DevScal* snap = nullptr) {
   DevScal* sc = w.sc;
+  const bool snapper = PassFinish && snap != nullptr && g.bid == 0 && threadIdx.x == 0;
   // The passes' partials and this thread's first element are requested
   // before the stop flag is tested (every read is in bounds either way) and
   // before the grid total below (the element does not depend on alpha), so
@@ -1511,7 +1521,10 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
     for (int q = threadIdx.x; q < n1; q += kWG) a[0] += p1[(int64_t)q * ps];
     for (int q = threadIdx.x; q < n2; q += kWG) a[0] += p2[(int64_t)q * ps];
   }
-  if (sc->done) return;
+  if (sc->done) {
+    if (snapper) snapshot_scal(sc, snap);
+    return;
+  }
   const double rho = sc->rho;
   __shared__ double sq_sh;
   {
@@ -1526,6 +1539,7 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
       sc->status = kStatBreakdown;
       sc->done = 1;
       sc->alpha = 0.0;
+      if (snapper) snapshot_scal(sc, snap);
     }
     return;
   }
@@ -1553,6 +1567,7 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
       if (g.bid == 0) {
         sc->sq = sq;
         sc->alpha = alpha;
+        if (snapper) snapshot_scal(sc, snap);
       }
     }
     return;
@@ -1605,9 +1620,10 @@ __global__ __launch_bounds__(kWG) void k_cg_step_pf(VecWork w, const T* s, Combi
                                                     const double* d, const double* m,
                                                     double* beta, double* r, double* z,
                                                     const double* p1, int n1, const double* p2,
-                                                    int n2, int64_t p, int parity) {
+                                                    int n2, int64_t p, int parity,
+                                                    DevScal* snap) {
   cg_step_body<T, true>(w, s, 1, qsrc, d, m, beta, r, z, 1, p1, n1, p2, n2, 1, p, own_grid(),
-                        parity);
+                        parity, snap);
 }
 
 hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
@@ -1622,11 +1638,12 @@ template <typename T>
 hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity, bool pass_finish,
                           const Combine<T>& qsrc, const double* d, const double* m,
                           double* beta, double* r, double* z, const double* p1, int32_t n1,
-                          const double* p2, int32_t n2, int64_t p, hipStream_t st) {
+                          const double* p2, int32_t n2, int64_t p, hipStream_t st,
+                          DevScal* snap) {
   const T* sn = s + (int64_t)(1 - parity) * sstride;
   if (pass_finish)
     hipLaunchKernelGGL((k_cg_step_pf<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, sn, qsrc, d, m,
-                       beta, r, z, p1, n1, p2, n2, p, parity);
+                       beta, r, z, p1, n1, p2, n2, p, parity, snap);
   else
     hipLaunchKernelGGL((k_cg_step<T>), dim3(red_grid(p)), dim3(kWG), 0, st, w, sn, qsrc, d, m,
                        beta, r, z, p1, n1, p2, n2, p);
@@ -1688,7 +1705,7 @@ hipError_t launch_cg_step_batched(const VecJob<T>* jobs, const int32_t* blk_job,
   template hipError_t launch_cg_step<T>(VecWork, const T*, int64_t, int, bool, const Combine<T>&,  \
                                         const double*, const double*, double*, double*,      \
                                         double*, const double*, int32_t, const double*,      \
-                                        int32_t, int64_t, hipStream_t);                      \
+                                        int32_t, int64_t, hipStream_t, DevScal*);            \
   template hipError_t launch_cg_start_batched<T>(const VecJob<T>*, const int32_t*,           \
                                                  const int32_t*, int32_t, int, double, int,    \
                                                  int, double, hipStream_t);                    \
