@@ -58,9 +58,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "a820600b5949493a1ca6c0f99de7fa9c37fa41d0600741d726771178c633fafc",
+    "sources_sha256": "a436701aa39adddad2bf11be19da5a62cba9beb4389d00851570067e1f6ffc44",
     # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
-    "bytes_per_launch": 118769263,
+    "bytes_per_launch": 118772695,
 }
 
 
