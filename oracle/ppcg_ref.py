@@ -119,10 +119,14 @@ def solve_chol(Phi, b):
 
 def draw_chol(Phi, mean_rhs, xi):
     """Textbook Cholesky sampler of N(Phi^-1 mean_rhs, Phi^-1):
-    beta = mu + L^-T xi with Phi = L L^T, xi ~ N(0, I) (Section 2.1)."""
+    beta = mu + L^-T xi with Phi = L L^T, xi ~ N(0, I) (Section 2.1).
+    xi is one standard normal vector (p) or one per column (p x N); the
+    result has the same shape."""
     L = cholesky(Phi)
     mu = sla.cho_solve((L, True), mean_rhs)
-    return mu + sla.solve_triangular(L.T, xi, lower=False)
+    xi = np.asarray(xi, dtype=np.float64)
+    dev = sla.solve_triangular(L.T, xi, lower=False)
+    return mu + dev if xi.ndim == 1 else mu[:, None] + dev
 
 
 @dataclasses.dataclass
@@ -288,6 +292,42 @@ def criterion_value(criterion, r, b, m):
     if criterion == REL_PLAIN:
         return float(np.linalg.norm(r) / np.linalg.norm(b))
     raise ValueError(criterion)
+
+
+def error_metrics(beta, beta_ref, scale, Phi=None, mean_rhs=None):
+    """Distances of an iterate from a reference solution (FP64).
+
+    rel_l2:     ||beta - beta_ref||_2 / ||beta_ref||_2
+    scaled_max: max_j |beta_j - beta_ref_j| / scale_j, scale = tau lambda
+                (the prior scale of beta_j, Supplement S4.2; any positive
+                scale, e.g. sqrt(M^-1) of a general preconditioner)
+    coord_rel:  mean_j |(beta - beta_ref)_j / (beta_ref)_j|, the coordinate-
+                wise relative error averaged over the coefficients that
+                Section 3.2 plots (coefficients with beta_ref_j = 0 left out)
+    secmom_rms: {p^-1 sum_j xi_j^-2 (beta - beta_ref)_j^2}^1/2 with xi_j^2 =
+                E[beta_j^2] = mu_j^2 + (Phi^-1)_jj under N(Phi^-1 mean_rhs,
+                Phi^-1): eq. cg_sampler_error_metric divided by p^1/2, the
+                form plotted beside the RMS residual in Supplement S8.2; only
+                when Phi and mean_rhs are given (small p).
+    """
+    beta = np.asarray(beta, dtype=np.float64)
+    ref = np.asarray(beta_ref, dtype=np.float64)
+    d = beta - ref
+    nr = float(np.linalg.norm(ref))
+    out = {
+        "rel_l2": float(np.linalg.norm(d) / nr) if nr > 0 else float(np.linalg.norm(d)),
+        "scaled_max": float(np.max(np.abs(d) / np.asarray(scale, dtype=np.float64))),
+    }
+    nz = ref != 0.0
+    out["coord_rel"] = float(np.mean(np.abs(d[nz] / ref[nz]))) if np.any(nz) else 0.0
+    if Phi is not None and mean_rhs is not None:
+        L = cholesky(Phi)
+        mu = sla.cho_solve((L, True), mean_rhs)
+        Linv = sla.solve_triangular(L, np.eye(L.shape[0]), lower=True)
+        var = np.sum(Linv * Linv, axis=0)  # diag(Phi^-1) = diag(L^-T L^-1)
+        xi2 = mu * mu + var
+        out["secmom_rms"] = float(np.sqrt(np.mean(d * d / xi2)))
+    return out
 
 
 def posterior_error_bound(X, omega, lam, tau, b, beta):

@@ -198,6 +198,97 @@ def test_criteria_thresholds():
     assert R.stop_threshold(R.REL_PLAIN, 0.5, b, m, 2) == pytest.approx(2.5)
 
 
+def test_criterion_value_by_hand():
+    """r = (1, 0), b = (0, 4), m = (4, 1):
+    REL_PRECOND  sqrt(<r, m r>) / sqrt(<b, m b>) = 2 / 4 = 1/2;
+    RMS_PRECOND_ABS  sqrt(<r, m r> / p) = sqrt(4 / 2) = sqrt 2;
+    REL_PLAIN  ||r|| / ||b|| = 1/4.
+    (A dropped square root gives 1/4, 2 and 1/16; m in the plain rule 1/2.)
+    The value is sign-invariant and 1 exactly at the threshold."""
+    r, b, m = np.array([1.0, 0.0]), np.array([0.0, 4.0]), np.array([4.0, 1.0])
+    assert R.criterion_value(R.REL_PRECOND, r, b, m) == pytest.approx(0.5, rel=1e-15)
+    assert R.criterion_value(R.RMS_PRECOND_ABS, r, b, m) == pytest.approx(np.sqrt(2.0), rel=1e-15)
+    assert R.criterion_value(R.REL_PLAIN, r, b, m) == pytest.approx(0.25, rel=1e-15)
+    for crit in (R.REL_PRECOND, R.RMS_PRECOND_ABS, R.REL_PLAIN):
+        assert R.criterion_value(crit, -r, b, m) == R.criterion_value(crit, r, b, m)
+    # at the threshold: value == tol  <=>  measure == stop_threshold
+    for crit, meas in ((R.REL_PRECOND, 2.0), (R.RMS_PRECOND_ABS, 2.0), (R.REL_PLAIN, 1.0)):
+        tol = R.criterion_value(crit, r, b, m)
+        assert R.stop_threshold(crit, tol, b, m, 2) == pytest.approx(meas, rel=1e-15)
+
+
+def test_criterion_value_matches_pcg_history():
+    """On a small problem, the value of each rule on the true residual
+    b - Phi beta_k of PCG's iterates equals what PCG records for the
+    recursive residual (||c r_k|| and ||r_k||, scaled as the rule scales
+    them) to rounding, at every k."""
+    P, X = _small(n=120, p=30, rho=0.2, tau=0.8, seed=13)
+    # moderate local scales keep the gap between the recursive and the true
+    # residual (rounding, growing with ||Phi||) far below the values compared
+    lam = np.exp(0.4 * np.random.default_rng(18).standard_normal(P.p))
+    b = np.random.default_rng(14).standard_normal(P.p)
+    res = R.pcg_solve(X, P.omega, lam, P.tau, b, tol=1e-9, keep_iterates=True)
+    m = R.precond_inverse(lam, P.tau)
+    n0, q0 = res.resid_norms[0], res.plain_norms[0]
+    assert res.status == R.STATUS_OK and res.iters > 5
+    for k in range(len(res.iterates)):
+        rt = R.true_residual(X, P.omega, lam, P.tau, b, res.iterates[k])
+        assert R.criterion_value(R.REL_PRECOND, rt, b, m) == pytest.approx(
+            res.resid_norms[k] / n0, rel=1e-6, abs=1e-12)
+        assert R.criterion_value(R.RMS_PRECOND_ABS, rt, b, m) == pytest.approx(
+            res.resid_norms[k] / np.sqrt(P.p), rel=1e-6, abs=1e-12 * n0)
+        assert R.criterion_value(R.REL_PLAIN, rt, b, m) == pytest.approx(
+            res.plain_norms[k] / q0, rel=1e-6, abs=1e-12)
+    # at the stop, the value of the configured rule is at most tol
+    rt = R.true_residual(X, P.omega, lam, P.tau, b, res.beta)
+    assert R.criterion_value(R.REL_PRECOND, rt, b, m) <= 1e-9 * (1 + 1e-3)
+
+
+def test_error_metrics_by_hand():
+    """Phi = [[4, 2], [2, 3]], mean_rhs = (2, 1): mu = (1/2, 0) and
+    diag(Phi^-1) = (3/8, 1/2), so xi^2 = mu^2 + diag(Phi^-1) = (5/8, 1/2).
+    For beta - beta_ref = (0.1, -0.2) with beta_ref = (0.5, 0.25), scale
+    (0.5, 4): rel_l2 = sqrt(0.05) / sqrt(0.3125), scaled_max = max(0.2,
+    0.05), coord_rel = (0.2 + 0.8) / 2 and secmom_rms = sqrt((0.01 / 0.625
+    + 0.04 / 0.5) / 2)."""
+    Phi = np.array([[4.0, 2.0], [2.0, 3.0]])
+    ref = np.array([0.5, 0.25])
+    e = R.error_metrics(ref + np.array([0.1, -0.2]), ref, np.array([0.5, 4.0]), Phi,
+                        np.array([2.0, 1.0]))
+    assert e["rel_l2"] == pytest.approx(np.sqrt(0.05 / 0.3125), rel=1e-14)
+    assert e["scaled_max"] == pytest.approx(0.2, rel=1e-14)
+    assert e["coord_rel"] == pytest.approx(0.5, rel=1e-14)
+    assert e["secmom_rms"] == pytest.approx(np.sqrt((0.01 / 0.625 + 0.04 / 0.5) / 2), rel=1e-14)
+    # zero reference coefficients are left out of the coordinate-wise mean
+    e = R.error_metrics(np.array([0.1, 1.1]), np.array([0.0, 1.0]), np.ones(2))
+    assert e["coord_rel"] == pytest.approx(0.1, rel=1e-14) and "secmom_rms" not in e
+
+
+def test_secmom_error_under_the_residual_bound():
+    """Supplement S4.2, eq. normalized_error_relation_to_precond_resid:
+    ||xi^-1 (beta_k - beta)|| <= max_j(xi_j^-1 tau lambda_j) ||Phi~^-1 r~_k||
+    <= max_j(xi_j^-1 tau lambda_j) ||r~_k|| at every iterate (the smallest
+    eigenvalue of Phi~ is at least one, Theorem 2.4)."""
+    P, X = _small(n=150, p=25, rho=0.25, tau=0.5, seed=15)
+    Phi = R.phi_dense(X, P.omega, P.lam, P.tau)
+    mean_b = R.rhs_mean(X, P.omega, P.z)
+    b = R.rhs_b(X, P.omega, P.z, P.lam, P.tau, np.random.default_rng(16).standard_normal(P.n),
+                np.random.default_rng(17).standard_normal(P.p))
+    exact = R.solve_chol(Phi, b)
+    res = R.pcg_solve(X, P.omega, P.lam, P.tau, b, tol=1e-12, keep_iterates=True)
+    c = P.tau * P.lam
+    mu = R.solve_chol(Phi, mean_b)
+    xi = np.sqrt(mu * mu + np.diag(np.linalg.inv(Phi)))
+    factor = np.max(c / xi)
+    for k in range(len(res.iterates)):
+        e = R.error_metrics(res.iterates[k], exact, c, Phi, mean_b)
+        rt = R.true_residual(X, P.omega, P.lam, P.tau, b, res.iterates[k])
+        norm = e["secmom_rms"] * np.sqrt(P.p)
+        assert norm <= factor * np.linalg.norm(c * rt) * (1 + 1e-9) + 1e-13
+        # and the prior-scaled error sits under the a-posteriori bound
+        assert e["scaled_max"] <= np.linalg.norm(c * rt) * (1 + 1e-9) + 1e-13
+
+
 def test_paper_rms_rule_stops_where_stated():
     """With the paper's rule p^-1/2 ||r~_k|| <= 1e-6 the oracle stops at the
     first k where the recorded preconditioned residual crosses the threshold."""

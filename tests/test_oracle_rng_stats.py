@@ -95,9 +95,28 @@ def test_chi2_cholesky_draws_pass(p):
     P, X, Phi, L, mean_b, mu = _tiny_setup(p)
     rng = np.random.default_rng(100 + p)
     xi = rng.standard_normal((N_DRAWS, p))
-    draws = mu + np.linalg.solve(L.T, xi.T).T
+    draws = R.draw_chol(Phi, mean_b, xi.T).T  # the oracle's own sampler
     res = S.gaussian_tests(S.whiten_beta(draws, mu, L))
     assert S.passes(res), res
+    # one draw at a time is the same sampler
+    for s in (0, 7, N_DRAWS - 1):
+        assert np.allclose(R.draw_chol(Phi, mean_b, xi[s]), draws[s], rtol=1e-14, atol=1e-14)
+
+
+def test_draw_chol_by_hand():
+    """Phi = [[4, 2], [2, 3]] = L L^T with L = [[2, 0], [1, sqrt 2]];
+    mean_rhs = (2, 1) gives mu = Phi^-1 (2, 1) = (1/2, 0); xi = (1, 1) gives
+    L^-T xi = ((1 - 2^-1/2) / 2, 2^-1/2).  And L^-T L^-1 = Phi^-1 =
+    [[3, -2], [-2, 4]] / 8, the covariance of the draws."""
+    Phi = np.array([[4.0, 2.0], [2.0, 3.0]])
+    r2 = np.sqrt(2.0)
+    beta = R.draw_chol(Phi, np.array([2.0, 1.0]), np.array([1.0, 1.0]))
+    assert np.allclose(beta, [0.5 + (1 - 1 / r2) / 2, 1 / r2], rtol=0, atol=1e-15)
+    # the deviation part is linear in xi: columns of L^-T from unit vectors
+    A = R.draw_chol(Phi, np.zeros(2), np.eye(2))
+    assert np.allclose(A @ A.T, np.array([[3.0, -2.0], [-2.0, 4.0]]) / 8, rtol=0, atol=1e-15)
+    assert np.allclose(R.draw_chol(Phi, np.array([2.0, 1.0]), np.zeros(2)), [0.5, 0.0],
+                       rtol=0, atol=1e-15)
 
 
 def _cg_sampler_draws(P, X, seed, drop_eta=False):
