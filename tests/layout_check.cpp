@@ -3,7 +3,8 @@
 // UndefinedBehaviorSanitizer).
 //
 // For a binary X read from a file it builds the tables of both orientations
-// at both value sizes exactly as the library does (build_panels), then runs
+// at both value sizes (and at the K-interleaved entry sizes of shared-design
+// batches) exactly as the library does (build_panels), then runs
 // a lane-by-lane model of the pass kernel's reads over them: every
 // workgroup's panel, every wavefront's chunk list, the loads each lane
 // issues for every window (the stand-in loads of lanes without a group and
@@ -316,7 +317,9 @@ int main(int argc, char** argv) {
     }
   Stats st;
   int64_t bad = 0;
-  for (int elem : {8, 4}) {
+  // 8 and 4: one FP64 or FP32 vector; 16 to 64: the K-interleaved tables of
+  // shared-design batches (K x value size per panel entry)
+  for (int elem : {8, 4, 16, 32, 64}) {
     PanelBuild Br, Bc;
     build_panels(rp, ci, n, p, elem, 256, Br);
     build_panels(cp, ri, p, n, elem, 256, Bc);

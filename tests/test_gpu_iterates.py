@@ -1,0 +1,363 @@
+"""GPU parity of the CG iterates themselves, and of the long-segment kernel
+path, against the oracle.
+
+Why iterates are compared where the oracle is reproducible.  A CG iterate at a
+fixed iteration count is not a continuous function of rounding when the
+prior-preconditioned system is ill-conditioned.  On the n = 2000, p = 500
+workload (condition number of the preconditioned Phi about 1e5) two FP64 runs
+of the oracle that differ only in summation order (rows and columns of X
+permuted) agree to 1e-14 after 3 iterations, 3e-9 after 5 and only
+to 12 % after 8; once both have converged (about 240 iterations) they agree
+to 1e-15 again.  The same holds for a well-conditioned design in a milder
+form (1e-10 at K = 10 for condition number 13).  So the GPU's iterate is
+compared with the oracle's:
+
+* after one and two iterations from a start vector (zero, or an earlier
+  iterate), with tol 0 and max_iter K: the first step exercises alpha and the
+  beta and r updates, the second the direction recurrence.  Where two
+  summation orders of the oracle agree to 1e-12 (every start tried here but
+  the chaotic ones, which are reported) the GPU agrees with the oracle to
+  1e-10 in FP64, norm-wise and in the prior-scaled maximum norm
+  max_j |d beta_j| / (tau lambda_j) (relative to max_j |beta_j| / (tau
+  lambda_j)); the FP32 form agrees to 1e-5 where the orders agree to 1e-14
+  (its rounding is 1e9 times larger, amplified the same way);
+* after K iterations from zero, for every K at which two summation orders of
+  the oracle agree to 1e-12, to 1e-10 (FP64).
+
+The long-segment designs put more than 16,384 entries of one row or column
+of X into one panel of the gathered vector, so that the pass kernels cut the
+segment into pieces whose sums the consumer adds: an all-ones (intercept)
+column over 40,000 and 90,000 rows (FP64 panels of 20,471 rows, FP32 panels
+of 40,943) and a dense row over 20,000 columns.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import paper_1810_12437_amd as pk  # noqa: E402
+import synth  # noqa: E402
+from oracle import philox_ref as H  # noqa: E402
+from oracle import ppcg_ref as R  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def c32(a):
+    return np.float32(a).astype(np.float64)
+
+
+def tdev(a, dt):
+    t = torch.as_tensor(np.asarray(a, dtype=np.float64), device=DEV)
+    return t if dt == pk.F64 else t.float()
+
+
+def add_dense(P, col=None, row=None):
+    """P's design with column `col` and/or row `row` set to all ones."""
+    rows = np.repeat(np.arange(P.n, dtype=np.int64), np.diff(P.row_ptr))
+    cols = P.col_idx.astype(np.int64)
+    extra_r, extra_c = [], []
+    if col is not None:
+        extra_r.append(np.arange(P.n, dtype=np.int64))
+        extra_c.append(np.full(P.n, col, dtype=np.int64))
+    if row is not None:
+        extra_r.append(np.full(P.p, row, dtype=np.int64))
+        extra_c.append(np.arange(P.p, dtype=np.int64))
+    key = np.unique(np.concatenate([rows * P.p + cols] + [r * P.p + c for r, c in
+                                                          zip(extra_r, extra_c)]))
+    r = key // P.p
+    rp = np.zeros(P.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=P.n), out=rp[1:])
+    return synth.Problem(P.name, P.n, P.p, rp, (key - r * P.p).astype(np.int32), P.omega, P.z,
+                         P.lam, P.tau)
+
+
+def long_segment_cases():
+    """(name, problem): segments longer than 16,384 entries in one panel."""
+    return [
+        ("intercept_40k", add_dense(synth.scaled_problem(40000, 300, seed=21, tau=0.02), col=0)),
+        ("intercept_90k", add_dense(synth.scaled_problem(90000, 200, seed=22, tau=0.02), col=0)),
+        ("dense_row_20k", add_dense(synth.scaled_problem(3000, 20000, seed=23, tau=0.02,
+                                                         dmin=1e-3, dmax=2e-2), row=7)),
+    ]
+
+
+def segment_lengths(P):
+    col_counts = np.bincount(P.col_idx, minlength=P.p)
+    row_counts = np.diff(P.row_ptr)
+    return int(col_counts.max()), int(row_counts.max())
+
+
+class Oracle:
+    """The oracle's CG on one system, also run in a second summation order
+    (rows and columns of X permuted, every product and inner product summed
+    in the permuted order) to measure how far rounding alone moves an
+    iterate."""
+
+    def __init__(self, P, d, m, dt=pk.F64):
+        cast = (lambda a: np.asarray(a, np.float64)) if dt == pk.F64 else c32
+        self.om = cast(P.omega)
+        self.d = np.asarray(d, np.float64)
+        self.m = np.asarray(m, np.float64)
+        self.Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+        rng = np.random.default_rng(0)
+        rp, self.cp = rng.permutation(P.n), rng.permutation(P.p)
+        self.Xp = self.Xs[rp][:, self.cp].tocsr()
+        self.omp, self.dp, self.mp = self.om[rp], self.d[self.cp], self.m[self.cp]
+        self.scale = np.sqrt(self.m)
+
+    def mv(self, v):
+        return R.phi_matvec_general(self.Xs, self.om, self.d, v)
+
+    def mv_perm(self, v):
+        return self.Xp.T @ (self.omp * (self.Xp @ v)) + self.dp * v
+
+    def run(self, b, beta0, K):
+        """(the oracle's K iterations from beta0, (spread, scaled spread))."""
+        a = R.pcg(self.mv, b, self.m, beta0, tol=0.0, max_iter=K)
+        cp = self.cp
+        c = R.pcg(self.mv_perm, b[cp], self.mp, None if beta0 is None else beta0[cp], tol=0.0,
+                  max_iter=K)
+        back = np.empty_like(c.beta)
+        back[cp] = c.beta
+        assert a.iters == K or a.status != R.STATUS_NOTCONV
+        return a, self.distance(back, a.beta)
+
+    def distance(self, got, ref):
+        """(norm-wise relative, prior-scaled max relative) distance."""
+        e = R.error_metrics(got, ref, self.scale)
+        top = float(np.max(np.abs(ref) / self.scale))
+        return e["rel_l2"], e["scaled_max"] / (top if top > 0 else 1.0)
+
+
+def shrinkage(P, dt=pk.F64):
+    lam = P.lam if dt == pk.F64 else c32(P.lam)
+    return R.prior_precision(lam, P.tau), R.precond_inverse(lam, P.tau)
+
+
+def gpu_steps(X, P, dt):
+    """K CG iterations (tol 0, max_iter K) on the GPU from beta0 (None:
+    zero) under the shrinkage prior."""
+    def run(b, beta0, K):
+        beta, info = pk.solve(X, tdev(P.omega, dt), tdev(P.lam, dt), P.tau, tdev(b, dt),
+                              beta0=None if beta0 is None else tdev(beta0, dt), tol=0.0,
+                              max_iter=K, refine=0)
+        return beta.double().cpu().numpy(), info
+    return run
+
+
+def check_restart_steps(name, O, gpu, b, starts, dt, steps=(1, 2)):
+    """One and two iterations from each start vector, GPU (gpu(b, beta0, K))
+    against the oracle O."""
+    bb = b if dt == pk.F64 else c32(b)
+    checked = 0
+    for label, beta0 in starts:
+        s0 = None if beta0 is None else (beta0 if dt == pk.F64 else c32(beta0))
+        for K in steps:
+            ref, spread = O.run(bb, s0, K)
+            got, info = gpu(b, beta0, K)
+            # the same count, unless a residual vanished exactly on one side
+            assert info["iters"] <= K and (info["iters"] == ref.iters or info["status"] == pk.OK
+                                           or ref.status == R.STATUS_OK), (name, label, K)
+            err = O.distance(got, ref.beta)
+            gate_spread = 1e-12 if dt == pk.F64 else 1e-14
+            tol = 1e-10 if dt == pk.F64 else 1e-5
+            say(f"   [{name} {'f64' if dt == pk.F64 else 'f32'}] start {label} K={K}: "
+                f"err rel {err[0]:.1e} scaled {err[1]:.1e} (oracle two-order spread "
+                f"{spread[0]:.1e})")
+            if max(spread) <= gate_spread:
+                assert err[0] <= tol and err[1] <= tol, (name, label, K, err)
+                checked += 1
+            elif dt == pk.F64:
+                # chaotic start: only consistency with the oracle's own spread
+                assert err[0] <= 100 * spread[0] + tol, (name, label, K, err, spread)
+    assert checked >= len(steps)  # at least the start from zero
+    return checked
+
+
+def draw_rhs(P, seed=1810, draw_index=0):
+    Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+    eta, delta = H.eta_delta(seed, 0, draw_index, P.n, P.p)
+    return R.rhs_b(Xs, P.omega, P.z, P.lam, P.tau, eta, delta)
+
+
+def oracle_iterates(P, b, Ks):
+    Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+    return [(f"K0={k}", R.pcg_solve(Xs, P.omega, P.lam, P.tau, b, tol=0.0, max_iter=k).beta)
+            for k in Ks]
+
+
+def cases():
+    from tests.test_gpu_parity import structure_cases
+    out = [("c0", synth.make_problem("c0"))]
+    out += [c for c in structure_cases() if c[0] != "one_row"]
+    out += long_segment_cases()
+    return out
+
+
+CASES = cases()
+
+
+@pytest.mark.parametrize("dt", [pk.F64, pk.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("name,P", CASES, ids=[c[0] for c in CASES])
+def test_restart_steps_match_oracle(name, P, dt):
+    """One and two CG iterations from zero and from iterates 5, 20 and 60 of
+    an earlier solve, on every structure case, the n = 2000 workload and the
+    long-segment designs."""
+    say(f"[restart steps] {name} n={P.n} p={P.p} nnz={P.nnz} longest col/row "
+        f"{segment_lengths(P)}")
+    X = pk.Matrix.from_problem(P)
+    b = draw_rhs(P)
+    starts = [("zero", None)] + oracle_iterates(P, b, (5, 20, 60))
+    d, m = shrinkage(P, dt)
+    check_restart_steps(name, Oracle(P, d, m, dt), gpu_steps(X, P, dt), b, starts, dt)
+
+
+@pytest.mark.parametrize("name", ["c0", "column_law", "empties", "intercept_40k"])
+def test_fixed_counts_from_zero_match_oracle(name):
+    """K iterations from zero (tol 0, max_iter K) for K up to twice the count
+    to convergence: wherever two summation orders of the oracle agree to
+    1e-12 the GPU agrees with the oracle to 1e-10 (FP64); elsewhere it is
+    within 100 times the oracle's own spread."""
+    P = dict(CASES)[name]
+    X = pk.Matrix.from_problem(P)
+    b = draw_rhs(P)
+    d, m = shrinkage(P)
+    O = Oracle(P, d, m)
+    conv = R.pcg(O.mv, b, m, tol=1e-12).iters
+    Ks = sorted({1, 2, 3, 4, 5, 8, 12, 20, conv // 2, conv, conv + 20, 2 * conv})
+    gated = 0
+    for K in Ks:
+        ref, spread = O.run(b, None, K)
+        got, info = gpu_steps(X, P, pk.F64)(b, None, K)
+        assert info["iters"] <= K and (info["iters"] == ref.iters or info["status"] == pk.OK
+                                       or ref.status == R.STATUS_OK)
+        err = O.distance(got, ref.beta)
+        say(f"   [{name}] K={K} (converged at {conv}): err {err[0]:.1e}/{err[1]:.1e} "
+            f"spread {spread[0]:.1e}/{spread[1]:.1e}")
+        if max(spread) <= 1e-12:
+            assert max(err) <= 1e-10, (K, err)
+            gated += 1
+        else:
+            assert err[0] <= 100 * spread[0] + 1e-10, (K, err, spread)
+    assert gated >= 4
+
+
+@pytest.mark.parametrize("dt", [pk.F64, pk.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("name,P", CASES[-3:], ids=[c[0] for c in CASES[-3:]])
+def test_long_segment_phi_matvec(name, P, dt):
+    """Phi v over segments cut into pieces (FP64 1e-12, FP32 1e-5 against
+    the oracle on the rounded inputs), two calls bitwise equal."""
+    ncol, nrow = segment_lengths(P)
+    say(f"[long segments] {name}: longest column {ncol}, longest row {nrow}")
+    assert max(ncol, nrow) > 16384
+    X = pk.Matrix.from_problem(P)
+    Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+    v = np.random.default_rng(3).standard_normal(P.p)
+    cast = (lambda a: np.asarray(a, np.float64)) if dt == pk.F64 else c32
+    ref = R.phi_matvec(Xs, cast(P.omega), cast(P.lam), P.tau, cast(v))
+    got = pk.phi_matvec(X, tdev(P.omega, dt), tdev(P.lam, dt), P.tau, tdev(v, dt))
+    again = pk.phi_matvec(X, tdev(P.omega, dt), tdev(P.lam, dt), P.tau, tdev(v, dt))
+    e = float(np.linalg.norm(got.double().cpu().numpy() - ref) / np.linalg.norm(ref))
+    say(f"   {'f64' if dt == pk.F64 else 'f32'} rel err {e:.2e}")
+    assert e <= (1e-12 if dt == pk.F64 else 1e-5)
+    assert torch.equal(got, again)
+
+
+@pytest.mark.parametrize("name,P", CASES[-3:], ids=[c[0] for c in CASES[-3:]])
+def test_long_segment_draw_matches_oracle(name, P):
+    """Draws over the long-segment designs: FP64 at tol 1e-13 against the
+    oracle's CG at the same tolerance (1e-10), the prior-scaled error under
+    the a-posteriori bound, FP32 (refined) against the FP64 oracle (1e-5)."""
+    X = pk.Matrix.from_problem(P)
+    Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+    b = draw_rhs(P, seed=77, draw_index=1)
+    cap = 20 * P.p  # beyond the default p: these systems need more at tol 1e-13
+    ref = R.pcg_solve(Xs, P.omega, P.lam, P.tau, b, tol=1e-13, max_iter=cap)
+    beta, info = pk.draw(X, tdev(P.omega, pk.F64), tdev(P.z, pk.F64), tdev(P.lam, pk.F64), P.tau,
+                         77, 0, 1, tol=1e-13, max_iter=cap)
+    got = beta.cpu().numpy()
+    e = R.error_metrics(got, ref.beta, P.tau * P.lam)
+    bound = R.posterior_error_bound(Xs, P.omega, P.lam, P.tau, b, got)
+    say(f"[long draw] {name}: iters {info['iters']} (oracle {ref.iters}) {e} bound {bound:.2e}")
+    assert info["status"] == pk.OK and ref.status == R.STATUS_OK
+    assert e["rel_l2"] <= 1e-10
+    assert e["scaled_max"] <= bound
+    b32 = R.rhs_b(Xs, c32(P.omega), c32(P.z), c32(P.lam), P.tau,
+                  *H.eta_delta(77, 0, 1, P.n, P.p))
+    ref32 = R.pcg_solve(Xs, c32(P.omega), c32(P.lam), P.tau, b32, tol=1e-13, max_iter=cap)
+    beta32, info32 = pk.draw(X, tdev(P.omega, pk.F32), tdev(P.z, pk.F32), tdev(P.lam, pk.F32),
+                             P.tau, 77, 0, 1, tol=1e-8, max_iter=cap)
+    e32 = float(np.linalg.norm(beta32.double().cpu().numpy() - ref32.beta)
+                / np.linalg.norm(ref32.beta))
+    say(f"   f32 iters {info32['iters']}+{info32['refine_iters']} err {e32:.2e}")
+    assert info32["status"] == pk.OK and e32 <= 1e-5
+
+
+def test_shared_design_long_segments():
+    """Four chains on the 40,000-row intercept design (K = 4 interleaved FP64
+    vectors: panels of 5,117 entries, so the intercept's parts are long
+    chunks that one wavefront sums whole): one and two iterations from zero
+    against the oracle (1e-10), and draws at tol 1e-13 against the
+    single-chain draws (1e-10)."""
+    P = dict(CASES)["intercept_40k"]
+    chains = synth.shared_x_chains(P, 4, seed=31)
+    B = pk.Batch.shared(P.n, P.p, P.row_ptr, P.col_idx, 4, dtype=pk.F64)
+    X = pk.Matrix.from_problem(P)
+    Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+    rng = np.random.default_rng(5)
+    bs = [rng.standard_normal(P.p) for _ in chains]
+    t = lambda a: torch.as_tensor(a, device=DEV)  # noqa: E731
+    for K in (1, 2):
+        betas, infos = B.solve([t(c[0]) for c in chains], [t(c[2]) for c in chains],
+                               [c[3] for c in chains], [t(b) for b in bs], tol=0.0, max_iter=K,
+                               refine=0)
+        for c, (om, z, lam, tau) in enumerate(chains):
+            ref = R.pcg_solve(Xs, om, lam, tau, bs[c], tol=0.0, max_iter=K)
+            e = float(np.linalg.norm(betas[c].cpu().numpy() - ref.beta)
+                      / np.linalg.norm(ref.beta))
+            say(f"[shared long] K={K} chain {c}: iters {infos[c]['iters']} err {e:.1e}")
+            assert infos[c]["iters"] == K and e <= 1e-10
+    n = len(chains)
+    betas, infos = B.draw([t(c[0]) for c in chains], [t(c[1]) for c in chains],
+                          [t(c[2]) for c in chains], [c[3] for c in chains], [44] * n,
+                          list(range(n)), [2] * n, tol=1e-13)
+    for c, (om, z, lam, tau) in enumerate(chains):
+        one, _ = pk.draw(X, t(om), t(z), t(lam), tau, 44, c, 2, tol=1e-13)
+        e = float(torch.linalg.norm(betas[c] - one) / torch.linalg.norm(one))
+        say(f"[shared long] draw chain {c}: iters {infos[c]['iters']} rel diff {e:.1e}")
+        assert infos[c]["status"] == pk.OK and e <= 1e-10
+
+
+def test_f32_refinement_restart_runs_and_meets_the_rule(problem_cache):
+    """The FP32 form at tol 1e-9 with the recursion run to the tolerance
+    itself (loop factor 1): the recursive residual (FP64 r updated with FP32
+    products) reaches the rule while the FP64 true residual does not, so the
+    one refinement restart must run, and after it the FP64 true residual of
+    the FP64 state meets the rule and the FP32 draw returned is within 1e-5
+    of the FP64 oracle's Cholesky solution."""
+    P = problem_cache("c0")
+    X = pk.Matrix.from_problem(P)
+    Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+    for draw_index in (0, 1, 2):
+        beta, info = pk.draw(X, tdev(P.omega, pk.F32), tdev(P.z, pk.F32), tdev(P.lam, pk.F32),
+                             P.tau, 1810, 0, draw_index, tol=1e-9, loop_factor=1.0)
+        eta, delta = H.eta_delta(1810, 0, draw_index, P.n, P.p)
+        b = R.rhs_b(Xs, c32(P.omega), c32(P.z), c32(P.lam), P.tau, eta, delta)
+        exact = R.solve_chol(R.phi_dense(Xs, c32(P.omega), c32(P.lam), P.tau), b)
+        got = beta.double().cpu().numpy()
+        e = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+        say(f"[refine] draw {draw_index}: iters {info['iters']}+{info['refine_iters']} "
+            f"refined {info['refined']} first true/tol {info['resid_true_first']:.2f} "
+            f"final {info['resid_true']:.3f} err {e:.1e}")
+        assert info["refined"] == 1 and info["resid_true_first"] > 1.0
+        # (the rule holds for the FP64 state; the returned FP32 beta carries
+        # its own rounding, about 6e-8 relative, on top)
+        assert info["status"] == pk.OK and info["resid_true"] <= 1.0
+        assert e <= 1e-5

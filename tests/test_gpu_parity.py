@@ -186,6 +186,11 @@ def test_draw_f64_c0_matches_oracle(problem_cache):
         # the truncation error itself, hence the factor 3.
         e_ = rel(got, exact)
         assert e_ <= 3 * rel(ref.beta, exact) + 1e-10
+        # Per coordinate, on the prior scale: max_j |beta_j - exact_j| / (tau
+        # lambda_j) is at most ||tau lambda (b - Phi beta)|| (the smallest
+        # eigenvalue of the preconditioned Phi is at least one, Theorem 2.4).
+        sm = R.error_metrics(got, exact, P.tau * P.lam)["scaled_max"]
+        assert sm <= R.posterior_error_bound(Xs, P.omega, P.lam, P.tau, b, got)
         beta, info = pk.draw(X, t64(P.omega), t64(P.z), t64(P.lam), P.tau, 1810, 0, draw_index,
                              tol=1e-13)
         got = beta.cpu().numpy()
@@ -196,6 +201,8 @@ def test_draw_f64_c0_matches_oracle(problem_cache):
         assert e_ <= 1e-10
         e_ = rel(got, exact)
         assert e_ <= 1e-10
+        sm = R.error_metrics(got, exact, P.tau * P.lam)["scaled_max"]
+        assert sm <= R.posterior_error_bound(Xs, P.omega, P.lam, P.tau, b, got)
 
 
 def test_draw_is_deterministic(problem_cache):
