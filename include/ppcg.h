@@ -55,6 +55,7 @@ extern "C" {
 #define PPCG_ENOTCONV 4   /* max_iter reached; the last iterate is returned           */
 #define PPCG_EBREAKDOWN 5 /* <s, Phi s> <= 0 or non-finite (Phi not positive definite) */
 #define PPCG_ENODEV 6     /* no HIP device                                            */
+#define PPCG_ETOOBIG 7    /* needs more scratch than an entry point that allocates nothing has */
 
 /* Element type of vector arguments (and of the CG iteration's matvecs). */
 #define PPCG_F64 0 /* FP64 vectors and matvecs throughout                               */
@@ -160,6 +161,33 @@ int ppcg_matrix_shape(const ppcg_matrix* X, int64_t* n, int64_t* p, int64_t* nnz
 int ppcg_phi_matvec(const ppcg_matrix* X, const void* omega, const void* lambda,
                     double tau, const void* v, void* out, int32_t dtype,
                     hipStream_t stream);
+
+/*
+ * ppcg_phi_matvec for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result from the same kernels (bitwise equal), with
+ * every intermediate (d = tau^-2 lambda^-2, both passes' per-panel partial
+ * sums and piece sums, the combined X^T u) in a fixed device array of
+ * PPCG_NOALLOC_SCRATCH_BYTES per device that the library holds from its
+ * first use on that device until the process ends, instead of the handle's
+ * workspace (which it does not touch).  The call allocates nothing and
+ * calls no allocating routine; it zero-fills what must start at zero with
+ * kernels (no memset nodes), so it may be captured into a graph.  Scratch
+ * needed, in bytes, each term rounded up to 256: 2 x 8p + sv (P_r n + N_r +
+ * P_c p + N_c + p) with sv = 8 (PPCG_F64) or 4 (PPCG_F32), P_r, P_c the
+ * panels and N_r, N_c (at least 1) the pieces of the row and column tables
+ * of that precision; PPCG_ETOOBIG (nothing enqueued) when that exceeds
+ * PPCG_NOALLOC_SCRATCH_BYTES (e.g. n = 5e5, p = 5e4 needs about 23 MB in
+ * FP64).  Every call on a device shares that device's array: calls that
+ * overlap on one device (two streams, or two threads) race and must be
+ * ordered by the caller.  The handle's device must be the current device
+ * (PPCG_EINVAL otherwise).  Arguments and errors otherwise as
+ * ppcg_phi_matvec; asynchronous on `stream`.
+ */
+#define PPCG_NOALLOC_SCRATCH_BYTES (32u * 1024u * 1024u)
+int ppcg_phi_matvec_noalloc(const ppcg_matrix* X, const void* omega, const void* lambda,
+                            double tau, const void* v, void* out, int32_t dtype,
+                            hipStream_t stream);
 
 /*
  * Writes `count` standard normals of one stream of the counter-based generator

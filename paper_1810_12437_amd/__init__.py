@@ -32,7 +32,7 @@ F64, F32 = 0, 1
 REL_PRECOND, RMS_PRECOND_ABS, REL_PLAIN = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 STREAM_ETA, STREAM_DELTA = 0, 1
-OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENODEV = 0, 1, 2, 3, 4, 5, 6
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENODEV, ETOOBIG = 0, 1, 2, 3, 4, 5, 6, 7
 _SOLVER_STATUS = (OK, ENOTCONV, EBREAKDOWN)
 
 EXPORTED_SYMBOLS = (
@@ -47,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
     "ppcg_moments_update", "ppcg_unshrunk_setup", "ppcg_jacobi_precond",
     "ppcg_switch_create", "ppcg_switch_destroy", "ppcg_switch_state", "ppcg_draw_switch",
-    "ppcg_pg_update", "ppcg_pg_sample", "ppcg_matrix_create_csc",
+    "ppcg_pg_update", "ppcg_pg_sample", "ppcg_matrix_create_csc", "ppcg_phi_matvec_noalloc",
 )
 
 
@@ -109,6 +109,7 @@ def _declare(L):
     L.ppcg_matrix_destroy.argtypes = [_vp]
     L.ppcg_matrix_shape.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
     L.ppcg_phi_matvec.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, _i32, _vp]
+    L.ppcg_phi_matvec_noalloc.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, _i32, _vp]
     L.ppcg_normals.argtypes = [_u64, _u64, _u64, _u64, _i64, _vp, _vp]
     L.ppcg_rhs.argtypes = [_vp, _vp, _vp, _vp, _dbl, _u64, _u64, _u64, _i32, _vp, _vp]
     L.ppcg_solve.argtypes = [_vp, _vp, _vp, _dbl, _vp, _vp, ctypes.POINTER(Options), _vp,
@@ -155,7 +156,8 @@ def _declare(L):
                  "ppcg_phi_diag", "ppcg_warm_start_accumulate", "ppcg_warm_start_vector",
                  "ppcg_moments_update", "ppcg_unshrunk_setup", "ppcg_jacobi_precond",
                  "ppcg_switch_create", "ppcg_switch_destroy", "ppcg_switch_state",
-                 "ppcg_draw_switch", "ppcg_pg_update", "ppcg_pg_sample"):
+                 "ppcg_draw_switch", "ppcg_pg_update", "ppcg_pg_sample",
+                 "ppcg_phi_matvec_noalloc"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -440,6 +442,20 @@ def phi_matvec(X, omega, lam, tau, v):
                                _stream())
     _check(rc, "ppcg_phi_matvec")
     return out
+
+
+def phi_matvec_noalloc(X, omega, lam, tau, v, out):
+    """out = Phi v into the caller's `out` through the entry point that
+    allocates nothing (its scratch is a fixed per-device array); returns
+    the status code (OK, or ETOOBIG when the fixed scratch is too small)."""
+    dt = _dtype_of(v)
+    rc = lib().ppcg_phi_matvec_noalloc(X.handle, _dev(omega, dt, X.n, "omega"),
+                                       _dev(lam, dt, X.p, "lambda"), float(tau),
+                                       _dev(v, dt, X.p, "v"), _dev(out, dt, X.p, "out"), dt,
+                                       _stream())
+    if rc not in (OK, ETOOBIG):
+        raise PPCGError("ppcg_phi_matvec_noalloc", rc)
+    return rc
 
 
 def normals(seed, stream_id, chain, draw_index, count, device="cuda"):

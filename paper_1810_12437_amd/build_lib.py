@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libppcg.so")
 SOURCES = ["ppcg_kernels.hip", "ppcg_host.hip", "ppcg_api.hip", "ppcg_batch.hip",
-           "ppcg_gibbs.hip", "ppcg_pg.hip"]
+           "ppcg_gibbs.hip", "ppcg_pg.hip", "ppcg_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

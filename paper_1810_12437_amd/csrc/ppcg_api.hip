@@ -414,6 +414,7 @@ const char* ppcg_status_string(int status) {
     case PPCG_ENOTCONV: return "not converged within max_iter";
     case PPCG_EBREAKDOWN: return "CG breakdown (<s, Phi s> <= 0 or non-finite)";
     case PPCG_ENODEV: return "no HIP device";
+    case PPCG_ETOOBIG: return "needs more scratch than the fixed array of the entry point that allocates nothing";
     default: return "unknown status";
   }
 }
