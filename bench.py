@@ -14,8 +14,12 @@ pass, timed with HIP events on the solver's stream during the timed draws),
 the general-prior forms on the same draws (prior preconditioner cold and
 warm-started, Jacobi, the adaptive switch), the adjoint form against plain
 solves of the same systems, Gibbs steps with the device
-Polya-Gamma omega update, and the CPU oracle timed on this host as a
-baseline.
+Polya-Gamma omega update, summaries of the other workloads (8 chains on the
+same design, 32 uneven chains, the 200-step sequence at n = 5e5, p = 5e4;
+``--no-forms`` skips them), and the CPU baselines timed on this host: the
+oracle's CG draw (one thread) at n = 1e5, p = 2e4 and at n = 2000, p = 500,
+and the direct Cholesky draw the paper compares with (all BLAS threads; at
+n = 1e5 from a bounded sample), with the host's CPU model and core count.
 
 ``--copy-calibration`` instead times a plain 512 MiB device copy: its
 FETCH_SIZE / WRITE_SIZE counters calibrate the pass kernel's counters.
@@ -46,6 +50,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "Gibbs beta-draws/sec + SpMV-CG HBM GB/s (% peak), n=1e5 p=2e4, rel err<=1e-5"
 SEED = 12437
 COPY_BYTES = 512 << 20
+FORM_STEPS = 5  # timed steps of the shared-design and batched summaries in the default line
 
 # HBM traffic of one X-pass launch (k_panel<double, 1> row pass and
 # k_panel<double, 2> column pass, averaged) on this workload, from two
@@ -81,6 +86,8 @@ def parse():
                     help="skip the prior / warm-start / Jacobi / switch comparison")
     ap.add_argument("--no-gibbs", action="store_true",
                     help="skip the Gibbs steps with the device Polya-Gamma update")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the shared-design, batched and large workloads in the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--form", choices=("single", "batched", "shared", "large"), default="single",
@@ -167,6 +174,32 @@ def check_accuracy(pk, torch, X, P, tol):
     return out
 
 
+def host_info():
+    """The host the CPU baselines ran on: CPU model, logical CPUs, the CPUs
+    this process may use, and the BLAS threads."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": i.get("internal_api"), "threads": i.get("num_threads")}
+                for i in threadpool_info()]
+    except Exception:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable, "blas": blas}
+
+
 def cpu_baseline(P, tol, draws):
     """The oracle as it stands, on this host, one thread: `draws` complete
     draws of the same workload (Prop 2.1's b, then PCG to the same stopping
@@ -190,6 +223,82 @@ def cpu_baseline(P, tol, draws):
                    f"draws (Prop 2.1 b, PCG to relative preconditioned residual {tol:g}; "
                    f"{', '.join(map(str, iters))} iterations) in {el:.1f} s"),
     }
+
+
+def cpu_small_and_direct(P1, tol):
+    """The CPU baselines beside the oracle's CG draw at n = 1e5, p = 2e4:
+
+    * the oracle's CG draw at n = 2000, p = 500 (one thread): median of 5
+      after one warm-up;
+    * the direct Cholesky draw (the standard method the paper compares
+      with, Section 2.1 and Supplement S7.3: Phi = X^T Omega X by SciPy's
+      sparse product, one thread, then LAPACK's Cholesky, the solve for the
+      mean and the triangular solve for the noise with every BLAS thread of
+      this process): at n = 2000, p = 500 in full (median of 5 after one
+      warm-up); at n = 1e5, p = 2e4 from a bounded sample: the sparse
+      product over the first 5,000 rows, scaled by n / 5,000 (its work is a
+      sum over rows), plus the full-size dense factorisation and solves of
+      that sample's Phi with the prior added (the same size and cost as the
+      full one)."""
+    import synth
+    from oracle import philox_ref, ppcg_ref
+
+    from threadpoolctl import threadpool_limits
+
+    out = {}
+    P0 = synth.make_problem("c0")
+    X0 = ppcg_ref.csr_matrix(P0.n, P0.p, P0.row_ptr, P0.col_idx)
+    d0 = ppcg_ref.prior_precision(P0.lam, P0.tau)
+
+    def direct(X, P, d, k):
+        Phi = ppcg_ref.phi_dense_general(X, P.omega, d)
+        xi = np.random.default_rng(k).standard_normal(P.p)
+        return ppcg_ref.draw_chol(Phi, ppcg_ref.rhs_mean(X, P.omega, P.z), xi)
+
+    def oracle_cg(k):
+        eta, delta = philox_ref.eta_delta(SEED, 0, k, P0.n, P0.p)
+        b = ppcg_ref.rhs_b(X0, P0.omega, P0.z, P0.lam, P0.tau, eta, delta)
+        return ppcg_ref.pcg_solve(X0, P0.omega, P0.lam, P0.tau, b, tol=1e-10).iters
+
+    def median_of_5(fn):
+        fn(99)
+        ts = []
+        for k in range(5):
+            t0 = time.perf_counter()
+            fn(k)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    with threadpool_limits(1):
+        t = median_of_5(oracle_cg)
+    out["oracle_cg_c0"] = {"draws_per_s": 1.0 / t, "threads": 1,
+                           "sample": "n=2000 p=500, tol 1e-10, median of 5 after 1 warm-up"}
+    t = median_of_5(lambda k: direct(X0, P0, d0, k))
+    out["direct_cholesky_c0"] = {"draws_per_s": 1.0 / t,
+                                 "sample": "n=2000 p=500, median of 5 after 1 warm-up"}
+    X1 = ppcg_ref.csr_matrix(P1.n, P1.p, P1.row_ptr, P1.col_idx)
+    rows = 5000
+    Xs = X1[:rows]
+    t0 = time.perf_counter()
+    XO = Xs.multiply(P1.omega[:rows, None]).tocsr()
+    G = (Xs.T @ XO).toarray()
+    t_prod = time.perf_counter() - t0
+    del XO
+    G[np.diag_indices_from(G)] += ppcg_ref.prior_precision(P1.lam, P1.tau)
+    xi = np.random.default_rng(5).standard_normal(P1.p)
+    t0 = time.perf_counter()
+    ppcg_ref.draw_chol(G, ppcg_ref.rhs_mean(X1, P1.omega, P1.z), xi)
+    t_chol = time.perf_counter() - t0
+    del G
+    t_draw = t_prod * (P1.n / rows) + t_chol
+    out["direct_cholesky_c1"] = {
+        "draws_per_s": 1.0 / t_draw, "s_per_draw": t_draw,
+        "sparse_product_s": t_prod * (P1.n / rows), "factor_and_solves_s": t_chol,
+        "sample": (f"n=1e5 p=2e4: X^T Omega X over the first {rows} rows in {t_prod:.1f} s "
+                   f"(one thread), scaled by n/{rows}; Cholesky, mean and noise solves of a "
+                   f"{P1.p} x {P1.p} Phi in {t_chol:.1f} s on the BLAS threads"),
+    }
+    return out
 
 
 def precond_forms(pk, torch, P, X, steps, warmup, tol):
@@ -378,41 +487,31 @@ def copy_calibration():
                                            "best_ms": best, "gbps": gbps}}), flush=True)
 
 
-def run_batched(args):
-    import torch
+def batched_summary(pk, torch, steps, warmup, tol, no_f32=False):
+    """32 independent chains of uneven size (n log-uniform [2e4, 2e5], p in
+    [5e3, 4e4], tau in [1e-4, 1e-2], the column law), one batched draw of all
+    chains per step, against the same chains drawn one at a time."""
+    import gc
     from concurrent.futures import ThreadPoolExecutor
 
-    import paper_1810_12437_amd as pk
     import synth
 
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
     workers = max(1, min(16, os.cpu_count() or 1))
     print(f"[bench] generating 32 chains ({workers} processes) ...", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     probs = synth.batched_problems(count=32, workers=workers)
+    t_gen = time.perf_counter() - t0
     nnz = sum(P.nnz for P in probs)
-    print(f"[bench] total nnz {nnz} in {time.perf_counter() - t0:.1f} s; building handles",
+    print(f"[bench] total nnz {nnz} in {t_gen:.1f} s; building handles",
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=4) as ex:
         mats = list(ex.map(pk.Matrix.from_problem, probs))
     t_build = time.perf_counter() - t0
     C = len(probs)
-    out = {
-        "metric": "batched chain-draws/sec, 32 uneven chains",
-        "unit": "chain-draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
-        "config": {
-            "workload": ("32 chains, n log-uniform [2e4, 2e5], p log-uniform [5e3, 4e4], "
-                         "column densities log-uniform [1e-4, 0.2], tau log-uniform [1e-4, 1e-2]; "
-                         f"relative preconditioned residual {args.tol:g}"),
-            "chains": C, "nnz_total": int(nnz), "tol": args.tol, "seed": SEED,
-        },
-        "handle_build_s": t_build,
-    }
     forms = {}
     for name, dtype, dt in (("f64", pk.F64, torch.float64), ("f32", pk.F32, torch.float32)):
-        if name == "f32" and args.no_f32:
+        if name == "f32" and no_f32:
             continue
         B = pk.Batch(mats, dtype=dtype)
         om = [torch.as_tensor(P.omega, device="cuda").to(dt) for P in probs]
@@ -421,36 +520,113 @@ def run_batched(args):
         ta = [P.tau for P in probs]
         seeds = [SEED] * C
         chains = list(range(C))
-        for w in range(args.warmup):
-            B.draw(om, zz, la, ta, seeds, chains, [1000 + w] * C, tol=args.tol)
+        for w in range(warmup):
+            B.draw(om, zz, la, ta, seeds, chains, [1000 + w] * C, tol=tol)
         torch.cuda.synchronize()
-        print(f"[bench] timing batched {name} ({args.steps} steps)", file=sys.stderr, flush=True)
+        print(f"[bench] timing batched {name} ({steps} steps)", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         iters = []
-        for k in range(args.steps):
-            _, infos = B.draw(om, zz, la, ta, seeds, chains, [k] * C, tol=args.tol)
+        for k in range(steps):
+            _, infos = B.draw(om, zz, la, ta, seeds, chains, [k] * C, tol=tol)
             iters.append([i["iters"] + i["refine_iters"] for i in infos])
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         it = np.array(iters, dtype=np.float64)
-        f = {"chain_draws_per_s": C * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+        f = {"chain_draws_per_s": C * steps / el, "ms_per_step": 1e3 * el / steps,
              "cg_iters_mean": float(it.mean()), "cg_iters_max": float(it.max()),
              "cg_iters_min": float(it.min())}
         # the same chains one at a time (single-chain path)
         t0 = time.perf_counter()
         for c in range(C):
-            pk.draw(mats[c], om[c], zz[c], la[c], ta[c], SEED, c, 0, tol=args.tol)
+            pk.draw(mats[c], om[c], zz[c], la[c], ta[c], SEED, c, 0, tol=tol)
         torch.cuda.synchronize()
         f["single_chain_path_chain_draws_per_s"] = C / (time.perf_counter() - t0)
         f["speedup_vs_single_chain_path"] = (f["chain_draws_per_s"] /
                                              f["single_chain_path_chain_draws_per_s"])
         forms[name] = f
         B.close()
-    out["value"] = forms["f64"]["chain_draws_per_s"]
-    out["ms_per_step"] = forms["f64"]["ms_per_step"]
-    out["dtype"] = "f64"
-    out["forms"] = forms
+    for m in mats:
+        m.close()
+    del mats, probs
+    gc.collect()
+    return {"chains": C, "nnz_total": int(nnz), "steps": steps, "generate_s": t_gen,
+            "handle_build_s": t_build, "forms": forms,
+            "workload": ("32 chains, n log-uniform [2e4, 2e5], p log-uniform [5e3, 4e4], "
+                         "column densities log-uniform [1e-4, 0.2], tau log-uniform "
+                         f"[1e-4, 1e-2]; relative preconditioned residual {tol:g}")}
+
+
+def run_batched(args):
+    import torch
+
+    import paper_1810_12437_amd as pk
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    s = batched_summary(pk, torch, args.steps, args.warmup, args.tol, args.no_f32)
+    forms = s["forms"]
+    out = {
+        "metric": "batched chain-draws/sec, 32 uneven chains",
+        "value": forms["f64"]["chain_draws_per_s"],
+        "unit": "chain-draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": forms["f64"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": s["workload"], "chains": s["chains"],
+                   "nnz_total": s["nnz_total"], "tol": args.tol, "seed": SEED},
+        "generate_s": s["generate_s"], "handle_build_s": s["handle_build_s"],
+        "forms": forms,
+    }
     print(json.dumps(out), flush=True)
+
+
+def shared_summary(pk, torch, P, X, steps, warmup, tol, no_f32=False):
+    """8 chains on the design of P (handle X for the single-chain path), each
+    with its own omega, z, lambda, tau and stream; every X pass serves all 8
+    (K = 8 interleaved vectors).  Per form: chain-draws/s over `steps`
+    batched draws against the same chains drawn one at a time."""
+    import synth
+
+    C = 8
+    chains = synth.shared_x_chains(P, C, seed=1815)
+    forms = {}
+    for name, dtype, dt in (("f64", pk.F64, torch.float64), ("f32", pk.F32, torch.float32)):
+        if name == "f32" and no_f32:
+            continue
+        t0 = time.perf_counter()
+        B = pk.Batch.shared(P.n, P.p, P.row_ptr, P.col_idx, C, dtype=dtype)
+        t_build = time.perf_counter() - t0
+        om = [torch.as_tensor(c[0], device="cuda").to(dt) for c in chains]
+        zz = [torch.as_tensor(c[1], device="cuda").to(dt) for c in chains]
+        la = [torch.as_tensor(c[2], device="cuda").to(dt) for c in chains]
+        ta = [c[3] for c in chains]
+        for w in range(warmup):
+            B.draw(om, zz, la, ta, [SEED] * C, list(range(C)), [1000 + w] * C, tol=tol)
+        torch.cuda.synchronize()
+        print(f"[bench] timing shared {name} ({steps} steps)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        iters = []
+        for k in range(steps):
+            _, infos = B.draw(om, zz, la, ta, [SEED] * C, list(range(C)), [k] * C, tol=tol)
+            iters.append([i["iters"] + i["refine_iters"] for i in infos])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        it = np.array(iters, dtype=np.float64)
+        f = {"chain_draws_per_s": C * steps / el, "ms_per_step": 1e3 * el / steps,
+             "cg_iters_mean": float(it.mean()), "cg_iters_max": float(it.max()),
+             "handle_build_s": t_build}
+        t0 = time.perf_counter()
+        for c in range(C):
+            pk.draw(X, om[c], zz[c], la[c], ta[c], SEED, c, 0, tol=tol)
+        torch.cuda.synchronize()
+        f["single_chain_path_chain_draws_per_s"] = C / (time.perf_counter() - t0)
+        f["speedup_vs_single_chain_path"] = (f["chain_draws_per_s"] /
+                                             f["single_chain_path_chain_draws_per_s"])
+        forms[name] = f
+        B.close()
+    return {"chains": C, "steps": steps, "forms": forms,
+            "workload": ("8 chains on one n=1e5 p=2e4 binary X (column densities log-uniform "
+                         "[1e-4, 0.2]); per-chain omega, z, lambda, tau = 1e-3 x exp(U[-1/2, 1/2]); "
+                         f"relative preconditioned residual {tol:g}")}
 
 
 def run_shared(args):
@@ -463,63 +639,24 @@ def run_shared(args):
     print("[bench] generating the n=1e5 p=2e4 design and 8 chains ...", file=sys.stderr,
           flush=True)
     P = synth.make_problem("c1")
-    C = 8
-    chains = synth.shared_x_chains(P, C, seed=1815)
     X = pk.Matrix.from_problem(P)
+    s = shared_summary(pk, torch, P, X, args.steps, args.warmup, args.tol, args.no_f32)
+    forms = s["forms"]
     out = {
         "metric": "shared-design chain-draws/sec, 8 chains, n=1e5 p=2e4",
+        "value": forms["f64"]["chain_draws_per_s"],
         "unit": "chain-draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
-        "config": {
-            "workload": ("8 chains on one n=1e5 p=2e4 binary X (column densities log-uniform "
-                         "[1e-4, 0.2]); per-chain omega, z, lambda, tau = 1e-3 x exp(U[-1/2, 1/2]); "
-                         f"relative preconditioned residual {args.tol:g}"),
-            "chains": C, "nnz": P.nnz, "tol": args.tol, "seed": SEED,
-        },
+        "ms_per_step": forms["f64"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": s["workload"], "chains": s["chains"], "nnz": P.nnz,
+                   "tol": args.tol, "seed": SEED},
+        "forms": forms,
     }
-    forms = {}
-    for name, dtype, dt in (("f64", pk.F64, torch.float64), ("f32", pk.F32, torch.float32)):
-        if name == "f32" and args.no_f32:
-            continue
-        t0 = time.perf_counter()
-        B = pk.Batch.shared(P.n, P.p, P.row_ptr, P.col_idx, C, dtype=dtype)
-        t_build = time.perf_counter() - t0
-        om = [torch.as_tensor(c[0], device="cuda").to(dt) for c in chains]
-        zz = [torch.as_tensor(c[1], device="cuda").to(dt) for c in chains]
-        la = [torch.as_tensor(c[2], device="cuda").to(dt) for c in chains]
-        ta = [c[3] for c in chains]
-        for w in range(args.warmup):
-            B.draw(om, zz, la, ta, [SEED] * C, list(range(C)), [1000 + w] * C, tol=args.tol)
-        torch.cuda.synchronize()
-        print(f"[bench] timing shared {name} ({args.steps} steps)", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        iters = []
-        for k in range(args.steps):
-            _, infos = B.draw(om, zz, la, ta, [SEED] * C, list(range(C)), [k] * C, tol=args.tol)
-            iters.append([i["iters"] + i["refine_iters"] for i in infos])
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        it = np.array(iters, dtype=np.float64)
-        f = {"chain_draws_per_s": C * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
-             "cg_iters_mean": float(it.mean()), "cg_iters_max": float(it.max()),
-             "handle_build_s": t_build}
-        t0 = time.perf_counter()
-        for c in range(C):
-            pk.draw(X, om[c], zz[c], la[c], ta[c], SEED, c, 0, tol=args.tol)
-        torch.cuda.synchronize()
-        f["single_chain_path_chain_draws_per_s"] = C / (time.perf_counter() - t0)
-        f["speedup_vs_single_chain_path"] = (f["chain_draws_per_s"] /
-                                             f["single_chain_path_chain_draws_per_s"])
-        forms[name] = f
-        B.close()
-    out["value"] = forms["f64"]["chain_draws_per_s"]
-    out["ms_per_step"] = forms["f64"]["ms_per_step"]
-    out["dtype"] = "f64"
-    out["forms"] = forms
     print(json.dumps(out), flush=True)
 
 
-def run_large(args):
+def large_summary(pk, torch, steps, warmup, tol):
     """The Gibbs-style sequence on the large design (n = 5e5, p = 5e4, 6.6e8
     non-zeros; tau = 0.05): 200 steps (``--steps``), each with omega and
     lambda redrawn from the config-0 laws (all steps' vectors resident in HBM
@@ -530,13 +667,10 @@ def run_large(args):
     sit in the 256 MB MALL, so the pass rate is an HBM figure.  A 100-
     iteration prior-preconditioned FP64 solve is timed beside it (the prior
     preconditioner does not converge within p iterations on this law)."""
-    import torch
+    import gc
 
-    import paper_1810_12437_amd as pk
     import synth
 
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    steps = args.steps
     t0 = time.perf_counter()
     P = synth.large_problem()
     t_gen = time.perf_counter() - t0
@@ -553,9 +687,9 @@ def run_large(args):
         la_all[k].copy_(torch.as_tensor(la))
     z = torch.as_tensor(P.z, device="cuda").float()
     sw = pk.Switch(P.p, period=100)
-    for w in range(args.warmup):
+    for w in range(warmup):
         d, m = pk.unshrunk_setup(la_all[w % steps], P.tau)
-        sw.draw(X, om_all[w % steps], z, d, SEED, 1, w, precond_inv=m, tol=args.tol)
+        sw.draw(X, om_all[w % steps], z, d, SEED, 1, w, precond_inv=m, tol=tol)
     sw.close()
     sw = pk.Switch(P.p, period=100)
     torch.cuda.synchronize()
@@ -565,7 +699,7 @@ def run_large(args):
     t0 = time.perf_counter()
     for k in range(steps):
         d, m = pk.unshrunk_setup(la_all[k], P.tau)
-        _, info = sw.draw(X, om_all[k], z, d, SEED, 0, k, precond_inv=m, tol=args.tol)
+        _, info = sw.draw(X, om_all[k], z, d, SEED, 0, k, precond_inv=m, tol=tol)
         infos.append(info)
         if k % 100 == 0:
             choices.append(sw.state())
@@ -594,7 +728,7 @@ def run_large(args):
     # the prior preconditioner's passes in FP64, 100 iterations of draw 0
     t = lambda a: torch.as_tensor(a, device="cuda")  # noqa: E731
     X.profile(True)
-    _, info = pk.draw(X, t(P.omega), t(P.z), t(P.lam), P.tau, SEED, 0, 0, tol=args.tol,
+    _, info = pk.draw(X, t(P.omega), t(P.z), t(P.lam), P.tau, SEED, 0, 0, tol=tol,
                       max_iter=100)
     torch.cuda.synchronize()
     st = X.stats()
@@ -609,18 +743,35 @@ def run_large(args):
              "bytes_per_launch": 0.5 * (c64 + s64)}
     prior["pass_frac"] = prior["pass_gbps"] / HBM_PEAK_GBPS
     prior["pass_frac_of_copy"] = prior["pass_gbps"] / copy_gbps
+    del X, om_all, la_all, z
+    gc.collect()
+    return {"generate_s": t_gen, "handle_build_s": t_build, "sequence": seq,
+            "prior_fp64_100_iterations": prior, "nnz": P.nnz, "n": P.n, "p": P.p,
+            "tau": P.tau,
+            "workload": ("n=5e5 p=5e4 binary X, column densities log-uniform "
+                         "[1e-4, 0.2], tau=0.05, omega ~ Gamma(1, 0.25) + 0.01 and "
+                         "lambda ~ half-Cauchy redrawn per step; FP32 vectors with the FP64 "
+                         "refinement restart; adaptive prior/Jacobi preconditioner; "
+                         f"relative residual {tol:g}")}
+
+
+def run_large(args):
+    import torch
+
+    import paper_1810_12437_amd as pk
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    s = large_summary(pk, torch, args.steps, args.warmup, args.tol)
+    seq = s["sequence"]
     out = {
         "metric": "Gibbs-style sequence draws/sec, n=5e5 p=5e4, FP32 + FP64 refinement",
-        "value": seq["draws_per_s"], "unit": "draws/s", "n_gpus": 1, "steps": steps,
+        "value": seq["draws_per_s"], "unit": "draws/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": seq["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": ("n=5e5 p=5e4 binary X, column densities log-uniform "
-                                "[1e-4, 0.2], tau=0.05, omega ~ Gamma(1, 0.25) + 0.01 and "
-                                "lambda ~ half-Cauchy redrawn per step; adaptive "
-                                f"prior/Jacobi preconditioner; relative residual {args.tol:g}"),
-                   "nnz": P.nnz, "n": P.n, "p": P.p, "tau": P.tau},
-        "generate_s": t_gen, "handle_build_s": t_build,
-        "sequence": seq, "prior_fp64_100_iterations": prior,
+        "config": {"workload": s["workload"], "nnz": s["nnz"], "n": s["n"], "p": s["p"],
+                   "tau": s["tau"]},
+        "generate_s": s["generate_s"], "handle_build_s": s["handle_build_s"],
+        "sequence": seq, "prior_fp64_100_iterations": s["prior_fp64_100_iterations"],
     }
     print(json.dumps(out), flush=True)
 
@@ -737,10 +888,27 @@ def main():
         print(f"[bench] Gibbs steps with the Polya-Gamma update ({args.warmup}+{args.steps} "
               "per form)", file=sys.stderr, flush=True)
         out["gibbs_step"] = gibbs_forms(pk, torch, P, X, args.steps, args.warmup, args.tol)
+    if not args.no_forms:
+        # the other workloads, summarised in the same line (fewer timed steps
+        # than their own --form runs, except the large sequence, whose 200
+        # steps are the workload)
+        print("[bench] shared-design form (8 chains)", file=sys.stderr, flush=True)
+        out["shared_form"] = shared_summary(pk, torch, P, X, FORM_STEPS, 1, args.tol,
+                                            args.no_f32)
+        print("[bench] batched form (32 uneven chains)", file=sys.stderr, flush=True)
+        out["batched_form"] = batched_summary(pk, torch, FORM_STEPS, 1, args.tol, args.no_f32)
+        print("[bench] large form (n=5e5 p=5e4, 200-step sequence)", file=sys.stderr,
+              flush=True)
+        out["large_form"] = large_summary(pk, torch, 200, 2, args.tol)
     if not args.no_cpu:
         print(f"[bench] CPU oracle sample ({args.cpu_draws} draws)", file=sys.stderr,
               flush=True)
-        out["cpu_baseline"] = cpu_baseline(P, args.tol, args.cpu_draws)
+        cb = cpu_baseline(P, args.tol, args.cpu_draws)
+        cb["host"] = host_info()
+        print("[bench] CPU oracle at n=2000 p=500 and the direct Cholesky draw",
+              file=sys.stderr, flush=True)
+        cb.update(cpu_small_and_direct(P, args.tol))
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
