@@ -340,9 +340,9 @@ static int build_handle(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
     auto job = [&](int q) {
       const int elem = (q / 2) == 0 ? 8 : 4;
       if (q % 2 == 0)
-        build_panels(rp, ci, n, p, elem, ncu, Bt[q]);
+        build_panels(rp, ci, n, p, elem, ncu, Bt[q], /*compact=*/true);
       else
-        build_panels(cp, ri, p, n, elem, ncu, Bt[q]);
+        build_panels(cp, ri, p, n, elem, ncu, Bt[q], /*compact=*/true);
     };
     bool threaded = true;
     std::vector<std::thread> th;

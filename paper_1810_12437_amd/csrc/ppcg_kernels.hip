@@ -269,10 +269,14 @@ __device__ __forceinline__ void stream_open(const PanelPass& t, const ChunkDesc&
 
 // Issues the loads of the cursor's window into one ring slot and advances.
 // Bit `bit` of `have` tells whether this lane has a group in that window.
+// CMP: compact groups (ppcg_layout.h), one 16-byte load per lane (b unused);
+// otherwise a group's two halves.
+template <bool CMP>
 __device__ __forceinline__ void stream_issue(const PanelPass& t, int c_end, int lane,
                                              StreamLoad& L, u16x8& a, u16x8& b, int32_t& slot,
                                              uint32_t& have, int bit) {
   constexpr int H = kPV / 2;
+  constexpr int GW = CMP ? H : kPV;  // words per group in the stream
   int64_t ea = L.last_base, eb = L.last_base;
   int32_t si = t.no_slot;
   bool h = false, first = false;
@@ -283,25 +287,26 @@ __device__ __forceinline__ void stream_issue(const PanelPass& t, int c_end, int 
     if (L.kind == kChunkPacked) {
       const uint64_t m = L.k == 0 ? L.vm0 : L.k == 1 ? L.vm1 : L.k == 2 ? L.vm2 : L.vm3;
       h = ((m >> lane) & 1ull) != 0;
-      w0 = L.base + (int64_t)L.pre * kPV;
+      w0 = L.base + (int64_t)L.pre * GW;
       ng = __popcll(m);
       r = bits_below(m);
       L.pre += ng;
     } else {
-      w0 = L.base + (int64_t)L.k * kPC;
+      w0 = L.base + (int64_t)L.k * 64 * GW;
       const int64_t left = (L.clen - (int64_t)L.k * kPC) / kPV;
       ng = left < 64 ? (int)left : 64;
       r = lane;
       h = lane < ng;
     }
     ea = h ? w0 + (int64_t)r * H : w0;
-    eb = h ? w0 + (int64_t)(ng + r) * H : w0;
+    eb = (h && !CMP) ? w0 + (int64_t)(ng + r) * H : w0;
     si = L.sidx;
     first = L.k == 0;
     if (++L.k == L.windows && ++L.c < c_end) stream_open(t, read_desc(t.chunks, L.c), L.c, lane, L);
   }
   a = __builtin_nontemporal_load(gview(reinterpret_cast<const u16x8*>(t.idx + ea)));
-  b = __builtin_nontemporal_load(gview(reinterpret_cast<const u16x8*>(t.idx + eb)));
+  if constexpr (!CMP) b = __builtin_nontemporal_load(gview(reinterpret_cast<const u16x8*>(t.idx + eb)));
+  (void)eb;
   // the chunk's output slot rides with its first window only
   if (first) slot = gview(t.seg_out)[si];
   have = (have & ~(1u << bit)) | ((h ? 1u : 0u) << bit);
@@ -355,6 +360,41 @@ __device__ __forceinline__ void gather_add16(const T* xl, const u16x8& a, const 
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] += s[r];
   }
+}
+
+// Adds this lane's compact group (ppcg_layout.h) to acc: its first index
+// and the running sums of its byte differences give its kCGroup panel-local
+// indices, their gathers are all in flight before a pairwise sum, and the c
+// pads (copies of the last entry) are taken off again with one fused
+// multiply-add.
+template <typename T>
+__device__ __forceinline__ void gather_cmp(const T* xl, const u16x8& a, T& acc) {
+  const u32x4 d = __builtin_bit_cast(u32x4, a);
+  uint32_t e[kCGroup];
+  e[0] = d[0] & 0xffffu;
+  const uint32_t pads = (d[0] >> 16) & 0xffu;
+  e[1] = e[0] + (d[0] >> 24);
+#pragma unroll
+  for (int w = 1; w < 4; ++w) {
+    e[4 * w - 2] = e[4 * w - 3] + (d[w] & 0xffu);
+    e[4 * w - 1] = e[4 * w - 2] + ((d[w] >> 8) & 0xffu);
+    e[4 * w] = e[4 * w - 1] + ((d[w] >> 16) & 0xffu);
+    e[4 * w + 1] = e[4 * w] + (d[w] >> 24);
+  }
+  const uint32_t l0 = __builtin_amdgcn_readfirstlane(lds_addr(xl));
+  T v[16];
+#pragma unroll
+  for (int k = 0; k < kCGroup; ++k) v[k] = lds_load<T>(e[k] * (uint32_t)sizeof(T) + l0);
+  const T last = v[kCGroup - 1];
+#pragma unroll
+  for (int w = 1; w < 8; w *= 2)
+#pragma unroll
+    for (int j = 0; j + w < kCGroup; j += 2 * w) v[j] += v[j + w];
+  // v[0]: entries 0..7, v[8]: entries 8..13
+  if constexpr (sizeof(T) == 8)
+    acc += __builtin_fma(-(double)pads, last, v[0] + v[8]);
+  else
+    acc += __builtin_fmaf(-(float)pads, last, v[0] + v[8]);
 }
 
 // acc[r] += (cond ? DPP move of acc[r] : 0) for every vector.
@@ -683,7 +723,8 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       ld.last_base = 0;
     }
 #pragma unroll
-    for (int q = 0; q < kRing; ++q) stream_issue(t, c_end, lane, ld, ra[q], rb[q], rs[q], rh, q);
+    for (int q = 0; q < kRing; ++q)
+      stream_issue<K == 1>(t, c_end, lane, ld, ra[q], rb[q], rs[q], rh, q);
   };
 
   // The panel of the gathered vector(s), assembled once per workgroup; entry
@@ -843,9 +884,14 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
             }
           }
         }
-        if ((rh >> q) & 1u) gather_add16<T, K>(xl, ra[q], rb[q], acc);
+        if ((rh >> q) & 1u) {
+          if constexpr (K == 1)
+            gather_cmp<T>(xl, ra[q], acc[0]);
+          else
+            gather_add16<T, K>(xl, ra[q], rb[q], acc);
+        }
       }
-      stream_issue(t, c_end, lane, ld, ra[q], rb[q], rs[q], rh, q);
+      stream_issue<K == 1>(t, c_end, lane, ld, ra[q], rb[q], rs[q], rh, q);
       if (live && ++k == ck_windows(cinfo)) {
         finish_chunk<T, K, dotting>(cinfo, csm, acc, slot, scl, cfirst, lane, part_out, piece_out,
                                     out_scale, sd, p2acc);

@@ -15,6 +15,7 @@ constexpr int kRing = 4;               // windows a pass wavefront has in flight
 constexpr int kPLongWin = 16;          // most windows of a long chunk
 constexpr int kPLongMax = kPLongWin * kPC;  // longest segment one wavefront sums whole
 constexpr int kPanelBytes = 160 * 1024 - 64;  // LDS for the gathered panel (+ zero slot)
+constexpr int kPLongGroups = kPLongWin * 64;  // most groups one wavefront sums whole
 // (after the pass, the same LDS holds the workgroup's partial-sum reduction)
 
 // Relative work of the wavefronts of a pass workgroup by rank.  Wavefront q
@@ -28,24 +29,34 @@ inline double wave_weight(int q) { return kWaveRankWeight[(q % kPWaves) / 4]; }
 
 enum ChunkKind { kChunkPacked = 0, kChunkLong = 1, kChunkPiece = 2 };
 
+// Compact groups (the tables of one gathered vector per pass): a group is
+// 16 bytes, read by its lane with one 16-byte load: its first panel-local
+// index (bytes 0-1), its pad count c (byte 2) and 13 one-byte differences
+// (bytes 3-15) give indices e_0..e_13 of at most kCGroup real entries, any
+// two consecutive ones at most 255 apart (a segment's run is cut into as
+// many groups as that takes).  The c pads repeat the last real index
+// (difference 0), and the summing lane takes c times that entry off again.
+constexpr int kCGroup = 14;  // entries per compact group
+
 // One chunk of an orientation's index stream, read by one wavefront.
 //
 // Packed chunk: up to 64 lanes x kPR windows.  Each segment of the chunk owns
-// a contiguous lane range (a slice) for the whole chunk: its groups of kPV
-// elements go to its lanes kPR at a time (group j on lane l0 + j / kPR in
-// window j % kPR), so a lane only ever sums elements of one segment.  Bit l
-// of vm[k] is set when lane l has a group in window k; the ng groups of
-// window k follow those of the windows before it, stored as halves: the first
-// kPV / 2 entries of each group in lane order, then the second halves (the
-// lane of rank r reads entries r kPV/2 and (ng + r) kPV/2 of the window).  Bit
+// a contiguous lane range (a slice) for the whole chunk: its groups go to
+// its lanes kPR at a time (group j on lane l0 + j / kPR in window j % kPR),
+// so a lane only ever sums elements of one segment.  Bit l of vm[k] is set when lane l has a
+// group in window k; the ng groups of window k follow those of the windows
+// before it: compact groups in lane order (the lane of rank r reads group r),
+// kPV-index groups stored as halves: the first kPV / 2 entries of each group
+// in lane order, then the second halves (the lane of rank r reads entries
+// r kPV/2 and (ng + r) kPV/2 of the window).  Bit
 // l of sm is set when lane l starts a slice (lanes after the last segment
 // form one idle slice).
 //
 // Long chunk: one segment (or, for a piece, a part of one) laid out as
-// consecutive windows of 64 groups (the last one fewer), each stored as
-// halves the same way; vm[0] holds its padded element count.
+// consecutive windows of 64 groups (the last one fewer), each stored the
+// same way; vm[0] holds its group count times kPV.
 struct alignas(64) ChunkDesc {
-  int64_t base;      // first element of the chunk in the index stream
+  int64_t base;      // first 16-bit word of the chunk in the index stream
   uint64_t vm[kPR];  // see above
   uint64_t sm;
   int32_t first;     // packed: first seg_out entry; long: its seg_out entry; piece: its id

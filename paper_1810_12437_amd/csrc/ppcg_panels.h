@@ -43,6 +43,7 @@ inline bool crosses(int l0, int w, int a) { return l0 <= a && a + 1 < l0 + w; }
 struct Entry {
   int64_t a, e, g;  // element range, groups
   int32_t slot;     // panel * out_dim + segment
+  int64_t g0;       // compact tables: the entry's first group in the group starts
 };
 
 inline int chunk_cost(const ChunkDesc& d) {
@@ -142,8 +143,15 @@ inline void spread_window(uint16_t* const* grp, const int* lanes, int ngroups, i
 // windows (in proportion to wave_weight), the last chunk of a share built
 // with fewer windows (from the shortest entries when the longest do not fit
 // in fewer) to end on the share.
+//
+// With `compact` (tables of one gathered vector) groups are the compact
+// 16-byte groups of ppcg_layout.h: up to kCGroup consecutive entries at most
+// 255 apart, a segment's run being cut into as many groups as that takes;
+// otherwise (K interleaved vectors) groups are kPV 16-bit indices padded
+// with the zero index W and stored as halves.
 inline void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& gidx,
-                         int64_t out_dim, int64_t gdim, int elem, int ncu, PanelBuild& B) {
+                         int64_t out_dim, int64_t gdim, int elem, int ncu, PanelBuild& B,
+                         bool compact = false) {
   using detail::Entry;
   B = PanelBuild();
   B.gdim = gdim;
@@ -154,12 +162,42 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
   B.W = (int32_t)((gdim + B.npanels - 1) / B.npanels);
   const uint16_t sentinel = (uint16_t)B.W;
   const int64_t packed_max = 64 * kPR;  // groups
+  std::vector<int64_t> gstart;  // compact: first element of every group
 
   auto append_group = [&](int64_t a, int64_t e, int64_t glo) {
     // elements [a, e) (at most kPV) as one padded group
     int64_t q = a;
     for (; q < e; ++q) B.idx.push_back((uint16_t)(gidx[q] - glo));
     for (; q < a + kPV; ++q) B.idx.push_back(sentinel);
+  };
+  // group j of entry en as one compact group: first index, pad count, the
+  // differences (0 for the pads, which repeat the last index)
+  auto append_cgroup = [&](const Entry& en, int64_t j, int64_t glo) {
+    const int64_t a = gstart[en.g0 + j];
+    const int64_t e = j + 1 < en.g ? gstart[en.g0 + j + 1] : en.e;
+    uint8_t by[16];
+    const int64_t i0 = gidx[a] - glo;
+    by[0] = (uint8_t)(i0 & 0xff);
+    by[1] = (uint8_t)(i0 >> 8);
+    by[2] = (uint8_t)(kCGroup - (e - a));
+    for (int k = 1; k < kCGroup; ++k) {
+      const int64_t q = a + k;
+      by[k + 2] = q < e ? (uint8_t)(gidx[q] - gidx[q - 1]) : 0;
+    }
+    for (int w = 0; w < 8; ++w) B.idx.push_back((uint16_t)(by[2 * w] | (by[2 * w + 1] << 8)));
+  };
+  // compact: cuts the run [a, e) into groups
+  auto cut_groups = [&](int64_t a, int64_t e) {
+    int64_t q = a;
+    while (q < e) {
+      gstart.push_back(q);
+      int n = 1;
+      ++q;
+      while (q < e && n < kCGroup && gidx[q] - gidx[q - 1] <= 255) {
+        ++n;
+        ++q;
+      }
+    }
   };
 
   // 1. entries of every panel
@@ -174,7 +212,13 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
         const int64_t end = off[sgm + 1];
         while (e < end && gidx[e] < hi) ++e;
         if (e > a) {
-          ent[k].push_back({a, e, (e - a + kPV - 1) / kPV, (int32_t)((int64_t)k * out_dim + sgm)});
+          Entry en{a, e, (e - a + kPV - 1) / kPV, (int32_t)((int64_t)k * out_dim + sgm), 0};
+          if (compact) {
+            en.g0 = (int64_t)gstart.size();
+            cut_groups(a, e);
+            en.g = (int64_t)gstart.size() - en.g0;
+          }
+          ent[k].push_back(en);
           cur[sgm] = e;
         }
       }
@@ -192,10 +236,15 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
     for (int32_t i = 0; i < (int32_t)ent[k].size(); ++i) {
       const Entry& en = ent[k][i];
       if (en.g > packed_max) {
-        const int64_t len = en.e - en.a;
-        for (int64_t o = 0; o < len; o += kPLongMax) {
-          const int64_t ng = (std::min<int64_t>(o + kPLongMax, len) - o + kPV - 1) / kPV;
-          pwin[k] += (ng + 63) / 64;
+        if (compact) {
+          for (int64_t o = 0; o < en.g; o += kPLongGroups)
+            pwin[k] += (std::min<int64_t>(o + kPLongGroups, en.g) - o + 63) / 64;
+        } else {
+          const int64_t len = en.e - en.a;
+          for (int64_t o = 0; o < len; o += kPLongMax) {
+            const int64_t ng = (std::min<int64_t>(o + kPLongMax, len) - o + kPV - 1) / kPV;
+            pwin[k] += (ng + 63) / 64;
+          }
         }
       } else {
         P.order.push_back(i);
@@ -263,21 +312,27 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
     // long entries: least loaded wavefront first
     for (const Entry& en : ent[k]) {
       if (en.g <= packed_max) continue;
-      const int64_t len = en.e - en.a;
-      const bool pieces = len > kPLongMax;
+      const int64_t len = compact ? en.g : en.e - en.a;  // groups or elements
+      const int64_t step = compact ? kPLongGroups : kPLongMax;
+      const bool pieces = len > step;
       if (!pieces) B.seg_out.push_back(en.slot);
       const int32_t p_first = B.npieces;
-      for (int64_t o = en.a; o < en.e; o += kPLongMax) {
-        const int64_t oe = std::min<int64_t>(o + kPLongMax, en.e);
+      for (int64_t o = 0; o < len; o += step) {
+        const int64_t oe = std::min<int64_t>(o + step, len);
         ChunkDesc d{};
         d.base = (int64_t)B.idx.size();
-        const int64_t ng = (oe - o + kPV - 1) / kPV;
+        const int64_t ng = compact ? oe - o : (oe - o + kPV - 1) / kPV;
         d.vm[0] = (uint64_t)(ng * kPV);
         const int win = (int)((ng + 63) / 64);
         d.first = pieces ? B.npieces++ : (int32_t)B.seg_out.size() - 1;
         d.seg = en.slot % out_dim;
         d.info = chunk_info(win, pieces ? kChunkPiece : kChunkLong, 0, 0, 0, 1);
-        for (int64_t q = o; q < oe; q += kPV) append_group(q, std::min<int64_t>(q + kPV, oe), glo);
+        if (compact) {
+          for (int64_t j = o; j < oe; ++j) append_cgroup(en, j, glo);
+        } else {
+          for (int64_t q = en.a + o; q < en.a + oe; q += kPV)
+            append_group(q, std::min<int64_t>(q + kPV, en.a + oe), glo);
+        }
         const int q = least_loaded();
         lists[q].push_back(d);
         load[q] += win;
@@ -320,8 +375,12 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
             const int64_t j = (int64_t)i * R + kw;
             if (j >= en.g) continue;
             d.vm[kw] |= 1ull << (l0s[s] + i);
-            const int64_t q = en.a + j * kPV;
-            append_group(q, std::min<int64_t>(q + kPV, en.e), glo);
+            if (compact) {
+              append_cgroup(en, j, glo);
+            } else {
+              const int64_t q = en.a + j * kPV;
+              append_group(q, std::min<int64_t>(q + kPV, en.e), glo);
+            }
           }
         }
         if (d.vm[kw]) nw = kw + 1;
@@ -377,8 +436,9 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
     }
   }
 
-  // 5. bank-spread order within the groups of every window
-  {
+  // 5. bank-spread order within the groups of every window (the compact
+  // groups' order is their positions' order)
+  if (!compact) {
     uint16_t* grp[64];
     int lanes[64];
     const uint16_t sentinel = (uint16_t)B.W;
@@ -412,8 +472,9 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
 
   // 6. each window's groups stored as halves: the first kPV / 2 entries of
   // every group in lane order, then the second halves (one 16-byte load per
-  // lane then reads a contiguous block of the window)
-  {
+  // lane then reads a contiguous block of the window); compact groups are
+  // already one 16-byte block each
+  if (!compact) {
     std::vector<uint16_t> tmp;
     auto split = [&](int64_t at, int ng) {
       tmp.assign(B.idx.begin() + at, B.idx.begin() + at + (int64_t)ng * kPV);

@@ -3,8 +3,9 @@
 // UndefinedBehaviorSanitizer).
 //
 // For a binary X read from a file it builds the tables of both orientations
-// at both value sizes (and at the K-interleaved entry sizes of shared-design
-// batches) exactly as the library does (build_panels), then runs
+// at both value sizes (compact groups, as the library's one-vector tables)
+// and at the K-interleaved entry sizes of shared-design batches (16-bit
+// indices as halves) exactly as the library does (build_panels), then runs
 // a lane-by-lane model of the pass kernel's reads over them: every
 // workgroup's panel, every wavefront's chunk list, the loads each lane
 // issues for every window (the stand-in loads of lanes without a group and
@@ -23,6 +24,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <climits>
 #include <memory>
 #include <string>
 #include <vector>
@@ -105,11 +107,13 @@ void scan(int64_t (&acc)[64], uint64_t sm, int nrow, int b15, int b31) {
 
 struct Stats {
   int64_t packed = 0, longc = 0, piece = 0, segs = 0, pieces = 0, nwg = 0, panels = 0;
+  int64_t cgroups = 0;  // compact groups decoded
 };
 
 // The model of one orientation: gathered vector x (gdim), outputs out_dim.
 // Returns the consumer's totals.
-std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x, Stats& st) {
+std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x, Stats& st,
+                              bool compact) {
   const int64_t out_dim = B.out_dim;
   // device tables (as uploaded: the index stream at least kPV long, a
   // trailing -1 output slot)
@@ -140,6 +144,29 @@ std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x
     // the panel in LDS, entry W zero
     std::vector<int64_t> xl((size_t)B.W + 1, 0);
     for (int64_t j = 0; j < wlen; ++j) xl[j] = x[g0 + j];
+    // one compact group read by a lane at word ea: first index, pad count,
+    // differences; the sum of its entries less the pads' copies of the last
+    auto cgroup = [&](int64_t ea) {
+      ++st.cgroups;
+      uint8_t by[16];
+      for (int e = 0; e < 8; ++e) {
+        const uint16_t wv = idx.at(ea + e, "idx");
+        by[2 * e] = (uint8_t)(wv & 0xff);
+        by[2 * e + 1] = (uint8_t)(wv >> 8);
+      }
+      const int pads = by[2];
+      CHECK(pads < kCGroup, "pad count %d", pads);
+      int64_t ix = by[0] | (by[1] << 8), sum = 0;
+      for (int e = 0; e < kCGroup; ++e) {
+        if (e > 0) ix += by[e + 2];
+        CHECK(ix >= 0 && ix < wlen, "index %lld outside the panel's %lld values", (long long)ix,
+              (long long)wlen);
+        CHECK(e < kCGroup - pads || by[e + 2] == 0 || e == 0, "pad %d moves the index", e);
+        sum += (ix >= 0 && ix <= B.W) ? xl[ix] : 0;
+      }
+      sum -= (int64_t)pads * ((ix >= 0 && ix <= B.W) ? xl[ix] : 0);
+      return sum;
+    };
     // ownership of the panel's entries (the direction update's slices)
     const int64_t o0 = wg_s0.at(w, "wg_s0"), o1 = wg_s1.at(w, "wg_s1");
     CHECK(o0 >= g0 && o1 <= g0 + wlen && o0 <= o1, "slice [%lld, %lld) of panel %d",
@@ -171,6 +198,17 @@ std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x
             const uint64_t m = D.vm[k];
             const int ng = popc(m);
             CHECK(ng > 0, "empty window %d of a packed chunk", k);
+            if (compact) {
+              const int64_t w0 = D.base + pre * (kPV / 2);
+              for (int l = 0; l < 64; ++l) {
+                const bool h = (m >> l) & 1ull;
+                const int64_t ea = h ? w0 + (int64_t)below(m, l) * (kPV / 2) : w0;
+                const int64_t v = cgroup(ea);
+                if (h) acc[l] += v;
+              }
+              pre += ng;
+              continue;
+            }
             const int64_t w0 = D.base + pre * kPV;
             for (int l = 0; l < 64; ++l) {
               const bool h = (m >> l) & 1ull;
@@ -205,9 +243,18 @@ std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x
                 (long long)clen);
           CHECK(R == (int)((clen / kPV + 63) / 64), "long windows");
           for (int k = 0; k < R; ++k) {
-            const int64_t w0 = D.base + (int64_t)k * kPC;
             const int64_t left = (clen - (int64_t)k * kPC) / kPV;
             const int ng = left < 64 ? (int)left : 64;
+            if (compact) {
+              const int64_t w0 = D.base + (int64_t)k * 64 * (kPV / 2);
+              for (int l = 0; l < 64; ++l) {
+                const bool h = l < ng;
+                const int64_t v = cgroup(h ? w0 + (int64_t)l * (kPV / 2) : w0);
+                if (h) acc[l] += v;
+              }
+              continue;
+            }
+            const int64_t w0 = D.base + (int64_t)k * kPC;
             for (int l = 0; l < 64; ++l) {
               const bool h = l < ng;
               const int64_t ea = h ? w0 + (int64_t)l * (kPV / 2) : w0;
@@ -321,10 +368,12 @@ int main(int argc, char** argv) {
   // shared-design batches (K x value size per panel entry)
   for (int elem : {8, 4, 16, 32, 64}) {
     PanelBuild Br, Bc;
-    build_panels(rp, ci, n, p, elem, 256, Br);
-    build_panels(cp, ri, p, n, elem, 256, Bc);
-    const std::vector<int64_t> a = run_pass(Br, v, st);
-    const std::vector<int64_t> b = run_pass(Bc, u, st);
+    // compact groups in the one-vector tables, as the library builds them
+    const bool compact = elem <= 8;
+    build_panels(rp, ci, n, p, elem, 256, Br, compact);
+    build_panels(cp, ri, p, n, elem, 256, Bc, compact);
+    const std::vector<int64_t> a = run_pass(Br, v, st, compact);
+    const std::vector<int64_t> b = run_pass(Bc, u, st, compact);
     for (int64_t i = 0; i < n; ++i)
       if (a[i] != xv[i]) {
         if (bad < 10)
@@ -342,9 +391,10 @@ int main(int argc, char** argv) {
   }
   printf("{\"n\": %lld, \"p\": %lld, \"nnz\": %lld, \"packed\": %lld, \"long\": %lld, "
          "\"piece_chunks\": %lld, \"pieces\": %lld, \"segments\": %lld, \"workgroups\": %lld, "
-         "\"panels\": %lld, \"mismatches\": %lld, \"failed_checks\": %d}\n",
+         "\"panels\": %lld, \"compact_groups\": %lld, \"mismatches\": %lld, "
+         "\"failed_checks\": %d}\n",
          (long long)n, (long long)p, (long long)nnz, (long long)st.packed, (long long)st.longc,
          (long long)st.piece, (long long)st.pieces, (long long)st.segs, (long long)st.nwg,
-         (long long)st.panels, (long long)bad, g_fail);
+         (long long)st.panels, (long long)st.cgroups, (long long)bad, g_fail);
   return (bad == 0 && g_fail == 0) ? 0 : 1;
 }

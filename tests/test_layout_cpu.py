@@ -5,8 +5,10 @@ for both orientations of X at both value sizes and runs a lane-by-lane model
 of the pass kernel's reads over them (every window's loads, the stand-in
 loads of idle lanes and of steps past a wavefront's end, the segmented lane
 sums of packed chunks, the whole-wavefront sums of long chunks and of the
-pieces of segments longer than one wavefront sums whole, and the consumer's
-total over panels and pieces).  Integer values make every sum exact, so the
+pieces of segments longer than one wavefront sums whole, the decode of the
+one-vector tables' compact groups (a first index, a pad count and byte
+differences; every index inside the panel) and the consumer's total over
+panels and pieces).  Integer values make every sum exact, so the
 model's X v and X^T u must equal the direct products element by element.
 The program is built with AddressSanitizer and UndefinedBehaviorSanitizer,
 so a read outside a table is reported by the sanitizer as well as by the
@@ -141,7 +143,7 @@ def test_oracle_size_and_ragged_designs(checker, tmp_path, problem_cache):
     assert st["mismatches"] == 0 and st["packed"] > 0
     P = synth.scaled_problem(4001, 903, seed=6)
     st = _run(checker, tmp_path, P.n, P.p, P.row_ptr, P.col_idx)
-    assert st["mismatches"] == 0
+    assert st["mismatches"] == 0 and st["compact_groups"] > 0
     rng = np.random.default_rng(34)
     M = rng.random((900, 300)) < 0.1
     M[:, ::7] = False
@@ -150,4 +152,22 @@ def test_oracle_size_and_ragged_designs(checker, tmp_path, problem_cache):
     rp = np.zeros(901, dtype=np.int64)
     np.cumsum(np.bincount(rows, minlength=900), out=rp[1:])
     st = _run(checker, tmp_path, 900, 300, rp, cols.astype(np.int32))
+    assert st["mismatches"] == 0
+
+
+def test_compact_groups_of_the_column_law(checker, tmp_path):
+    """A column-law design at n = 30,000, p = 6,000 (densities down to 1e-4,
+    so runs with differences beyond 255 cut groups short) and a design of
+    very short columns beside a dense one: the compact groups reproduce X v
+    and X^T u exactly."""
+    P = synth.scaled_problem(30000, 6000, seed=35)
+    st = _run(checker, tmp_path, P.n, P.p, P.row_ptr, P.col_idx)
+    assert st["mismatches"] == 0 and st["compact_groups"] > 0
+    n, p = 300, 21000
+    rng = np.random.default_rng(36)
+    cols = [np.sort(rng.choice(n, size=int(rng.integers(1, 5)), replace=False))
+            for _ in range(p)]
+    cols[0] = np.arange(n)
+    rp, ci = _csr_from_columns(n, p, cols)
+    st = _run(checker, tmp_path, n, p, rp, ci)
     assert st["mismatches"] == 0
