@@ -63,9 +63,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "a436701aa39adddad2bf11be19da5a62cba9beb4389d00851570067e1f6ffc44",
+    "sources_sha256": "ea4a4d972bd7b718faa8f808506febc3ccc36899402a6d3d2dd2f9bd1e225730",
     # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
-    "bytes_per_launch": 118772695,
+    "bytes_per_launch": 80457677,
 }
 
 
