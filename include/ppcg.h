@@ -91,7 +91,12 @@ typedef struct ppcg_options {
   int32_t check_every;/* host convergence check period in iterations (0: default 16);
                          a batch queued when the decay of the rule measure
                          predicts the end within one period is shortened to
-                         the predicted remainder plus one iteration          */
+                         the predicted remainder plus one iteration.  The
+                         first batch of a solve phase (first solve or
+                         refinement restart) runs to 2 iterations short of
+                         the same handle's previous phase of that kind and
+                         precision, with 3 more queued behind it, when the
+                         handle has one; results do not depend on batching */
   double loop_factor; /* the recursion runs to loop_factor * tol before the FP64
                          check (0: default, 0.5 for F32 and 1 for F64)         */
   int32_t no_graph;   /* batched loops: 0 (default) replays each check batch as a
@@ -415,7 +420,8 @@ int ppcg_solve_backward(const ppcg_matrix* X, const void* omega,
  * and w -> X^T w, the products Section 2.2 says dominate each iteration's
  * cost).  With `enable` != 0 the handle has the dispatch of both passes of one
  * iteration in every fourth convergence-check batch of a solve phase,
- * starting with its first (the batch's middle iteration, when it runs)
+ * starting with its first (iteration check_every / 2 of the batch, when the
+ * batch is longer than that and the iteration runs)
  * stamp HIP events on the caller's stream and accumulates their elapsed
  * times: a sample of the loop's launches, since event-stamped dispatches
  * leave the device idle for microseconds each.  Enabling resets the totals.  Host-only bookkeeping; PPCG_EINVAL

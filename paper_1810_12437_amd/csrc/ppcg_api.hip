@@ -81,12 +81,15 @@ int sync_scal(ppcg_matrix* X, hipStream_t st) {
 
 // Runs CG iterations until the device reports done; returns via h_sc[0].
 // The host checks the device's flag after each batch of check_every
-// iterations (fewer near the predicted end, see below).  From the second
-// check on the next batch is normally already
-// queued when the host waits for a batch's flag (read back into the other
-// pinned slot), so the device does not idle while the host checks.
+// iterations (fewer near the predicted end, see below).  The next batch is
+// normally already queued when the host waits for a batch's flag (read
+// back into the other pinned slot), so the device does not idle while the
+// host checks.  `phase` (0: first solve, 1: refinement restart) selects the
+// iteration count of the handle's previous phase of that kind, which sizes
+// the first batch (see below).
 template <typename T>
-int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t st) {
+int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
+             hipStream_t st) {
   const int ti = prec_index<T>();
   T* s = Bufs<T>::s(X);
   const int32_t* done = &X->sc->done;
@@ -109,9 +112,10 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
   dot.p2 = X->p2[ti];
   const int32_t n1 = X->rows[ti].pass.nwg, n2 = X->cols[ti].pass.nwg;
   const bool prof = X->profile != 0;
-  // Profiling times both passes of one iteration (the middle one) in every
-  // kProfileEvery-th batch: event-stamped dispatches leave the device idle
-  // for several microseconds each, so few iterations carry them.
+  // Profiling times both passes of one iteration (check_every / 2 into the
+  // batch) in every kProfileEvery-th batch longer than that, the first
+  // included: event-stamped dispatches leave the device idle for several
+  // microseconds each, so few iterations carry them.
   constexpr int kProfileEvery = 4;
   const int sample = o.check_every / 2;
   while (prof && X->ev.size() < 8) {
@@ -173,7 +177,8 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
   // (The measure's decay is irregular, so a wider margin saves nothing: a
   // replay of the rule on FP64 convergence histories at n = 1e5, p = 2e4
   // gave 12 iterations after the stop per draw against 16 with full batches
-  // and 14 with 1.25 times the remainder plus two.)
+  // and 14 with 1.25 times the remainder plus two.)  The first prediction
+  // compares the first batch's end with the measure the start left (slot 2).
   auto ratio = [&](int slot) {
     const DevScal& h = X->h_sc[slot];
     return h.loop2 > 0.0 ? h.meas / h.loop2 : 0.0;
@@ -188,22 +193,32 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, hipStream_t
     const int nb = (int)std::ceil(left) + 1;
     return nb < full ? nb : full;
   };
+  // A sequence of draws on one handle (a Gibbs sampler's) repeats its
+  // iteration counts closely, so the first batch runs to kHintShort short
+  // of the previous phase's count, with a batch of kHintTail queued behind
+  // it: the first check then comes near the end, the device keeps working
+  // while the host makes it, and the remainder is sized by the prediction.
+  // Without a count the first batch is one period, checked with nothing
+  // queued behind it (a short solve then runs no launches after its stop).
+  constexpr int kHintShort = 2, kHintTail = 3;
+  const int32_t hint = X->iter_hint[phase][ti];
+  int first = full;
+  if (hint > 0) first = std::max(1, std::min(hint - kHintShort, o.max_iter));
   bool fin = false;
-  int rc = enqueue(0, full);
-  if (!rc) rc = check(0, fin);
-  if (rc || fin) return rc;
-  double m_prev = ratio(0);
-  int cur = 1;
-  if ((rc = enqueue(cur, full))) return rc;
-  bool ahead = true;
-  int next = full;
+  int rc = enqueue(0, first);
+  if (rc) return rc;
+  double m_prev = ratio(2);
+  int cur = 0;
+  bool ahead = hint > 0;
+  int next = kHintTail;
   for (;;) {
     if (ahead && (rc = enqueue(cur ^ 1, next))) return rc;
     if ((rc = check(cur, fin))) return rc;
     if (fin) {
       // a batch queued ahead exits launch by launch; the scalars no longer change
       if (ahead) PPCG_TRY_HIP(hipStreamSynchronize(st));
-      X->h_sc[0] = X->h_sc[cur];
+      if (cur != 0) X->h_sc[0] = X->h_sc[cur];
+      X->iter_hint[phase][ti] = X->h_sc[0].iters;
       return PPCG_OK;
     }
     const double m = ratio(cur);
@@ -236,8 +251,8 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
   const double loop_factor =
       o.loop_factor > 0.0 ? o.loop_factor : ((sizeof(T) == 4) ? 0.5 : 1.0);
   PPCG_TRY_HIP(launch_cg_start(w, 0, X->b64, qx0, X->d, X->m, X->beta64, X->r64, X->z64, X->p,
-                             o.tol, o.criterion, o.max_iter, loop_factor, st));
-  int rc = run_loop<T>(X, omegaT, o, st);
+                             o.tol, o.criterion, o.max_iter, loop_factor, st, &X->h_sc[2]));
+  int rc = run_loop<T>(X, omegaT, o, 0, st);
   if (rc) return rc;
   ppcg_info inf{};
   inf.status = X->h_sc->status;
@@ -261,8 +276,9 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
       // One refinement: restart CG from the FP64 true residual
       // b - Phi beta (qx64 holds the product part of the current beta).
       PPCG_TRY_HIP(launch_cg_start(w, 1, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, X->z64,
-                             X->p, o.tol, o.criterion, o.max_iter, loop_factor, st));
-      rc = run_loop<T>(X, omegaT, o, st);
+                             X->p, o.tol, o.criterion, o.max_iter, loop_factor, st,
+                             &X->h_sc[2]));
+      rc = run_loop<T>(X, omegaT, o, 1, st);
       if (rc) return rc;
       inf.refined = 1;
       inf.refine_iters = X->h_sc->iters;
@@ -379,11 +395,11 @@ static int build_handle(ppcg_matrix** out, int64_t n, int64_t p, int64_t nnz,
             X->mem.alloc(&X->sc, 1) == hipSuccess;
   if (!ok) return fail(PPCG_ENOMEM);
   if (hipMemset(X->sc, 0, sizeof(DevScal)) != hipSuccess) return fail(PPCG_EHIP);
-  if (hipHostMalloc(reinterpret_cast<void**>(&X->h_sc), 2 * sizeof(DevScal), 0) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&X->h_sc), 3 * sizeof(DevScal), 0) != hipSuccess) {
     X->h_sc = nullptr;
     return fail(PPCG_ENOMEM);
   }
-  std::memset(X->h_sc, 0, 2 * sizeof(DevScal));
+  std::memset(X->h_sc, 0, 3 * sizeof(DevScal));
   for (hipEvent_t& e : X->chk)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(PPCG_EHIP);
   if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);

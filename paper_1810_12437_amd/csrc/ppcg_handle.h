@@ -64,8 +64,12 @@ struct ppcg_matrix {
   double *p1[2] = {}, *p2[2] = {};        // workgroup partials of the passes, per table
   double* part = nullptr;
   ppcg::DevScal* sc = nullptr;
-  ppcg::DevScal* h_sc = nullptr;  // pinned host mirror: [0] the result, [0..1] check slots
+  ppcg::DevScal* h_sc = nullptr;  // pinned host mirror: [0] the result, [0..1] check slots,
+                                  // [2] the scalars a start left
   hipEvent_t chk[2] = {};         // one per check slot: that batch's flags are on the host
+  // CG iterations of the last solve phase, [phase: 0 first, 1 refinement][table]: the
+  // first check batch of the next such phase is sized from it (0: none yet)
+  int32_t iter_hint[2][2] = {{0, 0}, {0, 0}};
   // pass timing (ppcg_matrix_profile)
   int profile = 0;
   std::vector<hipEvent_t> ev;  // 4 per iteration of a check batch

@@ -248,10 +248,13 @@ hipError_t launch_phi_finish(const T* qx, const double* d, const T* v, int64_t p
 // mode 1: restart from the FP64 true residual of the current beta (keeps the
 //         thresholds);
 // mode 2: true-residual check only (no state change; writes true_meas, true_rm).
+// Modes 0 and 1 also copy the new scalars to `snap` when it is not null (a
+// pinned host slot: the host's first convergence check reads the starting
+// rule measure there).
 hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
                            const double* d, const double* m, double* beta, double* r,
                            double* z, int64_t p, double tol, int criterion, int max_iter,
-                           double loop_factor, hipStream_t st);
+                           double loop_factor, hipStream_t st, DevScal* snap = nullptr);
 
 // After the column pass: <s, Phi s> from the passes' workgroup partials
 // (fixed order), alpha = rho / <s, Phi s>; q = qx + d .* s with qx from the

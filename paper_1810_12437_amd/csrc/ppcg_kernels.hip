@@ -1444,6 +1444,15 @@ static inline unsigned red_grid(int64_t p) {
 }
 
 
+// The scalars copied word by word to snap by one thread, after that
+// thread's own writes to them (so its loads see them).
+__device__ __forceinline__ void snapshot_scal(const DevScal* sc, DevScal* snap) {
+  static_assert(sizeof(DevScal) % 8 == 0, "DevScal is copied in 8-byte words");
+  const uint64_t* a = reinterpret_cast<const uint64_t*>(sc);
+  uint64_t* b = reinterpret_cast<uint64_t*>(snap);
+  for (int i = 0; i < (int)(sizeof(DevScal) / 8); ++i) b[i] = a[i];
+}
+
 // Mode 1 restarts only a run that ended well but whose FP64 true residual
 // misses the rule; any other run is left as it is.
 __device__ __forceinline__ bool restart_wanted(const DevScal* sc) {
@@ -1455,7 +1464,7 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
                                               const double* m, double* beta, double* r,
                                               double* z, int64_t p, double tol, int criterion,
                                               int max_iter, double loop_factor, VGrid g,
-                                              int zes = 1) {
+                                              int zes = 1, DevScal* snap = nullptr) {
   if (mode == 1 && !restart_wanted(w.sc)) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // <r,Mr>, <r,r>, <b,Mb>, <b,b>
   for (int64_t j = (int64_t)g.bid * kWG + threadIdx.x; j < p; j += (int64_t)g.nblk * kWG) {
@@ -1514,16 +1523,8 @@ __device__ __forceinline__ void cg_start_body(VecWork w, int mode, const double*
       sc->status = kStatBreakdown;
       sc->done = 1;
     }
+    if (snap) snapshot_scal(sc, snap);
   }
-}
-
-// The scalars copied word by word to snap by one thread, after that
-// thread's own writes to them (so its loads see them).
-__device__ __forceinline__ void snapshot_scal(const DevScal* sc, DevScal* snap) {
-  static_assert(sizeof(DevScal) % 8 == 0, "DevScal is copied in 8-byte words");
-  const uint64_t* a = reinterpret_cast<const uint64_t*>(sc);
-  uint64_t* b = reinterpret_cast<uint64_t*>(snap);
-  for (int i = 0; i < (int)(sizeof(DevScal) / 8); ++i) b[i] = a[i];
 }
 
 // One CG step after the two passes (see launch_cg_step).  p1 / p2 hold the
@@ -1650,9 +1651,9 @@ __global__ __launch_bounds__(kWG) void k_cg_start(VecWork w, int mode, const dou
                                                   const double* m, double* beta, double* r,
                                                   double* z, int64_t p, double tol,
                                                   int criterion, int max_iter,
-                                                  double loop_factor) {
+                                                  double loop_factor, DevScal* snap) {
   cg_start_body(w, mode, b, qx64, d, m, beta, r, z, p, tol, criterion, max_iter, loop_factor,
-                own_grid());
+                own_grid(), 1, snap);
 }
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_cg_step(VecWork w, const T* s, Combine<T> qsrc,
@@ -1675,9 +1676,9 @@ __global__ __launch_bounds__(kWG) void k_cg_step_pf(VecWork w, const T* s, Combi
 hipError_t launch_cg_start(VecWork w, int mode, const double* b, const double* qx64,
                            const double* d, const double* m, double* beta, double* r,
                            double* z, int64_t p, double tol, int criterion, int max_iter,
-                           double loop_factor, hipStream_t st) {
+                           double loop_factor, hipStream_t st, DevScal* snap) {
   hipLaunchKernelGGL(k_cg_start, dim3(red_grid(p)), dim3(kWG), 0, st, w, mode, b, qx64, d, m,
-                     beta, r, z, p, tol, criterion, max_iter, loop_factor);
+                     beta, r, z, p, tol, criterion, max_iter, loop_factor, snap);
   return hipGetLastError();
 }
 template <typename T>

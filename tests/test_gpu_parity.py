@@ -217,22 +217,29 @@ def test_draw_is_deterministic(problem_cache):
 def test_profile_samples_leave_draw_unchanged(problem_cache):
     """Pass timing samples one iteration in every fourth check batch: the draw
     is the same bits with it on, and the sampled launches are counted and
-    timed."""
+    timed.  A handle's second draw runs its first batch to two iterations
+    short of the first draw's count (with three queued behind it): that
+    batch is the only one sampled."""
     P = problem_cache("c0")
-    X = pk.Matrix.from_problem(P)
-    a, ia = pk.draw(X, t64(P.omega), t64(P.z), t64(P.lam), P.tau, 7, 2, 5, tol=1e-10,
-                    check_every=4)
+    args = (t64(P.omega), t64(P.z), t64(P.lam), P.tau, 7, 2, 5)
+    a, ia = pk.draw(pk.Matrix.from_problem(P), *args, tol=1e-10, check_every=4)
+    X = pk.Matrix.from_problem(P)  # no earlier solve: batches of 4 from the start
     X.profile(True)
-    b, ib = pk.draw(X, t64(P.omega), t64(P.z), t64(P.lam), P.tau, 7, 2, 5, tol=1e-10,
-                    check_every=4)
+    b, ib = pk.draw(X, *args, tol=1e-10, check_every=4)
     st = X.stats()
-    X.profile(False)
     say(f"[profile] iters={ib['iters']} stats={st}")
     assert torch.equal(a, b) and ia["iters"] == ib["iters"]
     # iteration 2 of batches 0, 4, 8, ... (4 iterations each) that reached it
     want = sum(1 for b in range(0, ib["iters"]) if b % 4 == 0 and 4 * b + 2 < ib["iters"])
     assert st["csr_launches"] == want and st["csc_launches"] == want
     assert st["csr_ms"] > 0.0 and st["csc_ms"] > 0.0
+    c, ic = pk.draw(X, *args, tol=1e-10, check_every=4)
+    st2 = X.stats()
+    X.profile(False)
+    say(f"[profile] second draw iters={ic['iters']} stats={st2}")
+    assert torch.equal(a, c) and ic["iters"] == ia["iters"]
+    assert st2["csr_launches"] == want + 1 and st2["csc_launches"] == want + 1
+    assert st2["csr_ms"] > st["csr_ms"] and st2["csc_ms"] > st["csc_ms"]
 
 
 @pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
