@@ -464,10 +464,12 @@ int ppcg_batch_create(ppcg_batch** out, int32_t nchains, const ppcg_matrix* cons
 
 /*
  * A batch of nchains (1..8) chains on ONE design X (given as for
- * ppcg_matrix_create; copied).  Each X pass reads X's indices once for all
- * chains: the chains' vectors are interleaved in groups of K = 2, 4 or 8
- * (the next power of two) and a panel of the gathered vectors holds K values
- * per entry.  Each chain's omega, z, lambda, tau, b and random stream are its
+ * ppcg_matrix_create; copied).  Each X pass reads X's indices once for a
+ * group of K chains: the group's vectors are interleaved and a panel of the
+ * gathered vectors holds K values per entry.  K is 2 for up to two chains,
+ * else 4 for PPCG_F64 (five to eight chains run as two groups, one pass of
+ * each per CG step; a group whose chains have all stopped skips its passes)
+ * and 4 or 8 (the next power of two, one group) for PPCG_F32.  Each chain's omega, z, lambda, tau, b and random stream are its
  * own (ppcg_chain), so the chains' Phi differ and their CG runs are
  * independent (a chain that has converged keeps its result while the
  * others iterate).  Results agree with the single-chain calls to the solver

@@ -106,15 +106,19 @@ struct ppcg_batch {
   hipGraphExec_t gexec[2] = {};
   int64_t g_version = -1;
   int32_t g_every = 0, g_elem = 0;
-  // shared form: every chain on one design, K interleaved vectors per pass
+  // shared form: every chain on one design, K interleaved vectors per pass,
+  // in G groups of K chains (chain c is slot c % K of group c / K); each
+  // group's arrays follow the previous group's, and the groups' passes run
+  // one after the other through the same tables and partial buffers
   bool shared = false;
-  int32_t K = 1;
+  int32_t K = 1, G = 1;
   int64_t n = 0, p = 0;
   ppcg::Orient srows[2], scols[2];  // K-wide tables: [0] FP64, [1] FP32
-  double *y_K = nullptr, *om64_K = nullptr, *beta_K = nullptr;  // [dim][K]
-  double *z_K = nullptr, *d_K = nullptr;                         // [p][K]
-  double *p1_K = nullptr, *p2_K = nullptr;                       // [nwg][K]
-  void *omT_K = nullptr, *s_K = nullptr;                         // [dim][K], dtype
+  double *y_K = nullptr, *om64_K = nullptr, *beta_K = nullptr;  // [G][dim][K]
+  double *z_K = nullptr, *d_K = nullptr;                         // [G][p][K]
+  double *p1_K = nullptr, *p2_K = nullptr;                       // [G][nwg][K]
+  void *omT_K = nullptr, *s_K = nullptr;                         // [G][dim][K] / [G][2][p][K]
+  void* q_K = nullptr;  // [G][p][K], dtype: X^T u of the loop's column pass, summed over panels
 };
 
 namespace {
@@ -245,17 +249,18 @@ int build_vec_jobs(ppcg_batch* B) {
     if (B->shared) {
       // s, z and the pass partials interleaved over the chains; q from the
       // K-wide column pass
-      J.s = reinterpret_cast<T*>(B->s_K) + c;
-      J.sstride = B->p * B->K;
-      J.es = B->K;
-      J.z = B->z_K + c;
-      J.zes = B->K;
-      J.p1 = B->p1_K + c;
-      J.p2 = B->p2_K + c;
-      J.pstride = B->K;
+      const int64_t g = c / B->K, r = c % B->K, pK = B->p * B->K;
       J.n1 = B->srows[ti].pass.nwg;
       J.n2 = B->scols[ti].pass.nwg;
-      J.qsrc = comb_k<T>(B->scols[ti], B->K, c, nullptr);
+      J.s = reinterpret_cast<T*>(B->s_K) + g * 2 * pK + r;
+      J.sstride = pK;
+      J.es = B->K;
+      J.z = B->z_K + g * pK + r;
+      J.zes = B->K;
+      J.p1 = B->p1_K + g * J.n1 * B->K + r;
+      J.p2 = B->p2_K + g * J.n2 * B->K + r;
+      J.pstride = B->K;
+      J.qsrc = comb_all<T>(reinterpret_cast<const T*>(B->q_K) + g * pK + r, B->K);
     }
     for (int32_t b = 0; b < J.nblk; ++b) {
       bj.push_back(c);
@@ -376,46 +381,61 @@ int set_loop_chains(ppcg_batch* B, const std::vector<char>& act) {
 }
 
 // Shared form: row pass u = omega .* (X s) and column pass X^T u for the K
-// interleaved vectors of the loop's dtype, skipped once every chain is done.
+// interleaved vectors of the loop's dtype, group by group, each group's
+// launches skipped once all its chains are done.
 template <typename T>
 int shared_loop_passes(ppcg_batch* B, int parity, hipStream_t st) {
   const int ti = prec_index<T>();
   const Orient& ro = B->srows[ti];
   const Orient& co = B->scols[ti];
-  const T* om = reinterpret_cast<const T*>(B->omT_K);
   const int dstride = (int)(sizeof(DevScal) / sizeof(int32_t));
-  DirIn<T> dir{};
-  dir.z = B->z_K;
-  dir.s = reinterpret_cast<T*>(B->s_K);
-  dir.sstride = B->p * B->K;
-  dir.d = B->d_K;
-  dir.sc = B->sc;
-  dir.scstride = 1;
-  dir.p1 = B->p1_K;
-  DotOut<T> dot{};
-  dot.s = reinterpret_cast<const T*>(B->s_K);
-  dot.sstride = B->p * B->K;
-  dot.p2 = B->p2_K;
-  PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, ro.pass, Combine<T>{},
-                                      reinterpret_cast<T*>(ro.part),
-                                      reinterpret_cast<T*>(ro.piece),
-                                      rows_direct(ro) ? om : nullptr, &B->sc[0].done, dstride,
-                                      st, &dir, nullptr, parity));
-  PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, co.pass,
-                                      comb_k<T>(ro, B->K, 0, rows_direct(ro) ? nullptr : om),
-                                      reinterpret_cast<T*>(co.part),
-                                      reinterpret_cast<T*>(co.piece), nullptr, &B->sc[0].done,
-                                      dstride, st, nullptr, &dot, parity));
+  const int64_t K = B->K, pK = B->p * K;
+  const int64_t n1 = ro.pass.nwg, n2 = co.pass.nwg;
+  for (int64_t g = 0; g < B->G; ++g) {
+    const T* om = reinterpret_cast<const T*>(B->omT_K) + g * B->n * K;
+    T* sg = reinterpret_cast<T*>(B->s_K) + g * 2 * pK;
+    const int32_t* done = &B->sc[g * K].done;
+    DirIn<T> dir{};
+    dir.z = B->z_K + g * pK;
+    dir.s = sg;
+    dir.sstride = pK;
+    dir.d = B->d_K + g * pK;
+    dir.sc = B->sc + g * K;
+    dir.scstride = 1;
+    dir.p1 = B->p1_K + g * n1 * K;
+    DotOut<T> dot{};
+    dot.s = sg;
+    dot.sstride = pK;
+    dot.p2 = B->p2_K + g * n2 * K;
+    PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, ro.pass, Combine<T>{},
+                                        reinterpret_cast<T*>(ro.part),
+                                        reinterpret_cast<T*>(ro.piece),
+                                        rows_direct(ro) ? om : nullptr, done, dstride, st, &dir,
+                                        nullptr, parity));
+    PPCG_TRY_HIP(launch_panel_pass_k<T>(B->K, co.pass,
+                                        comb_k<T>(ro, B->K, 0, rows_direct(ro) ? nullptr : om),
+                                        reinterpret_cast<T*>(co.part),
+                                        reinterpret_cast<T*>(co.piece), nullptr, done, dstride,
+                                        st, nullptr, &dot, parity));
+    // q for the group's chains at once, read whole lines (the per-chain step
+    // reads it back with stride K from one array instead of from every
+    // panel's)
+    PPCG_TRY_HIP(launch_combine_k<T>(comb_k<T>(co, B->K, 0, nullptr), B->K, B->p,
+                                     reinterpret_cast<T*>(B->q_K) + g * pK, done, dstride, st));
+  }
   return PPCG_OK;
 }
 
-// Shared form: src_c (FP64, one per chain) interleaved into dst [dim][K].
+// Shared form: src_c (FP64, one per chain) interleaved into dst [G][dim][K].
 template <typename T>
 int interleave(ppcg_batch* B, double* const* src_of_chain, int64_t dim, T* dst,
                hipStream_t st) {
-  VecPtrs v{};
-  for (int32_t c = 0; c < B->nch; ++c) v.p[c] = src_of_chain[c];
-  PPCG_TRY_HIP(launch_interleave<T>(v, B->nch, B->K, dim, dst, st));
+  for (int32_t g = 0; g < B->G; ++g) {
+    VecPtrs v{};
+    const int32_t c0 = g * B->K, nc = std::min(B->K, B->nch - c0);
+    for (int32_t r = 0; r < nc; ++r) v.p[r] = src_of_chain[c0 + r];
+    PPCG_TRY_HIP(launch_interleave<T>(v, nc, B->K, dim, dst + (int64_t)g * dim * B->K, st));
+  }
   return PPCG_OK;
 }
 
@@ -522,18 +542,21 @@ int fp64_parts_batched(ppcg_batch* B, hipStream_t st) {
     if (rc) return rc;
     const Orient& ro = B->srows[0];
     const Orient& co = B->scols[0];
-    PPCG_TRY_HIP(launch_panel_pass_k<double>(B->K, ro.pass, comb_all<double>(B->beta_K, B->K),
-                                             reinterpret_cast<double*>(ro.part),
-                                             reinterpret_cast<double*>(ro.piece),
-                                             rows_direct(ro) ? B->om64_K : nullptr, nullptr, 0,
-                                             st));
-    PPCG_TRY_HIP(launch_panel_pass_k<double>(
-        B->K, co.pass, comb_k<double>(ro, B->K, 0, rows_direct(ro) ? nullptr : B->om64_K),
-        reinterpret_cast<double*>(co.part), reinterpret_cast<double*>(co.piece), nullptr,
-        nullptr, 0, st));
-    for (int32_t c = 0; c < B->nch; ++c)
-      PPCG_TRY_HIP(launch_combine<double, double>(comb_k<double>(co, B->K, c, nullptr), B->p,
-                                                  B->ch[c].qx64, st));
+    for (int32_t g = 0; g < B->G; ++g) {
+      const double* bg = B->beta_K + (int64_t)g * B->p * B->K;
+      const double* om = B->om64_K + (int64_t)g * B->n * B->K;
+      PPCG_TRY_HIP(launch_panel_pass_k<double>(B->K, ro.pass, comb_all<double>(bg, B->K),
+                                               reinterpret_cast<double*>(ro.part),
+                                               reinterpret_cast<double*>(ro.piece),
+                                               rows_direct(ro) ? om : nullptr, nullptr, 0, st));
+      PPCG_TRY_HIP(launch_panel_pass_k<double>(
+          B->K, co.pass, comb_k<double>(ro, B->K, 0, rows_direct(ro) ? nullptr : om),
+          reinterpret_cast<double*>(co.part), reinterpret_cast<double*>(co.piece), nullptr,
+          nullptr, 0, st));
+      for (int32_t c = g * B->K; c < std::min(B->nch, (g + 1) * B->K); ++c)
+        PPCG_TRY_HIP(launch_combine<double, double>(
+            comb_k<double>(co, B->K, c % B->K, nullptr), B->p, B->ch[c].qx64, st));
+    }
     return PPCG_OK;
   }
   PPCG_TRY_HIP(launch_panel_pass_batched<double>(
@@ -591,17 +614,19 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
     if (draw) {
       if ((rc = interleave<double>(B, y.data(), B->n, B->y_K, st))) return rc;
       const Orient& co = B->scols[0];
-      PPCG_TRY_HIP(launch_panel_pass_k<double>(B->K, co.pass, comb_all<double>(B->y_K, B->K),
-                                               reinterpret_cast<double*>(co.part),
-                                               reinterpret_cast<double*>(co.piece), nullptr,
-                                               nullptr, 0, st));
-      for (int32_t c = 0; c < B->nch; ++c) {
-        const ChainBufs& C = B->ch[c];
-        const ppcg_chain& A = chains[c];
-        PPCG_TRY_HIP(launch_combine<double, double>(comb_k<double>(co, B->K, c, nullptr), C.p,
-                                                    C.qx64, st));
-        PPCG_TRY_HIP(launch_rhs_fin(C.qx64, A.lambda, dt, A.tau, A.seed, A.chain,
-                                    A.draw_index, C.p, C.b64, st));
+      for (int32_t g = 0; g < B->G; ++g) {
+        PPCG_TRY_HIP(launch_panel_pass_k<double>(
+            B->K, co.pass, comb_all<double>(B->y_K + (int64_t)g * B->n * B->K, B->K),
+            reinterpret_cast<double*>(co.part), reinterpret_cast<double*>(co.piece), nullptr,
+            nullptr, 0, st));
+        for (int32_t c = g * B->K; c < std::min(B->nch, (g + 1) * B->K); ++c) {
+          const ChainBufs& C = B->ch[c];
+          const ppcg_chain& A = chains[c];
+          PPCG_TRY_HIP(launch_combine<double, double>(
+              comb_k<double>(co, B->K, c % B->K, nullptr), C.p, C.qx64, st));
+          PPCG_TRY_HIP(launch_rhs_fin(C.qx64, A.lambda, dt, A.tau, A.seed, A.chain,
+                                      A.draw_index, C.p, C.b64, st));
+        }
       }
     }
   } else if (draw) {
@@ -799,10 +824,16 @@ int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64
     B->shared = true;
     B->dtype = dtype;
     B->nch = nchains;
-    B->K = nchains <= 2 ? 2 : (nchains <= 4 ? 4 : 8);
+    // FP64 loops run groups of at most four chains (a pass over eight FP64
+    // vectors needs more registers than a 1024-thread workgroup leaves a
+    // lane, and two four-vector passes measured faster than one with the
+    // spills); FP32 loops run all chains in one group
+    B->K = nchains <= 2 ? 2 : (nchains <= 4 || dtype == PPCG_F64 ? 4 : 8);
+    B->G = (nchains + B->K - 1) / B->K;
     B->n = n;
     B->p = p;
     const int K = B->K;
+    const size_t KG = (size_t)K * B->G;  // vector slots
     if (hipGetDevice(&B->device) != hipSuccess) return fail(PPCG_EHIP);
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, B->device) !=
@@ -845,49 +876,51 @@ int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64
       if (rc) return fail(rc);
     }
     const size_t ts = dtype == PPCG_F64 ? 8 : 4;
-    unsigned char *omT = nullptr, *sK = nullptr;
+    unsigned char *omT = nullptr, *sK = nullptr, *qK = nullptr;
     const int tl = dtype == PPCG_F64 ? 0 : 1;
-    if (B->mem.alloc(&B->y_K, (size_t)n * K) != hipSuccess ||
-        B->mem.alloc(&B->om64_K, (size_t)n * K) != hipSuccess ||
-        B->mem.alloc(&B->beta_K, (size_t)p * K) != hipSuccess ||
-        B->mem.alloc(&B->z_K, (size_t)p * K) != hipSuccess ||
-        B->mem.alloc(&B->d_K, (size_t)p * K) != hipSuccess ||
-        B->mem.alloc(&B->p1_K, (size_t)B->srows[tl].pass.nwg * K) != hipSuccess ||
-        B->mem.alloc(&B->p2_K, (size_t)B->scols[tl].pass.nwg * K) != hipSuccess ||
-        B->mem.alloc(&sK, 2 * (size_t)p * K * ts) != hipSuccess)
+    if (B->mem.alloc(&B->y_K, (size_t)n * KG) != hipSuccess ||
+        B->mem.alloc(&B->om64_K, (size_t)n * KG) != hipSuccess ||
+        B->mem.alloc(&B->beta_K, (size_t)p * KG) != hipSuccess ||
+        B->mem.alloc(&B->z_K, (size_t)p * KG) != hipSuccess ||
+        B->mem.alloc(&B->d_K, (size_t)p * KG) != hipSuccess ||
+        B->mem.alloc(&B->p1_K, (size_t)B->srows[tl].pass.nwg * KG) != hipSuccess ||
+        B->mem.alloc(&B->p2_K, (size_t)B->scols[tl].pass.nwg * KG) != hipSuccess ||
+        B->mem.alloc(&sK, 2 * (size_t)p * KG * ts) != hipSuccess ||
+        B->mem.alloc(&qK, (size_t)p * KG * ts) != hipSuccess)
       return fail(PPCG_ENOMEM);
+    B->q_K = qK;
     if (dtype == PPCG_F32) {
-      if (B->mem.alloc(&omT, (size_t)n * K * ts) != hipSuccess) return fail(PPCG_ENOMEM);
+      if (B->mem.alloc(&omT, (size_t)n * KG * ts) != hipSuccess) return fail(PPCG_ENOMEM);
       B->omT_K = omT;
     } else {
       B->omT_K = B->om64_K;
     }
     B->s_K = sK;
     // vector slots beyond the chains stay zero (their products are ignored)
-    if (hipMemset(B->y_K, 0, (size_t)n * K * 8) != hipSuccess ||
-        hipMemset(B->om64_K, 0, (size_t)n * K * 8) != hipSuccess ||
-        hipMemset(B->beta_K, 0, (size_t)p * K * 8) != hipSuccess ||
-        hipMemset(B->z_K, 0, (size_t)p * K * 8) != hipSuccess ||
-        hipMemset(B->d_K, 0, (size_t)p * K * 8) != hipSuccess ||
-        hipMemset(sK, 0, 2 * (size_t)p * K * ts) != hipSuccess ||
-        (omT && hipMemset(omT, 0, (size_t)n * K * ts) != hipSuccess))
+    if (hipMemset(B->y_K, 0, (size_t)n * KG * 8) != hipSuccess ||
+        hipMemset(B->om64_K, 0, (size_t)n * KG * 8) != hipSuccess ||
+        hipMemset(B->beta_K, 0, (size_t)p * KG * 8) != hipSuccess ||
+        hipMemset(B->z_K, 0, (size_t)p * KG * 8) != hipSuccess ||
+        hipMemset(B->d_K, 0, (size_t)p * KG * 8) != hipSuccess ||
+        hipMemset(sK, 0, 2 * (size_t)p * KG * ts) != hipSuccess ||
+        (omT && hipMemset(omT, 0, (size_t)n * KG * ts) != hipSuccess))
       return fail(PPCG_EHIP);
     // one scalar block per vector slot; slots beyond the chains stay done
-    if (B->mem.alloc(&B->sc, (size_t)K) != hipSuccess) return fail(PPCG_ENOMEM);
+    if (B->mem.alloc(&B->sc, KG) != hipSuccess) return fail(PPCG_ENOMEM);
     {
-      std::vector<DevScal> init(K);
-      std::memset(init.data(), 0, sizeof(DevScal) * K);
-      for (int c = nchains; c < K; ++c) init[c].done = 1;
-      if (hipMemcpy(B->sc, init.data(), sizeof(DevScal) * K, hipMemcpyHostToDevice) !=
+      std::vector<DevScal> init(KG);
+      std::memset(init.data(), 0, sizeof(DevScal) * KG);
+      for (size_t c = (size_t)nchains; c < KG; ++c) init[c].done = 1;
+      if (hipMemcpy(B->sc, init.data(), sizeof(DevScal) * KG, hipMemcpyHostToDevice) !=
           hipSuccess)
         return fail(PPCG_EHIP);
     }
-    if (hipHostMalloc(reinterpret_cast<void**>(&B->h_sc), sizeof(DevScal) * K, 0) !=
+    if (hipHostMalloc(reinterpret_cast<void**>(&B->h_sc), sizeof(DevScal) * KG, 0) !=
         hipSuccess) {
       B->h_sc = nullptr;
       return fail(PPCG_ENOMEM);
     }
-    std::memset(B->h_sc, 0, sizeof(DevScal) * K);
+    std::memset(B->h_sc, 0, sizeof(DevScal) * KG);
     const int rc = dtype == PPCG_F64 ? build_vec_jobs<double>(B) : build_vec_jobs<float>(B);
     if (rc) return fail(rc);
     if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);

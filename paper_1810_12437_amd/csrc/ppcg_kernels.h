@@ -185,6 +185,12 @@ hipError_t launch_panel_pass(const PanelPass& t, const Combine<T>& x, T* part_ou
 template <typename T, typename U>
 hipError_t launch_combine(const Combine<T>& c, int64_t dim, U* out, hipStream_t st);
 
+// out[j * K + r] = value(c, j, r) for j < dim, r < K (c.es == K); a no-op
+// launch once all K flags done[r * dstride] are set.
+template <typename T>
+hipError_t launch_combine_k(const Combine<T>& c, int K, int64_t dim, T* out,
+                            const int32_t* done, int dstride, hipStream_t st);
+
 // Maximum dynamic LDS the pass kernels may use (call once per device).
 hipError_t setup_pass_kernels();
 

@@ -1159,6 +1159,35 @@ __global__ __launch_bounds__(kWG) void k_combine(Combine<T> c, int64_t dim, U* o
   if (i < dim) out[i] = (U)combine_at(c, i);
 }
 
+// The panel partials of K interleaved vectors summed into out[dim][K]: one
+// thread per element, consecutive threads on consecutive addresses of every
+// partial array (a per-vector reader with stride K would fetch each line K
+// times).  Returns at once when all K flags done[i * dstride] are set.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_combine_k(Combine<T> c, int K, int64_t dim, T* out,
+                                                   const int32_t* done, int dstride) {
+  int all = 1;
+  for (int r = 0; r < K; ++r) all &= gview(done)[(int64_t)r * dstride] != 0 ? 1 : 0;
+  if (all) return;
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < dim * K) out[i] = combine_at(c, i / K, (int)(i % K));
+}
+
+template <typename T>
+hipError_t launch_combine_k(const Combine<T>& c, int K, int64_t dim, T* out,
+                            const int32_t* done, int dstride, hipStream_t st) {
+  if (dim <= 0) return hipSuccess;
+  if (c.es != K || done == nullptr) return hipErrorInvalidValue;
+  const int64_t n = dim * K;
+  hipLaunchKernelGGL((k_combine_k<T>), dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG), 0, st,
+                     c, K, dim, out, done, dstride);
+  return hipGetLastError();
+}
+template hipError_t launch_combine_k<float>(const Combine<float>&, int, int64_t, float*,
+                                            const int32_t*, int, hipStream_t);
+template hipError_t launch_combine_k<double>(const Combine<double>&, int, int64_t, double*,
+                                             const int32_t*, int, hipStream_t);
+
 template <typename T, typename U>
 hipError_t launch_combine(const Combine<T>& c, int64_t dim, U* out, hipStream_t st) {
   if (dim <= 0) return hipSuccess;
