@@ -2,6 +2,7 @@
 // per-iteration phases run as one launch per phase for all chains.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <thread>
@@ -119,6 +120,11 @@ struct ppcg_batch {
   double *p1_K = nullptr, *p2_K = nullptr;                       // [G][nwg][K]
   void *omT_K = nullptr, *s_K = nullptr;                         // [G][dim][K] / [G][2][p][K]
   void* q_K = nullptr;  // [G][p][K], dtype: X^T u of the loop's column pass, summed over panels
+  // vector slot of each chain and chain of each slot (slots [0, nch) hold the
+  // chains), and each chain's CG iterations in the last call: with two
+  // groups the chains are dealt to slots by falling count, so that the
+  // chains that iterate longest share a group
+  std::vector<int32_t> slot_of, chain_at, last_iters;
 };
 
 namespace {
@@ -213,16 +219,18 @@ int build_pass_jobs(ppcg_batch* B, int kind) {
   return PPCG_OK;
 }
 
+// Slot of chain c (the chain itself unless the shared form reassigned it).
+int32_t slot(const ppcg_batch* B, int32_t c) { return B->slot_of.empty() ? c : B->slot_of[c]; }
+
 template <typename T>
-int build_vec_jobs(ppcg_batch* B) {
+std::vector<VecJob<T>> vec_jobs(ppcg_batch* B) {
   std::vector<VecJob<T>> jobs(B->nch);
-  std::vector<int32_t> bj, bl;
   const int ti = prec_index<T>();
   for (int32_t c = 0; c < B->nch; ++c) {
     const ChainBufs& C = B->ch[c];
     VecJob<T>& J = jobs[c];
     J = VecJob<T>{};
-    J.w = VecWork{C.red, &B->sc[c]};
+    J.w = VecWork{C.red, &B->sc[slot(B, c)]};
     J.s = reinterpret_cast<T*>(C.s);
     J.sstride = C.p;
     J.z = C.z;
@@ -249,7 +257,7 @@ int build_vec_jobs(ppcg_batch* B) {
     if (B->shared) {
       // s, z and the pass partials interleaved over the chains; q from the
       // K-wide column pass
-      const int64_t g = c / B->K, r = c % B->K, pK = B->p * B->K;
+      const int64_t g = slot(B, c) / B->K, r = slot(B, c) % B->K, pK = B->p * B->K;
       J.n1 = B->srows[ti].pass.nwg;
       J.n2 = B->scols[ti].pass.nwg;
       J.s = reinterpret_cast<T*>(B->s_K) + g * 2 * pK + r;
@@ -262,11 +270,19 @@ int build_vec_jobs(ppcg_batch* B) {
       J.pstride = B->K;
       J.qsrc = comb_all<T>(reinterpret_cast<const T*>(B->q_K) + g * pK + r, B->K);
     }
-    for (int32_t b = 0; b < J.nblk; ++b) {
+  }
+  return jobs;
+}
+
+template <typename T>
+int build_vec_jobs(ppcg_batch* B) {
+  const std::vector<VecJob<T>> jobs = vec_jobs<T>(B);
+  std::vector<int32_t> bj, bl;
+  for (int32_t c = 0; c < B->nch; ++c)
+    for (int32_t b = 0; b < jobs[c].nblk; ++b) {
       bj.push_back(c);
       bl.push_back(b);
     }
-  }
   VecJob<T>* dj = nullptr;
   int rc = upload(B, jobs, &dj);
   if (rc) return rc;
@@ -433,7 +449,7 @@ int interleave(ppcg_batch* B, double* const* src_of_chain, int64_t dim, T* dst,
   for (int32_t g = 0; g < B->G; ++g) {
     VecPtrs v{};
     const int32_t c0 = g * B->K, nc = std::min(B->K, B->nch - c0);
-    for (int32_t r = 0; r < nc; ++r) v.p[r] = src_of_chain[c0 + r];
+    for (int32_t r = 0; r < nc; ++r) v.p[r] = src_of_chain[B->chain_at[c0 + r]];
     PPCG_TRY_HIP(launch_interleave<T>(v, nc, B->K, dim, dst + (int64_t)g * dim * B->K, st));
   }
   return PPCG_OK;
@@ -520,7 +536,7 @@ int run_loop_batched(ppcg_batch* B, const ppcg_options& o, hipStream_t st) {
     PPCG_TRY_HIP(hipStreamSynchronize(st));
     bool any = false;
     for (int32_t c = 0; c < B->nch; ++c) {
-      act[c] = B->h_sc[c].done ? 0 : 1;
+      act[c] = B->h_sc[slot(B, c)].done ? 0 : 1;
       any = any || act[c];
     }
     if (!any) return PPCG_OK;
@@ -553,9 +569,9 @@ int fp64_parts_batched(ppcg_batch* B, hipStream_t st) {
           B->K, co.pass, comb_k<double>(ro, B->K, 0, rows_direct(ro) ? nullptr : om),
           reinterpret_cast<double*>(co.part), reinterpret_cast<double*>(co.piece), nullptr,
           nullptr, 0, st));
-      for (int32_t c = g * B->K; c < std::min(B->nch, (g + 1) * B->K); ++c)
-        PPCG_TRY_HIP(launch_combine<double, double>(
-            comb_k<double>(co, B->K, c % B->K, nullptr), B->p, B->ch[c].qx64, st));
+      for (int32_t sl = g * B->K; sl < std::min(B->nch, (g + 1) * B->K); ++sl)
+        PPCG_TRY_HIP(launch_combine<double, double>(comb_k<double>(co, B->K, sl % B->K, nullptr),
+                                                    B->p, B->ch[B->chain_at[sl]].qx64, st));
     }
     return PPCG_OK;
   }
@@ -578,10 +594,40 @@ int sync_all(ppcg_batch* B, hipStream_t st) {
   return PPCG_OK;
 }
 
+// Shared form with two groups: chains dealt to slots by falling iteration
+// count of the last call (ties by chain), so that the longest-iterating
+// chains share a group and the other group stops early.  A new assignment
+// rewrites the step's job table in place (the stream is idle between calls)
+// and drops the captured graphs.  The slot does not change a chain's
+// arithmetic: every slot of a group is summed the same way.
+template <typename T>
+int assign_slots(ppcg_batch* B, hipStream_t st) {
+  if (!B->shared || B->G < 2) return PPCG_OK;
+  std::vector<int32_t> order(B->nch);
+  for (int32_t c = 0; c < B->nch; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return B->last_iters[a] > B->last_iters[b];
+  });
+  if (order == B->chain_at) return PPCG_OK;
+  B->chain_at = order;
+  for (int32_t sl = 0; sl < B->nch; ++sl) B->slot_of[order[sl]] = sl;
+  const std::vector<VecJob<T>> jobs = vec_jobs<T>(B);
+  PPCG_TRY_HIP(hipStreamSynchronize(st));
+  PPCG_TRY_HIP(hipMemcpy(B->vjobs, jobs.data(), jobs.size() * sizeof(VecJob<T>),
+                         hipMemcpyHostToDevice));
+  drop_graphs(B);
+  ++B->lp_version;
+  return PPCG_OK;
+}
+
 template <typename T>
 int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
                 ppcg_info* infos, bool draw, hipStream_t st) {
   const int dt = B->dtype;
+  {
+    const int rc = assign_slots<T>(B, st);
+    if (rc) return rc;
+  }
   // per-chain preparation: d, m, FP64 omega (and its FP32 copy), b
   for (int32_t c = 0; c < B->nch; ++c) {
     const ChainBufs& C = B->ch[c];
@@ -619,11 +665,11 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
             B->K, co.pass, comb_all<double>(B->y_K + (int64_t)g * B->n * B->K, B->K),
             reinterpret_cast<double*>(co.part), reinterpret_cast<double*>(co.piece), nullptr,
             nullptr, 0, st));
-        for (int32_t c = g * B->K; c < std::min(B->nch, (g + 1) * B->K); ++c) {
-          const ChainBufs& C = B->ch[c];
-          const ppcg_chain& A = chains[c];
+        for (int32_t sl = g * B->K; sl < std::min(B->nch, (g + 1) * B->K); ++sl) {
+          const ChainBufs& C = B->ch[B->chain_at[sl]];
+          const ppcg_chain& A = chains[B->chain_at[sl]];
           PPCG_TRY_HIP(launch_combine<double, double>(
-              comb_k<double>(co, B->K, c % B->K, nullptr), C.p, C.qx64, st));
+              comb_k<double>(co, B->K, sl % B->K, nullptr), C.p, C.qx64, st));
           PPCG_TRY_HIP(launch_rhs_fin(C.qx64, A.lambda, dt, A.tau, A.seed, A.chain,
                                       A.draw_index, C.p, C.b64, st));
         }
@@ -652,7 +698,7 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
   if ((rc = run_loop_batched<T>(B, o, st))) return rc;
   std::vector<ppcg_info> inf(B->nch);
   for (int32_t c = 0; c < B->nch; ++c) {
-    const DevScal& S = B->h_sc[c];
+    const DevScal& S = B->h_sc[slot(B, c)];
     ppcg_info& I = inf[c];
     I = ppcg_info{};
     I.status = S.status;
@@ -671,7 +717,7 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
     if ((rc = sync_all(B, st))) return rc;
     bool any = false;
     for (int32_t c = 0; c < B->nch; ++c) {
-      const DevScal& S = B->h_sc[c];
+      const DevScal& S = B->h_sc[slot(B, c)];
       inf[c].resid_true = inf[c].resid_true_first = ratio(S.true_meas, S.thresh2);
       inf[c].rms_precond = std::sqrt(S.true_rm / (double)B->ch[c].p);
       any = any || (S.status == PPCG_OK && S.true_meas > S.thresh2);
@@ -685,7 +731,7 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
       if ((rc = run_loop_batched<T>(B, o, st))) return rc;
       std::vector<int32_t> refined(B->nch);
       for (int32_t c = 0; c < B->nch; ++c) {
-        const DevScal& S = B->h_sc[c];
+        const DevScal& S = B->h_sc[slot(B, c)];
         refined[c] = S.refined;
         if (S.refined) {
           inf[c].refined = 1;
@@ -701,7 +747,7 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
       if ((rc = sync_all(B, st))) return rc;
       for (int32_t c = 0; c < B->nch; ++c) {
         if (!refined[c]) continue;
-        const DevScal& S = B->h_sc[c];
+        const DevScal& S = B->h_sc[slot(B, c)];
         inf[c].resid_true = ratio(S.true_meas, S.thresh2);
         inf[c].rms_precond = std::sqrt(S.true_rm / (double)B->ch[c].p);
       }
@@ -711,6 +757,8 @@ int batch_solve(ppcg_batch* B, const ppcg_chain* chains, const ppcg_options& o,
     PPCG_TRY_HIP(launch_convert_from_f64(B->ch[c].beta64, dt, B->ch[c].p, chains[c].beta_out,
                                          st));
   PPCG_TRY_HIP(hipStreamSynchronize(st));
+  if (!B->last_iters.empty())
+    for (int32_t c = 0; c < B->nch; ++c) B->last_iters[c] = inf[c].iters + inf[c].refine_iters;
   int status = PPCG_OK;
   for (int32_t c = 0; c < B->nch; ++c) {
     if (infos) infos[c] = inf[c];
@@ -921,6 +969,10 @@ int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64
       return fail(PPCG_ENOMEM);
     }
     std::memset(B->h_sc, 0, sizeof(DevScal) * KG);
+    B->slot_of.resize(nchains);
+    B->chain_at.resize(nchains);
+    B->last_iters.assign(nchains, 0);
+    for (int32_t c = 0; c < nchains; ++c) B->slot_of[c] = B->chain_at[c] = c;
     const int rc = dtype == PPCG_F64 ? build_vec_jobs<double>(B) : build_vec_jobs<float>(B);
     if (rc) return fail(rc);
     if (hipDeviceSynchronize() != hipSuccess) return fail(PPCG_EHIP);

@@ -182,6 +182,34 @@ def test_shared_draw_matches_single_chain_draws():
         assert abs(infos[c]["iters"] - info["iters"]) <= max(3, 0.05 * info["iters"])
 
 
+def test_shared_slot_reassignment_keeps_draws():
+    """FP64 batches of five to eight chains on one design run as two groups
+    of four; after a call the chains are dealt to the groups by falling
+    iteration count.  The slot does not change a chain's arithmetic: a draw
+    after the reassignment equals, bit for bit and iteration for iteration,
+    the same draw from a fresh batch with the chains in their first slots."""
+    base, chains, B0, vecs = shared_setup(8, pk.F64)
+    n = len(vecs)
+    args = lambda d: ([44] * n, list(range(n)), [d] * n)  # noqa: E731
+    cols = lambda v: [[x[i] for x in v] for i in range(4)]  # noqa: E731
+    _, inf0 = B0.draw(*cols(vecs), *args(0), tol=1e-8)
+    its = [i["iters"] + i["refine_iters"] for i in inf0]
+    say("[slots] iterations by chain", its)
+    # chains handed over by rising count: the reassignment reverses them
+    order = sorted(range(n), key=lambda c: (its[c], c))
+    v2 = [vecs[c] for c in order]
+    assert sorted(its) != sorted(its, reverse=True)
+    B1 = pk.Batch.shared(base.n, base.p, base.row_ptr, base.col_idx, n, dtype=pk.F64)
+    B1.draw(*cols(v2), *args(0), tol=1e-8)
+    b1, i1 = B1.draw(*cols(v2), *args(1), tol=1e-8)
+    B2 = pk.Batch.shared(base.n, base.p, base.row_ptr, base.col_idx, n, dtype=pk.F64)
+    b2, i2 = B2.draw(*cols(v2), *args(1), tol=1e-8)
+    for c in range(n):
+        assert torch.equal(b1[c], b2[c]), c
+        assert (i1[c]["iters"], i1[c]["refine_iters"]) == (i2[c]["iters"], i2[c]["refine_iters"])
+        assert i1[c]["status"] == pk.OK
+
+
 def test_shared_f32_matches_f64_oracle():
     base, chains, B, vecs = shared_setup(4, pk.F32)
     n = len(vecs)
