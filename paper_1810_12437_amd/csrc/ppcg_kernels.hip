@@ -397,6 +397,31 @@ __device__ __forceinline__ void gather_cmp(const T* xl, const u16x8& a, T& acc) 
     acc += __builtin_fmaf(-(float)pads, last, v[0] + v[8]);
 }
 
+// The same for a wide group (ppcg_layout.h): its first index and the
+// running sums of six 16-bit differences give kWGroup indices.
+template <typename T>
+__device__ __forceinline__ void gather_wide(const T* xl, const u16x8& a, T& acc) {
+  const u32x4 d = __builtin_bit_cast(u32x4, a);
+  uint32_t e[kWGroup];
+  e[0] = d[0] & 0xffffu;
+  const uint32_t pads = (d[0] >> 16) & 0xffu;
+#pragma unroll
+  for (int w = 1; w < 4; ++w) {
+    e[2 * w - 1] = e[2 * w - 2] + (d[w] & 0xffffu);
+    e[2 * w] = e[2 * w - 1] + (d[w] >> 16);
+  }
+  const uint32_t l0 = __builtin_amdgcn_readfirstlane(lds_addr(xl));
+  T v[kWGroup];
+#pragma unroll
+  for (int k = 0; k < kWGroup; ++k) v[k] = lds_load<T>(e[k] * (uint32_t)sizeof(T) + l0);
+  const T last = v[kWGroup - 1];
+  const T s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + v[6]);
+  if constexpr (sizeof(T) == 8)
+    acc += __builtin_fma(-(double)pads, last, s);
+  else
+    acc += __builtin_fmaf(-(float)pads, last, s);
+}
+
 // acc[r] += (cond ? DPP move of acc[r] : 0) for every vector.
 template <int CTRL, int RM, typename T, int K>
 __device__ __forceinline__ void dpp_add(T (&acc)[K], bool cond) {
@@ -885,10 +910,14 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
           }
         }
         if ((rh >> q) & 1u) {
-          if constexpr (K == 1)
-            gather_cmp<T>(xl, ra[q], acc[0]);
-          else
+          if constexpr (K == 1) {
+            if (cinfo & kChunkWide)
+              gather_wide<T>(xl, ra[q], acc[0]);
+            else
+              gather_cmp<T>(xl, ra[q], acc[0]);
+          } else {
             gather_add16<T, K>(xl, ra[q], rb[q], acc);
+          }
         }
       }
       stream_issue<K == 1>(t, c_end, lane, ld, ra[q], rb[q], rs[q], rh, q);

@@ -37,6 +37,14 @@ enum ChunkKind { kChunkPacked = 0, kChunkLong = 1, kChunkPiece = 2 };
 // many groups as that takes).  The c pads repeat the last real index
 // (difference 0), and the summing lane takes c times that entry off again.
 constexpr int kCGroup = 14;  // entries per compact group
+// Wide groups, for segment entries whose runs the 255 limit would cut into
+// mostly padded compact groups (sparse segments): the same 16 bytes hold
+// the first index (bytes 0-1), the pad count (byte 2, byte 3 zero) and six
+// 16-bit differences (bytes 4-15), so kWGroup entries at any distance
+// within the panel.  A chunk holds groups of one kind: wide when bit
+// kChunkWide of its info is set.
+constexpr int kWGroup = 7;  // entries per wide group
+constexpr int32_t kChunkWide = 1 << 18;
 
 // One chunk of an orientation's index stream, read by one wavefront.
 //
@@ -61,13 +69,15 @@ struct alignas(64) ChunkDesc {
   uint64_t sm;
   int32_t first;     // packed: first seg_out entry; long: its seg_out entry; piece: its id
   int32_t info;      // windows | kind << 8 | row steps << 12 | bcast15 << 16 | bcast31 << 17
-                     //   | segments << 24
+                     //   | wide groups << 18 | segments << 24
   int64_t seg;       // piece: the segment (output element) it is part of
 };
 static_assert(sizeof(ChunkDesc) == 64, "chunk descriptor is one 64-byte scalar load");
 
-constexpr int32_t chunk_info(int windows, int kind, int nrow, int b15, int b31, int nseg) {
-  return windows | (kind << 8) | (nrow << 12) | (b15 << 16) | (b31 << 17) | (nseg << 24);
+constexpr int32_t chunk_info(int windows, int kind, int nrow, int b15, int b31, int nseg,
+                             bool wide = false) {
+  return windows | (kind << 8) | (nrow << 12) | (b15 << 16) | (b31 << 17) |
+         (wide ? kChunkWide : 0) | (nseg << 24);
 }
 
 }  // namespace ppcg

@@ -41,9 +41,10 @@ inline int ceil_log2(int v) {
 inline bool crosses(int l0, int w, int a) { return l0 <= a && a + 1 < l0 + w; }
 
 struct Entry {
-  int64_t a, e, g;  // element range, groups
-  int32_t slot;     // panel * out_dim + segment
-  int64_t g0;       // compact tables: the entry's first group in the group starts
+  int64_t a, e, g;    // element range, groups
+  int32_t slot;       // panel * out_dim + segment
+  int64_t g0;         // compact tables: the entry's first group in the group starts
+  bool wide = false;  // compact tables: wide groups (kWGroup entries, 16-bit differences)
 };
 
 inline int chunk_cost(const ChunkDesc& d) {
@@ -146,9 +147,12 @@ inline void spread_window(uint16_t* const* grp, const int* lanes, int ngroups, i
 //
 // With `compact` (tables of one gathered vector) groups are the compact
 // 16-byte groups of ppcg_layout.h: up to kCGroup consecutive entries at most
-// 255 apart, a segment's run being cut into as many groups as that takes;
-// otherwise (K interleaved vectors) groups are kPV 16-bit indices padded
-// with the zero index W and stored as halves.
+// 255 apart, a segment's run being cut into as many groups as that takes,
+// or, for an entry where wide groups of kWGroup entries are fewer (sparse
+// segments, whose runs the cuts would leave mostly padding), wide groups;
+// packed chunks hold entries of one kind.  Otherwise (K interleaved vectors)
+// groups are kPV 16-bit indices padded with the zero index W and stored as
+// halves.
 inline void build_panels(const std::vector<int64_t>& off, const std::vector<int32_t>& gidx,
                          int64_t out_dim, int64_t gdim, int elem, int ncu, PanelBuild& B,
                          bool compact = false) {
@@ -171,20 +175,32 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
     for (; q < a + kPV; ++q) B.idx.push_back(sentinel);
   };
   // group j of entry en as one compact group: first index, pad count, the
-  // differences (0 for the pads, which repeat the last index)
+  // differences (0 for the pads, which repeat the last index); one- or
+  // two-byte differences as the entry is narrow or wide
   auto append_cgroup = [&](const Entry& en, int64_t j, int64_t glo) {
     const int64_t a = gstart[en.g0 + j];
     const int64_t e = j + 1 < en.g ? gstart[en.g0 + j + 1] : en.e;
-    uint8_t by[16];
     const int64_t i0 = gidx[a] - glo;
-    by[0] = (uint8_t)(i0 & 0xff);
-    by[1] = (uint8_t)(i0 >> 8);
-    by[2] = (uint8_t)(kCGroup - (e - a));
-    for (int k = 1; k < kCGroup; ++k) {
-      const int64_t q = a + k;
-      by[k + 2] = q < e ? (uint8_t)(gidx[q] - gidx[q - 1]) : 0;
+    uint16_t w[8];
+    if (en.wide) {
+      w[0] = (uint16_t)i0;
+      w[1] = (uint16_t)(kWGroup - (e - a));
+      for (int k = 1; k < kWGroup; ++k) {
+        const int64_t q = a + k;
+        w[k + 1] = q < e ? (uint16_t)(gidx[q] - gidx[q - 1]) : 0;
+      }
+    } else {
+      uint8_t by[16];
+      by[0] = (uint8_t)(i0 & 0xff);
+      by[1] = (uint8_t)(i0 >> 8);
+      by[2] = (uint8_t)(kCGroup - (e - a));
+      for (int k = 1; k < kCGroup; ++k) {
+        const int64_t q = a + k;
+        by[k + 2] = q < e ? (uint8_t)(gidx[q] - gidx[q - 1]) : 0;
+      }
+      for (int q = 0; q < 8; ++q) w[q] = (uint16_t)(by[2 * q] | (by[2 * q + 1] << 8));
     }
-    for (int w = 0; w < 8; ++w) B.idx.push_back((uint16_t)(by[2 * w] | (by[2 * w + 1] << 8)));
+    for (int q = 0; q < 8; ++q) B.idx.push_back(w[q]);
   };
   // compact: cuts the run [a, e) into groups
   auto cut_groups = [&](int64_t a, int64_t e) {
@@ -216,7 +232,16 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
           if (compact) {
             en.g0 = (int64_t)gstart.size();
             cut_groups(a, e);
-            en.g = (int64_t)gstart.size() - en.g0;
+            const int64_t gn = (int64_t)gstart.size() - en.g0;
+            const int64_t gw = (e - a + kWGroup - 1) / kWGroup;
+            if (gw < gn) {  // panel-local differences always fit 16 bits
+              gstart.resize((size_t)en.g0);
+              for (int64_t q = a; q < e; q += kWGroup) gstart.push_back(q);
+              en.wide = true;
+              en.g = gw;
+            } else {
+              en.g = gn;
+            }
           }
           ent[k].push_back(en);
           cur[sgm] = e;
@@ -226,13 +251,17 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
     }
   }
 
-  // 2. estimated windows per panel (packed entries as chunks of kPR windows)
-  std::vector<detail::Packer> pk(B.npanels);
+  // 2. estimated windows per panel (packed entries as chunks of kPR windows;
+  // narrow and wide entries packed apart)
+  std::vector<detail::Packer> pk(B.npanels), pkw(B.npanels);
   std::vector<int64_t> pwin(B.npanels, 0);
+  std::vector<std::array<int64_t, 2>> pwin_kind(B.npanels, {0, 0});  // packed: narrow, wide
   std::vector<int32_t> members;
   for (int32_t k = 0; k < B.npanels; ++k) {
     detail::Packer& P = pk[k];
+    detail::Packer& Pw = pkw[k];
     P.ent = &ent[k];
+    Pw.ent = &ent[k];
     for (int32_t i = 0; i < (int32_t)ent[k].size(); ++i) {
       const Entry& en = ent[k][i];
       if (en.g > packed_max) {
@@ -247,20 +276,24 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
           }
         }
       } else {
-        P.order.push_back(i);
+        (ent[k][i].wide ? Pw : P).order.push_back(i);
       }
     }
-    std::stable_sort(P.order.begin(), P.order.end(),
-                     [&](int32_t x, int32_t y) { return ent[k][x].g > ent[k][y].g; });
-    detail::Packer T = P;
-    T.hi = T.order.size();
-    while (!T.empty()) {
-      T.take(kPR, members);
-      int64_t last = 0;  // windows of the chunk: the longest lane's groups
-      for (int32_t i : members) last = std::max<int64_t>(last, std::min<int64_t>(ent[k][i].g, kPR));
-      pwin[k] += last;
+    for (detail::Packer* Q : {&P, &Pw}) {
+      std::stable_sort(Q->order.begin(), Q->order.end(),
+                       [&](int32_t x, int32_t y) { return ent[k][x].g > ent[k][y].g; });
+      detail::Packer T = *Q;
+      T.hi = T.order.size();
+      while (!T.empty()) {
+        T.take(kPR, members);
+        int64_t last = 0;  // windows of the chunk: the longest lane's groups
+        for (int32_t i : members)
+          last = std::max<int64_t>(last, std::min<int64_t>(ent[k][i].g, kPR));
+        pwin[k] += last;
+        pwin_kind[k][Q == &Pw ? 1 : 0] += last;
+      }
+      Q->hi = Q->order.size();
     }
-    P.hi = P.order.size();
   }
 
   // 3. workgroups per panel, in proportion to its windows
@@ -326,7 +359,7 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
         const int win = (int)((ng + 63) / 64);
         d.first = pieces ? B.npieces++ : (int32_t)B.seg_out.size() - 1;
         d.seg = en.slot % out_dim;
-        d.info = chunk_info(win, pieces ? kChunkPiece : kChunkLong, 0, 0, 0, 1);
+        d.info = chunk_info(win, pieces ? kChunkPiece : kChunkLong, 0, 0, 0, 1, en.wide);
         if (compact) {
           for (int64_t j = o; j < oe; ++j) append_cgroup(en, j, glo);
         } else {
@@ -343,18 +376,31 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
     // windows; the share starts from the estimate and is rebuilt from the
     // windows the first fill actually used when that fill ends unevenly.
     detail::Packer& P = pk[k];
+    detail::Packer& Pw = pkw[k];
     const size_t idx0 = B.idx.size(), seg0 = B.seg_out.size();
     const std::vector<std::vector<ChunkDesc>> lists_long = lists;
     const std::vector<int64_t> load_long = load;
-    auto make_packed = [&](int R) {
-      P.take(R, members);
+    // narrow and wide chunks interleaved in the proportion of their
+    // estimated windows, so that every wavefront's share mixes them (wide
+    // chunks hold up to 64 short segments, and their outputs, gathered
+    // onto a few wavefronts, made those the pass's last)
+    auto all_taken = [&]() { return P.empty() && Pw.empty(); };
+    int64_t took[2] = {0, 0};
+    auto next_packer = [&]() -> detail::Packer& {
+      if (P.empty()) return Pw;
+      if (Pw.empty()) return P;
+      return took[1] * pwin_kind[k][0] <= took[0] * pwin_kind[k][1] ? Pw : P;
+    };
+    auto make_packed = [&](detail::Packer& Q, int R) {
+      const bool wide = &Q == &Pw;
+      Q.take(R, members);
       ChunkDesc d{};
       d.base = (int64_t)B.idx.size();
       d.first = (int32_t)B.seg_out.size();
       std::vector<int> l0s(members.size()), ws(members.size());
       int l = 0, maxw = 1, b15 = 0, b31 = 0;
       for (size_t s = 0; s < members.size(); ++s) {
-        const int w = P.lanes(members[s], R);
+        const int w = Q.lanes(members[s], R);
         l0s[s] = l;
         ws[s] = w;
         d.sm |= 1ull << l;
@@ -386,7 +432,7 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
         if (d.vm[kw]) nw = kw + 1;
       }
       d.info = chunk_info(nw, kChunkPacked, detail::ceil_log2(std::min(maxw, 16)), b15, b31,
-                          (int)members.size());
+                          (int)members.size(), wide);
       return d;
     };
     int64_t total = pwin[k];
@@ -397,23 +443,30 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
       B.seg_out.resize(seg0);
       P.lo = 0;
       P.hi = P.order.size();
+      Pw.lo = 0;
+      Pw.hi = Pw.order.size();
+      took[0] = took[1] = 0;
       const double per_w = (double)total / cumw[nwv];
-      for (int q = 0; q < nwv && !P.empty(); ++q) {
+      for (int q = 0; q < nwv && !all_taken(); ++q) {
         const int64_t target =
             (int64_t)std::llround(per_w * cumw[q + 1]) - (int64_t)std::llround(per_w * cumw[q]);
-        while (!P.empty() && load[q] < target) {
+        while (!all_taken() && load[q] < target) {
+          detail::Packer& Q = next_packer();
           int R = (int)std::min<int64_t>(kPR, target - load[q]);
-          R = std::max(R, P.min_windows());
-          const ChunkDesc d = make_packed(R);
+          R = std::max(R, Q.min_windows());
+          const ChunkDesc d = make_packed(Q, R);
           lists[q].push_back(d);
           load[q] += detail::chunk_cost(d);
+          took[&Q == &Pw ? 1 : 0] += detail::chunk_cost(d);
         }
       }
       bool leftover = false;
-      while (!P.empty()) {  // what the share missed: least loaded wavefront
+      while (!all_taken()) {  // what the share missed: least loaded wavefront
         leftover = true;
         const int q = least_loaded();
-        const ChunkDesc d = make_packed(kPR);
+        detail::Packer& Q = next_packer();
+        const ChunkDesc d = make_packed(Q, kPR);
+        took[&Q == &Pw ? 1 : 0] += detail::chunk_cost(d);
         lists[q].push_back(d);
         load[q] += detail::chunk_cost(d);
       }

@@ -108,6 +108,7 @@ void scan(int64_t (&acc)[64], uint64_t sm, int nrow, int b15, int b31) {
 struct Stats {
   int64_t packed = 0, longc = 0, piece = 0, segs = 0, pieces = 0, nwg = 0, panels = 0;
   int64_t cgroups = 0;  // compact groups decoded
+  int64_t wgroups = 0;  // of which wide
 };
 
 // The model of one orientation: gathered vector x (gdim), outputs out_dim.
@@ -146,8 +147,27 @@ std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x
     for (int64_t j = 0; j < wlen; ++j) xl[j] = x[g0 + j];
     // one compact group read by a lane at word ea: first index, pad count,
     // differences; the sum of its entries less the pads' copies of the last
-    auto cgroup = [&](int64_t ea) {
+    auto cgroup = [&](int64_t ea, bool wide) {
       ++st.cgroups;
+      if (wide) {
+        // wide: first index, pad count (byte 3 zero), six 16-bit differences
+        ++st.wgroups;
+        uint16_t wv[8];
+        for (int e = 0; e < 8; ++e) wv[e] = idx.at(ea + e, "idx");
+        const int pads = wv[1] & 0xff;
+        CHECK((wv[1] >> 8) == 0, "wide group byte 3 is %d", wv[1] >> 8);
+        CHECK(pads < kWGroup, "wide pad count %d", pads);
+        int64_t ix = wv[0], sum = 0;
+        for (int e = 0; e < kWGroup; ++e) {
+          if (e > 0) ix += wv[e + 1];
+          CHECK(ix >= 0 && ix < wlen, "index %lld outside the panel's %lld values",
+                (long long)ix, (long long)wlen);
+          CHECK(e < kWGroup - pads || wv[e + 1] == 0 || e == 0, "pad %d moves the index", e);
+          sum += (ix >= 0 && ix <= B.W) ? xl[ix] : 0;
+        }
+        sum -= (int64_t)pads * ((ix >= 0 && ix <= B.W) ? xl[ix] : 0);
+        return sum;
+      }
       uint8_t by[16];
       for (int e = 0; e < 8; ++e) {
         const uint16_t wv = idx.at(ea + e, "idx");
@@ -180,6 +200,8 @@ std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x
       for (int c = c0; c < c1; ++c) {
         const ChunkDesc D = chunks.at(c, "chunks");
         const int R = D.info & 0xff, kind = (D.info >> 8) & 3;
+        const bool wide = (D.info & kChunkWide) != 0;
+        CHECK(compact || !wide, "wide groups in a K-interleaved table");
         last_base = D.base;
         CHECK(R >= 1 && R <= kPLongWin, "windows %d", R);
         int64_t acc[64] = {};
@@ -203,7 +225,7 @@ std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x
               for (int l = 0; l < 64; ++l) {
                 const bool h = (m >> l) & 1ull;
                 const int64_t ea = h ? w0 + (int64_t)below(m, l) * (kPV / 2) : w0;
-                const int64_t v = cgroup(ea);
+                const int64_t v = cgroup(ea, wide);
                 if (h) acc[l] += v;
               }
               pre += ng;
@@ -249,7 +271,7 @@ std::vector<int64_t> run_pass(const PanelBuild& B, const std::vector<int64_t>& x
               const int64_t w0 = D.base + (int64_t)k * 64 * (kPV / 2);
               for (int l = 0; l < 64; ++l) {
                 const bool h = l < ng;
-                const int64_t v = cgroup(h ? w0 + (int64_t)l * (kPV / 2) : w0);
+                const int64_t v = cgroup(h ? w0 + (int64_t)l * (kPV / 2) : w0, wide);
                 if (h) acc[l] += v;
               }
               continue;
@@ -391,10 +413,11 @@ int main(int argc, char** argv) {
   }
   printf("{\"n\": %lld, \"p\": %lld, \"nnz\": %lld, \"packed\": %lld, \"long\": %lld, "
          "\"piece_chunks\": %lld, \"pieces\": %lld, \"segments\": %lld, \"workgroups\": %lld, "
-         "\"panels\": %lld, \"compact_groups\": %lld, \"mismatches\": %lld, "
-         "\"failed_checks\": %d}\n",
+         "\"panels\": %lld, \"compact_groups\": %lld, \"wide_groups\": %lld, "
+         "\"mismatches\": %lld, \"failed_checks\": %d}\n",
          (long long)n, (long long)p, (long long)nnz, (long long)st.packed, (long long)st.longc,
          (long long)st.piece, (long long)st.pieces, (long long)st.segs, (long long)st.nwg,
-         (long long)st.panels, (long long)st.cgroups, (long long)bad, g_fail);
+         (long long)st.panels, (long long)st.cgroups, (long long)st.wgroups, (long long)bad,
+         g_fail);
   return (bad == 0 && g_fail == 0) ? 0 : 1;
 }

@@ -7,8 +7,9 @@ loads of idle lanes and of steps past a wavefront's end, the segmented lane
 sums of packed chunks, the whole-wavefront sums of long chunks and of the
 pieces of segments longer than one wavefront sums whole, the decode of the
 one-vector tables' compact groups (a first index, a pad count and byte
-differences; every index inside the panel) and the consumer's total over
-panels and pieces).  Integer values make every sum exact, so the
+differences, or 16-bit differences in the wide groups of sparse segments;
+every index inside the panel) and the consumer's total over panels and
+pieces).  Integer values make every sum exact, so the
 model's X v and X^T u must equal the direct products element by element.
 The program is built with AddressSanitizer and UndefinedBehaviorSanitizer,
 so a read outside a table is reported by the sanitizer as well as by the
@@ -157,12 +158,12 @@ def test_oracle_size_and_ragged_designs(checker, tmp_path, problem_cache):
 
 def test_compact_groups_of_the_column_law(checker, tmp_path):
     """A column-law design at n = 30,000, p = 6,000 (densities down to 1e-4,
-    so runs with differences beyond 255 cut groups short) and a design of
-    very short columns beside a dense one: the compact groups reproduce X v
-    and X^T u exactly."""
+    so runs with differences beyond 255 cut groups short, and the sparsest
+    columns take wide groups) and a design of very short columns beside a
+    dense one: the compact groups reproduce X v and X^T u exactly."""
     P = synth.scaled_problem(30000, 6000, seed=35)
     st = _run(checker, tmp_path, P.n, P.p, P.row_ptr, P.col_idx)
-    assert st["mismatches"] == 0 and st["compact_groups"] > 0
+    assert st["mismatches"] == 0 and st["compact_groups"] > st["wide_groups"] > 0
     n, p = 300, 21000
     rng = np.random.default_rng(36)
     cols = [np.sort(rng.choice(n, size=int(rng.integers(1, 5)), replace=False))
