@@ -47,11 +47,16 @@ struct Entry {
   bool wide = false;  // compact tables: wide groups (kWGroup entries, 16-bit differences)
 };
 
+// A chunk's share of a wavefront's work, in half windows of compact groups:
+// a window of compact groups issues 14 gathers per lane, one of wide groups
+// 7 (window_cost).
+inline int window_cost(bool wide) { return wide ? 1 : 2; }
 inline int chunk_cost(const ChunkDesc& d) {
-  if (((d.info >> 8) & 3) != kChunkPacked) return d.info & 0xff;
+  const int u = window_cost((d.info & kChunkWide) != 0);
+  if (((d.info >> 8) & 3) != kChunkPacked) return (d.info & 0xff) * u;
   int c = 0;
   for (int k = 0; k < kPR; ++k) c += d.vm[k] ? 1 : 0;
-  return c;
+  return c * u;
 }
 
 // Packed chunks of one panel from its entries sorted by decreasing length:
@@ -267,12 +272,13 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
       if (en.g > packed_max) {
         if (compact) {
           for (int64_t o = 0; o < en.g; o += kPLongGroups)
-            pwin[k] += (std::min<int64_t>(o + kPLongGroups, en.g) - o + 63) / 64;
+            pwin[k] += (std::min<int64_t>(o + kPLongGroups, en.g) - o + 63) / 64 *
+                       detail::window_cost(en.wide);
         } else {
           const int64_t len = en.e - en.a;
           for (int64_t o = 0; o < len; o += kPLongMax) {
             const int64_t ng = (std::min<int64_t>(o + kPLongMax, len) - o + kPV - 1) / kPV;
-            pwin[k] += (ng + 63) / 64;
+            pwin[k] += (ng + 63) / 64 * detail::window_cost(false);
           }
         }
       } else {
@@ -289,8 +295,9 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
         int64_t last = 0;  // windows of the chunk: the longest lane's groups
         for (int32_t i : members)
           last = std::max<int64_t>(last, std::min<int64_t>(ent[k][i].g, kPR));
-        pwin[k] += last;
-        pwin_kind[k][Q == &Pw ? 1 : 0] += last;
+        const int64_t cost = last * detail::window_cost(Q == &Pw);
+        pwin[k] += cost;
+        pwin_kind[k][Q == &Pw ? 1 : 0] += cost;
       }
       Q->hi = Q->order.size();
     }
@@ -368,7 +375,7 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
         }
         const int q = least_loaded();
         lists[q].push_back(d);
-        load[q] += win;
+        load[q] += win * detail::window_cost(en.wide);
       }
       if (pieces) splits.push_back({(int32_t)(en.slot % out_dim), p_first, B.npieces - 1});
     }
@@ -452,7 +459,8 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
             (int64_t)std::llround(per_w * cumw[q + 1]) - (int64_t)std::llround(per_w * cumw[q]);
         while (!all_taken() && load[q] < target) {
           detail::Packer& Q = next_packer();
-          int R = (int)std::min<int64_t>(kPR, target - load[q]);
+          const int u = detail::window_cost(&Q == &Pw);
+          int R = (int)std::min<int64_t>(kPR, (target - load[q] + u - 1) / u);
           R = std::max(R, Q.min_windows());
           const ChunkDesc d = make_packed(Q, R);
           lists[q].push_back(d);
@@ -474,7 +482,7 @@ inline void build_panels(const std::vector<int64_t>& off, const std::vector<int3
       double excess = 0.0;  // most windows any wavefront has above its share
       for (int q = 0; q < nwv; ++q)
         excess = std::max(excess, (double)load[q] - (double)used * wave_weight(q) / cumw[nwv]);
-      if (!leftover && excess <= 2.0) break;
+      if (!leftover && excess <= 2.0 * detail::window_cost(false)) break;
       total = used;
     }
     const int64_t e0 = glo, e1 = std::min<int64_t>(glo + B.W, gdim);
