@@ -169,8 +169,8 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
     return PPCG_OK;
   };
   // The decay of the rule measure over the checked batch predicts how many
-  // iterations after it the solve needs (-1: no prediction, the measure did
-  // not fall).  A batch queued ahead is skipped when the running batch is
+  // iterations after it the solve needs (-1: no prediction, the measure has
+  // not fallen since the start).  A batch queued ahead is skipped when the running batch is
   // predicted to finish the solve (it would only run launches that exit
   // early), and is given the predicted remainder plus one iteration, not the
   // full period, when that is shorter: then few launches run after the stop.
@@ -184,23 +184,35 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
     return h.loop2 > 0.0 ? h.meas / h.loop2 : 0.0;
   };
   const int full = o.check_every;
-  auto predict = [&](double m, double m_prev, int nb) {
-    if (!(m_prev > 0.0 && m < m_prev)) return -1.0;
-    return m <= 1.0 ? 0.0 : nb * std::log(m) / std::log(m_prev / m);
+  // (CG's measure is not monotone: over a short batch it can rise, and the
+  // prediction then falls back to its mean decay since the start, m_start
+  // at iteration 0.)
+  double m_start = 0.0;
+  auto predict = [&](double m, double m_prev, int nb, int done_its) {
+    if (m <= 1.0) return 0.0;
+    if (m_prev > 0.0 && m < m_prev) return nb * std::log(m) / std::log(m_prev / m);
+    if (m_start > 0.0 && m < m_start && done_its > 0)
+      return done_its * std::log(m) / std::log(m_start / m);
+    return -1.0;
   };
-  auto size_for = [&](double left) {
-    if (left < 0.0 || left >= full) return full;
+  auto size_for = [&](double left, int most) {
+    if (left < 0.0 || left >= most) return most;
     const int nb = (int)std::ceil(left) + 1;
-    return nb < full ? nb : full;
+    return nb < most ? nb : most;
   };
   // A sequence of draws on one handle (a Gibbs sampler's) repeats its
   // iteration counts closely, so the first batch runs to kHintShort short
   // of the previous phase's count, with a batch of kHintTail queued behind
-  // it: the first check then comes near the end, the device keeps working
-  // while the host makes it, and the remainder is sized by the prediction.
-  // Without a count the first batch is one period, checked with nothing
-  // queued behind it (a short solve then runs no launches after its stop).
-  constexpr int kHintShort = 2, kHintTail = 3;
+  // it: the first check then comes near the end and the device keeps
+  // working while the host makes it.  Near the end the measure swings by
+  // orders of magnitude from one iteration to the next, so until a quarter
+  // past the previous count the batches stay at most kHintStep long and
+  // one is always queued ahead (a replay of the rule on six FP64 draws at
+  // n = 1e5, p = 2e4: 3.0 launches after the stop per draw against 6.0
+  // with predicted batches).  Without a count the first batch is one
+  // period, checked with nothing queued behind it (a short solve then runs
+  // no launches after its stop).
+  constexpr int kHintShort = 2, kHintTail = 3, kHintStep = 2;
   const int32_t hint = X->iter_hint[phase][ti];
   int first = full;
   if (hint > 0) first = std::max(1, std::min(hint - kHintShort, o.max_iter));
@@ -208,6 +220,7 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
   int rc = enqueue(0, first);
   if (rc) return rc;
   double m_prev = ratio(2);
+  m_start = m_prev;
   int cur = 0;
   bool ahead = hint > 0;
   int next = kHintTail;
@@ -221,14 +234,17 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
       X->iter_hint[phase][ti] = X->h_sc[0].iters;
       return PPCG_OK;
     }
+    const int its = start[cur] + size[cur];  // iterations after batch cur
+    const bool near = hint > 0 && its < hint + hint / 4;
+    const int most = near ? kHintStep : full;
     const double m = ratio(cur);
-    const double left = predict(m, m_prev, size[cur]);  // after batch cur
+    const double left = predict(m, m_prev, size[cur], its);
     m_prev = m;
-    if (!ahead && (rc = enqueue(cur ^ 1, size_for(left)))) return rc;
+    if (!ahead && (rc = enqueue(cur ^ 1, size_for(left, most)))) return rc;
     // batch cur ^ 1 runs next; what the one after it would have to do
     const double after = left < 0.0 ? -1.0 : left - size[cur ^ 1];
-    ahead = !(left >= 0.0 && after <= 0.0);
-    next = size_for(after);
+    ahead = near || !(left >= 0.0 && after <= 0.0);
+    next = size_for(after, most);
     cur ^= 1;
   }
 }
