@@ -467,9 +467,10 @@ int ppcg_batch_create(ppcg_batch** out, int32_t nchains, const ppcg_matrix* cons
  * ppcg_matrix_create; copied).  Each X pass reads X's indices once for a
  * group of K chains: the group's vectors are interleaved and a panel of the
  * gathered vectors holds K values per entry.  K is 2 for up to two chains,
- * else 4 for PPCG_F64 (five to eight chains run as two groups, one pass of
- * each per CG step; a group whose chains have all stopped skips its passes)
- * and 4 or 8 (the next power of two, one group) for PPCG_F32.  Each chain's omega, z, lambda, tau, b and random stream are its
+ * else 4: five to eight chains run as two groups, one pass of each per CG
+ * step, the chains dealt to the groups by falling iteration count of the
+ * previous call (a group whose chains have all stopped skips its passes).
+ * Each chain's omega, z, lambda, tau, b and random stream are its
  * own (ppcg_chain), so the chains' Phi differ and their CG runs are
  * independent (a chain that has converged keeps its result while the
  * others iterate).  Results agree with the single-chain calls to the solver

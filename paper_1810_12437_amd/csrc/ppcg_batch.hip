@@ -612,9 +612,11 @@ int assign_slots(ppcg_batch* B, hipStream_t st) {
   B->chain_at = order;
   for (int32_t sl = 0; sl < B->nch; ++sl) B->slot_of[order[sl]] = sl;
   const std::vector<VecJob<T>> jobs = vec_jobs<T>(B);
+  // on the caller's stream, after the work that read the old table; the
+  // host copy lives until the stream has taken it
+  PPCG_TRY_HIP(hipMemcpyAsync(B->vjobs, jobs.data(), jobs.size() * sizeof(VecJob<T>),
+                              hipMemcpyHostToDevice, st));
   PPCG_TRY_HIP(hipStreamSynchronize(st));
-  PPCG_TRY_HIP(hipMemcpy(B->vjobs, jobs.data(), jobs.size() * sizeof(VecJob<T>),
-                         hipMemcpyHostToDevice));
   drop_graphs(B);
   ++B->lp_version;
   return PPCG_OK;
@@ -872,11 +874,11 @@ int ppcg_batch_create_shared(ppcg_batch** out, int32_t nchains, int64_t n, int64
     B->shared = true;
     B->dtype = dtype;
     B->nch = nchains;
-    // FP64 loops run groups of at most four chains (a pass over eight FP64
-    // vectors needs more registers than a 1024-thread workgroup leaves a
-    // lane, and two four-vector passes measured faster than one with the
-    // spills); FP32 loops run all chains in one group
-    B->K = nchains <= 2 ? 2 : (nchains <= 4 || dtype == PPCG_F64 ? 4 : 8);
+    // Groups of at most four chains: a pass over eight FP64 vectors needs
+    // more registers than a 1024-thread workgroup leaves a lane (two
+    // four-vector passes measured faster than one with the spills), and
+    // with two groups the chains that iterate longest share one
+    B->K = nchains <= 2 ? 2 : 4;
     B->G = (nchains + B->K - 1) / B->K;
     B->n = n;
     B->p = p;
