@@ -63,9 +63,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "921b6ac2afaeec921e2f21b82ef8e29757a1ea84debd24957258805d362075c1",
+    "sources_sha256": "769a0be2fbb314d13f41a7e66e671f337409604d4df0f6c0348a83201c450c17",
     # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
-    "bytes_per_launch": 75564851,
+    "bytes_per_launch": 75555619,
 }
 
 

@@ -279,7 +279,7 @@ hipError_t launch_cg_step(VecWork w, const T* s, int64_t sstride, int parity, bo
                           const double* p2, int32_t n2, int64_t p, hipStream_t st,
                           DevScal* snap = nullptr);
 
-// One X pass over K in {2, 4, 8} interleaved vectors ([dim][K] inputs and
+// One X pass over K in {2, 4} interleaved vectors ([dim][K] inputs and
 // outputs; part_out[(k * out_dim + id) * K + r]); skipped when the K flags
 // done[i * dstride] are all set (done may be null).  dir / dot as for
 // launch_panel_pass, over the K vectors.

@@ -1057,8 +1057,7 @@ static hipError_t set_lds(int bytes) {
   const void* fns[] = {reinterpret_cast<const void*>(&k_panel<T, MODE>),
                        reinterpret_cast<const void*>(&k_panel_b<T, MODE>),
                        reinterpret_cast<const void*>(&k_panel_k<T, 2, MODE>),
-                       reinterpret_cast<const void*>(&k_panel_k<T, 4, MODE>),
-                       reinterpret_cast<const void*>(&k_panel_k<T, 8, MODE>)};
+                       reinterpret_cast<const void*>(&k_panel_k<T, 4, MODE>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -1124,9 +1123,6 @@ hipError_t launch_panel_pass_k(int K, const PanelPass& t, const Combine<T>& x, T
       break;
     case 4:
       PPCG_LAUNCH_M(4)
-      break;
-    case 8:
-      PPCG_LAUNCH_M(8)
       break;
     default:
       return hipErrorInvalidValue;

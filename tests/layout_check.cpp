@@ -386,8 +386,9 @@ int main(int argc, char** argv) {
     }
   Stats st;
   int64_t bad = 0;
-  // 8 and 4: one FP64 or FP32 vector; 16 to 64: the K-interleaved tables of
-  // shared-design batches (K x value size per panel entry)
+  // 8 and 4: one FP64 or FP32 vector; 16 and 32: the K-interleaved tables of
+  // shared-design batches (K x value size per panel entry, K = 2 or 4); 64
+  // checks the builder beyond the widths the library uses
   for (int elem : {8, 4, 16, 32, 64}) {
     PanelBuild Br, Bc;
     // compact groups in the one-vector tables, as the library builds them
