@@ -249,6 +249,29 @@ def scaled_problem(n: int, p: int, seed: int, tau: float = 1e-3,
     return Problem(name, n, p, rp, ci, om, z, lam, float(tau))
 
 
+def gapped_problem(n: int, p: int, seed: int, tau: float = 0.3) -> Problem:
+    """Columns whose consecutive rows lie a drawn gap apart: a third with gaps
+    uniform in [200, 600) (runs cut at gaps above 255), a third with gaps in
+    [256, 4000) (isolated entries), the rest Bernoulli(0.3); stresses the
+    index groups of sparse segments (structure tests)."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for j in range(p):
+        kind = j % 3
+        if kind == 2:
+            r = np.flatnonzero(rng.random(n) < 0.3)
+        else:
+            lo, hi = (200, 600) if kind == 0 else (256, 4000)
+            gaps = rng.integers(lo, hi, size=n // lo + 1)
+            r = np.cumsum(gaps) - gaps[0] + int(rng.integers(0, lo))
+            r = r[r < n]
+        rows.append(r)
+        cols.append(np.full(len(r), j))
+    rp, ci = _csr_from_pairs(n, p, np.concatenate(rows), np.concatenate(cols))
+    om, z, lam = _vectors(n, p, rng)
+    return Problem("gapped", n, p, rp, ci, om, z, lam, float(tau))
+
+
 def tiny_problem(p: int, n: int = 40, rho: float = 0.3, tau: float = 1.0,
                  seed: int = 7) -> Problem:
     """Tiny Bernoulli problems for distribution tests (dense Cholesky is exact)."""

@@ -81,6 +81,9 @@ def structure_cases():
     out.append(("one_col", problem_from_dense(np.ones((7000, 1), bool), 5)))
     # column-law design
     out.append(("column_law", synth.scaled_problem(4000, 900, seed=6)))
+    # sparse columns: runs cut at gaps above 255 and isolated entries (wide
+    # index groups) beside dense columns
+    out.append(("gapped", synth.gapped_problem(12000, 400, seed=8)))
     return out
 
 

@@ -172,3 +172,13 @@ def test_compact_groups_of_the_column_law(checker, tmp_path):
     rp, ci = _csr_from_columns(n, p, cols)
     st = _run(checker, tmp_path, n, p, rp, ci)
     assert st["mismatches"] == 0
+
+
+def test_wide_groups_of_gapped_columns(checker, tmp_path):
+    """Columns whose rows lie 200 to 600 apart (runs the 255 limit cuts) or
+    256 to 4000 apart (isolated entries) beside Bernoulli(0.3) columns: the
+    sparse ones take wide groups (16-bit differences), chunks of both kinds
+    interleave, and the model reproduces X v and X^T u exactly."""
+    P = synth.gapped_problem(12000, 400, seed=8)
+    st = _run(checker, tmp_path, P.n, P.p, P.row_ptr, P.col_idx)
+    assert st["mismatches"] == 0 and st["wide_groups"] > 1000
