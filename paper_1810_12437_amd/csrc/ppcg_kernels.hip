@@ -487,12 +487,19 @@ __device__ __forceinline__ void finish_chunk(int32_t info, uint64_t sm, T (&acc)
 // ---- panel assembly, FP64 single-vector fast paths ----
 template <typename T, int K>
 constexpr bool kFastPanel = sizeof(T) == 8 && K == 1;
+// the direction panel's fast path: one vector, FP64 or FP32 values
+template <typename T, int K>
+constexpr bool kFastDir = K == 1;
 constexpr int kAsmPairs = 10;  // 16-byte loads per thread: kPThreads * 2 * 10 >= W
 
 __device__ __forceinline__ bool aligned16(const void* p) {
   return ((uintptr_t)p & 15u) == 0;
 }
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { typedef f64x2 type; };
+template <> struct Pair2<float> { typedef f32x2 type; };
 
 // Pair u of thread tid of a panel assembly: pair tid + b kPThreads of block
 // b = (u + w) mod nb (nb blocks of kPThreads pairs), so that the workgroups
@@ -504,20 +511,27 @@ __device__ __forceinline__ int asm_pair(int u, int tid, int rb, int nb, int npai
   return (u < nb && pl < npairs) ? pl : -1;
 }
 
-// The loads of the FP64 direction panel, held in registers so that they are
-// in flight while the pass finishes the previous step (the ratio bc is not
-// needed until the stores).  False (nothing loaded) when the panel is not
-// 16-byte aligned or shorter than two entries.
+// The loads of the direction panel (z in FP64, the old direction in the
+// pass's type), held in registers so that they are in flight while the pass
+// finishes the previous step (the ratio bc is not needed until the stores).
+// False (nothing loaded) when the panel is not aligned for pair loads, is
+// shorter than two entries or holds more pairs than kAsmPairs per thread
+// (FP32 panels beyond 20,480 entries).
+template <typename T>
 struct DirFast {
-  f64x2 zv[kAsmPairs], sv[kAsmPairs];
+  f64x2 zv[kAsmPairs];
+  typename Pair2<T>::type sv[kAsmPairs];
   int pi[kAsmPairs];
-  double zt, st;
+  double zt;
+  T st;
 };
-__device__ __forceinline__ bool dir_fast_load(DirFast& L, const double* zp, const double* sp,
+template <typename T>
+__device__ __forceinline__ bool dir_fast_load(DirFast<T>& L, const double* zp, const T* sp,
                                               int wlen, int w) {
   const int npairs = wlen >> 1;
-  if (npairs < 1 || !aligned16(zp) || !aligned16(sp)) return false;
+  if (npairs < 1 || !aligned16(zp) || ((uintptr_t)sp & (2 * sizeof(T) - 1)) != 0) return false;
   const int nb = (npairs + kPThreads - 1) / kPThreads;
+  if (nb > kAsmPairs) return false;
   const int rb = w % nb;
   const int tid = threadIdx.x;
 #pragma unroll
@@ -525,7 +539,7 @@ __device__ __forceinline__ bool dir_fast_load(DirFast& L, const double* zp, cons
     L.pi[u] = asm_pair(u, tid, rb, nb, npairs);
     const int at = L.pi[u] >= 0 ? 2 * L.pi[u] : 0;
     L.zv[u] = *gview(reinterpret_cast<const f64x2*>(zp + at));
-    L.sv[u] = *gview(reinterpret_cast<const f64x2*>(sp + at));
+    L.sv[u] = *gview(reinterpret_cast<const typename Pair2<T>::type*>(sp + at));
   }
   // The odd entry, when wlen is odd (thread 0 stores it): a per-lane address
   // (entry 0 elsewhere), so that these are vector loads in flight with the
@@ -540,12 +554,12 @@ __device__ __forceinline__ bool dir_fast_load(DirFast& L, const double* zp, cons
 // entries go to LDS, the ring is primed, then the second half; an odd last
 // entry is stored by thread 0.  (The workgroup's own entries go to s_new
 // after the pass, from LDS.)
-template <typename PRIME>
-__device__ __forceinline__ void dir_fast_store(const DirFast& L, double bc, int wlen, double* xl,
+template <typename T, typename PRIME>
+__device__ __forceinline__ void dir_fast_store(const DirFast<T>& L, double bc, int wlen, T* xl,
                                                PRIME& prime) {
   const int tid = threadIdx.x;
   const int last = wlen - 1;
-  auto form = [&](double z, double so) { return bc == 0.0 ? z : z + bc * so; };
+  auto form = [&](double z, T so) { return (T)(bc == 0.0 ? z : z + bc * (double)so); };
 #pragma unroll
   for (int u = 0; u < kAsmPairs / 2; ++u) {
     if (L.pi[u] >= 0) {
@@ -665,9 +679,9 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   const int64_t g0 = (int64_t)panel * t.W;
   const int64_t rem = t.gdim - g0;
   const int wlen = (int)(rem < t.W ? rem : t.W);
-  DirFast dfl;
+  DirFast<T> dfl;
   bool dfl_ok = false;
-  if constexpr (MODE == kPassDir && kFastPanel<T, K>) {
+  if constexpr (MODE == kPassDir && kFastDir<T, K>) {
     const T* s_old = dir.s + (int64_t)parity * dir.sstride;
     dfl_ok = dir_fast_load(dfl, dir.z + g0, s_old + g0, wlen, w);
   }
@@ -766,18 +780,17 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   const T* sdot = dotting ? dot.s + (int64_t)(1 - parity) * dot.sstride : nullptr;
   const int64_t pofs = (int64_t)panel * t.out_dim;
   bool assembled = false;
-  if constexpr (kFastPanel<T, K>) {
-    // FP64, one vector: every thread's 16-byte loads issued at once, then
-    // the ring's first windows, then the LDS stores.
-    if constexpr (MODE == kPassDir) {
-      if (dfl_ok) {
-        dir_fast_store(dfl, bc0, wlen, xl, prime);
-        assembled = true;
-      }
-    } else if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr &&
-               xin.es == 1) {
-      assembled = assemble_copy_fast(xin.part + g0, wlen, w, xl, prime);
+  if constexpr (MODE == kPassDir && kFastDir<T, K>) {
+    // one vector: every thread's pair loads issued at once, then the ring's
+    // first windows, then the LDS stores
+    if (dfl_ok) {
+      dir_fast_store(dfl, bc0, wlen, xl, prime);
+      assembled = true;
     }
+  } else if constexpr (MODE != kPassDir && kFastPanel<T, K>) {
+    // FP64, one vector: the same for a copied panel
+    if (xin.nparts == 1 && xin.scale == nullptr && xin.sp_off == nullptr && xin.es == 1)
+      assembled = assemble_copy_fast(xin.part + g0, wlen, w, xl, prime);
   }
   if (assembled) {
     // panel done (the ring is primed)
@@ -937,7 +950,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
       }
     }
   }
-  if constexpr (MODE == kPassDir && kFastPanel<T, K>) {
+  if constexpr (MODE == kPassDir && kFastDir<T, K>) {
     if (assembled) {
       // the workgroup's own entries of the new direction, from the panel
       const int64_t o0 = read_table(t.wg_s0, w), o1 = read_table(t.wg_s1, w);
