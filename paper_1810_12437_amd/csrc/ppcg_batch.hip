@@ -108,9 +108,10 @@ struct ppcg_batch {
   int64_t g_version = -1;
   int32_t g_every = 0, g_elem = 0;
   // shared form: every chain on one design, K interleaved vectors per pass,
-  // in G groups of K chains (chain c is slot c % K of group c / K); each
-  // group's arrays follow the previous group's, and the groups' passes run
-  // one after the other through the same tables and partial buffers
+  // in G groups of K vector slots (slot s is position s % K of group s / K;
+  // chain c sits in slot slot_of[c]); each group's arrays follow the
+  // previous group's, and the groups' passes run one after the other
+  // through the same tables and partial buffers
   bool shared = false;
   int32_t K = 1, G = 1;
   int64_t n = 0, p = 0;
@@ -597,8 +598,8 @@ int sync_all(ppcg_batch* B, hipStream_t st) {
 // Shared form with two groups: chains dealt to slots by falling iteration
 // count of the last call (ties by chain), so that the longest-iterating
 // chains share a group and the other group stops early.  A new assignment
-// rewrites the step's job table in place (the stream is idle between calls)
-// and drops the captured graphs.  The slot does not change a chain's
+// rewrites the step's job table in place (ordered on the caller's stream
+// after the work that read it) and drops the captured graphs.  The slot does not change a chain's
 // arithmetic: every slot of a group is summed the same way.
 template <typename T>
 int assign_slots(ppcg_batch* B, hipStream_t st) {
