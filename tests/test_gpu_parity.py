@@ -245,6 +245,34 @@ def test_profile_samples_leave_draw_unchanged(problem_cache):
     assert st2["csr_ms"] > st["csr_ms"] and st2["csc_ms"] > st["csc_ms"]
 
 
+def test_first_batch_from_an_unlike_earlier_solve(problem_cache):
+    """The first check batch of a solve is sized from the handle's previous
+    solve.  When that one needed far more iterations (a draw at tol 1e-10)
+    than this one (a solve warm-started near its solution), the batch runs
+    past the stop: the launches after it return at once, and the result and
+    iteration count equal a fresh handle's; and the reverse order (a short
+    solve first) checks early and runs on to the same draw."""
+    P = problem_cache("c0")
+    args = (t64(P.omega), t64(P.z), t64(P.lam), P.tau, 3, 1, 4)
+    Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
+    rng = np.random.default_rng(21)
+    beta_true = rng.standard_normal(P.p)
+    b = R.phi_matvec(Xs, P.omega, P.lam, P.tau, beta_true)
+    beta0 = beta_true + 1e-7 * rng.standard_normal(P.p)
+    solve_args = (t64(P.omega), t64(P.lam), P.tau, t64(b))
+    ref_d, ref_di = pk.draw(pk.Matrix.from_problem(P), *args, tol=1e-10)
+    ref_s, ref_si = pk.solve(pk.Matrix.from_problem(P), *solve_args, beta0=t64(beta0), tol=1e-8)
+    X = pk.Matrix.from_problem(P)
+    d1, i1 = pk.draw(X, *args, tol=1e-10)
+    s1, j1 = pk.solve(X, *solve_args, beta0=t64(beta0), tol=1e-8)
+    d2, i2 = pk.draw(X, *args, tol=1e-10)
+    say(f"[hint] draw {ref_di['iters']} iterations, warm solve {ref_si['iters']}")
+    assert ref_di["iters"] > 5 * max(ref_si["iters"], 1)
+    assert torch.equal(s1, ref_s) and j1["iters"] == ref_si["iters"]
+    assert torch.equal(d1, ref_d) and torch.equal(d2, ref_d)
+    assert i1["iters"] == i2["iters"] == ref_di["iters"]
+
+
 @pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
 def test_check_period_leaves_draw_unchanged(f32):
     """The host's check batches (their period, the shortened batch queued when
