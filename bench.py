@@ -63,9 +63,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "3e1d13b82afb396cbd29c4fd456101abe93177e792e824dfe431576e9aa87ca0",
+    "sources_sha256": "2f4c339448a9b51cf1de22d91ad4ec9c46d1c8e9662e404d27e2da337d655934",
     # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
-    "bytes_per_launch": 75586935,
+    "bytes_per_launch": 75586010,
 }
 
 

@@ -439,7 +439,7 @@ int ppcg_matrix_stats(const ppcg_matrix* X, double* csr_ms, int64_t* csr_launche
 
 /*
  * Algorithmic bytes of one launch of each X pass in the handle's format for
- * vectors of `dtype`: the 16-bit index stream with its chunk padding, the
+ * vectors of `dtype`: the index stream (16-byte groups) with its padding, the
  * per-chunk tables, segment boundaries and output slots, the gathered
  * vector read once, and the per-panel partial outputs.  Host-only.
  */

@@ -19,15 +19,16 @@ constexpr int kMaxRedBlocks = 1024; // max workgroups of a p-vector phase
 // w -> X^T w) in a panel-blocked, index-only layout.  The gathered
 // dimension is cut into panels of at most W entries so that a panel of the
 // gathered vector fits in LDS; the elements of each (segment, panel) pair are
-// stored as 16-bit indices local to the panel, in groups of kPV padded with
-// the index W (an LDS zero).  Chunks (ChunkDesc, ppcg_layout.h) are the units
+// stored as indices local to the panel, in 16-byte groups (ppcg_layout.h:
+// compact or wide groups for one vector, kPV 16-bit indices padded with the
+// index W, an LDS zero, for K interleaved vectors).  Chunks (ChunkDesc, ppcg_layout.h) are the units
 // a wavefront reads: packed chunks give each of their segments a lane range
 // for up to kPR windows, long chunks run one segment over up to kPLongWin
 // windows, and pieces are parts of a longer segment whose sums the consumer
 // adds.  Workgroup w serves panel wg_panel[w]; its wavefront q runs the
 // chunks [wave_c[kPWaves w + q], wave_c[kPWaves w + q + 1]) in order.
 struct PanelPass {
-  const uint16_t* idx;      // [stream] panel-local gathered index (padded)
+  const uint16_t* idx;      // [stream] 16-bit words of the index groups
   const ChunkDesc* chunks;  // [nchunks]
   const int32_t* seg_out;   // [entries + 1] output slot = panel * out_dim + segment id;
                             // entry no_slot (the last) is -1: no output

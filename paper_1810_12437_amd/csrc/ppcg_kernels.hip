@@ -7,8 +7,10 @@
 //   dot phase   : <s, q + d .* s>  ->  alpha
 //   update      : beta += alpha s, r -= alpha (q + d s), rho' = <r, M^-1 r>
 //   direction   : s = M^-1 r + (rho'/rho) s
-// X is binary, so both passes are segmented gather-sums over 16-bit
-// panel-local index streams with no value array: a workgroup holds one panel
+// X is binary, so both passes are segmented gather-sums over panel-local
+// index streams with no value array (16-byte groups of byte or 16-bit
+// differences for one vector, 16-bit indices for K interleaved vectors;
+// ppcg_layout.h): a workgroup holds one panel
 // of the gathered vector in LDS, each wavefront runs its own list of chunks,
 // every lane of a chunk sums groups of one segment across the chunk's
 // windows, and one DPP segmented scan per chunk combines the lanes of each
@@ -143,21 +145,6 @@ __device__ __forceinline__ T combine_at(const Combine<T>& c, int64_t i, int r = 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// LDS address of the entry in the low / high 16 bits of w, for ES-byte
-// entries of a panel at LDS address lds0: the 16-bit half times ES plus lds0
-// in one multiply-add.
-template <int ES>
-__device__ __forceinline__ uint32_t lo_addr(uint32_t w, uint32_t lds0) {
-  uint32_t r;
-  asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(w), "n"(ES), "s"(lds0));
-  return r;
-}
-template <int ES>
-__device__ __forceinline__ uint32_t hi_addr(uint32_t w, uint32_t lds0) {
-  uint32_t r;
-  asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(r) : "v"(w), "n"(ES), "s"(lds0));
-  return r;
-}
 typedef __attribute__((address_space(3))) unsigned char lds_u8;
 __device__ __forceinline__ uint32_t lds_addr(const void* p) {
   return (uint32_t)(size_t)(const lds_u8*)p;
@@ -318,48 +305,27 @@ struct alignas(sizeof(T) * K) PanelEntry {
   T v[K];
 };
 
-// Adds this lane's group of kPV elements to acc (per vector), in element
-// order.
+// Adds this lane's group of kPV elements to acc (per vector, K > 1
+// interleaved vectors), in element order.
 template <typename T, int K>
 __device__ __forceinline__ void gather_add16(const T* xl, const u16x8& a, const u16x8& b,
                                              T (&acc)[K]) {
-  if constexpr (K == 1) {
-    // All sixteen gathers in flight, then a pairwise sum.  Each index dword
-    // holds two 16-bit entries: one multiply-add of a half by the entry size
-    // gives its LDS byte offset.
-    const u32x4 da = __builtin_bit_cast(u32x4, a), db = __builtin_bit_cast(u32x4, b);
-    const uint32_t l0 = __builtin_amdgcn_readfirstlane(lds_addr(xl));
-    T v[16];
+  static_assert(K > 1, "one vector reads compact groups (gather_cmp, gather_wide)");
+  const PanelEntry<T, K>* xp = reinterpret_cast<const PanelEntry<T, K>*>(xl);
+  T s[K];
+  {
+    const PanelEntry<T, K> u = xp[a[0]];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t wa = da[j], wb = db[j];
-      v[2 * j] = lds_load<T>(lo_addr<sizeof(T)>(wa, l0));
-      v[2 * j + 1] = lds_load<T>(hi_addr<sizeof(T)>(wa, l0));
-      v[8 + 2 * j] = lds_load<T>(lo_addr<sizeof(T)>(wb, l0));
-      v[8 + 2 * j + 1] = lds_load<T>(hi_addr<sizeof(T)>(wb, l0));
-    }
-#pragma unroll
-    for (int w = 1; w < 16; w *= 2)
-#pragma unroll
-      for (int j = 0; j < 16; j += 2 * w) v[j] += v[j + w];
-    acc[0] += v[0];
-  } else {
-    const PanelEntry<T, K>* xp = reinterpret_cast<const PanelEntry<T, K>*>(xl);
-    T s[K];
-    {
-      const PanelEntry<T, K> u = xp[a[0]];
-#pragma unroll
-      for (int r = 0; r < K; ++r) s[r] = u.v[r];
-    }
-#pragma unroll
-    for (int j = 1; j < kPV; ++j) {
-      const PanelEntry<T, K> u = xp[j < 8 ? a[j] : b[j - 8]];
-#pragma unroll
-      for (int r = 0; r < K; ++r) s[r] += u.v[r];
-    }
-#pragma unroll
-    for (int r = 0; r < K; ++r) acc[r] += s[r];
+    for (int r = 0; r < K; ++r) s[r] = u.v[r];
   }
+#pragma unroll
+  for (int j = 1; j < kPV; ++j) {
+    const PanelEntry<T, K> u = xp[j < 8 ? a[j] : b[j - 8]];
+#pragma unroll
+    for (int r = 0; r < K; ++r) s[r] += u.v[r];
+  }
+#pragma unroll
+  for (int r = 0; r < K; ++r) acc[r] += s[r];
 }
 
 // Adds this lane's compact group (ppcg_layout.h) to acc: its first index
