@@ -447,7 +447,9 @@ int ppcg_matrix_pass_bytes(const ppcg_matrix* X, int32_t dtype, int64_t* row_pas
                            int64_t* col_pass_bytes);
 
 /*
- * Many chains at once.  A batch binds C chains, chain c to the design X[c]
+ * Many chains at once (independent Gibbs chains, each drawing as Prop 2.1
+ * by the prior-preconditioned CG of Section 2.4 and Supplement S2; the
+ * paper runs one).  A batch binds C chains, chain c to the design X[c]
  * (the same handle may serve several chains; sizes may differ between
  * chains).  Each call runs every chain's CG with the per-iteration phases of
  * all chains issued as one launch each (X passes, inner products, updates):
@@ -464,7 +466,8 @@ int ppcg_batch_create(ppcg_batch** out, int32_t nchains, const ppcg_matrix* cons
 
 /*
  * A batch of nchains (1..8) chains on ONE design X (given as for
- * ppcg_matrix_create; copied).  Each X pass reads X's indices once for a
+ * ppcg_matrix_create; copied), each drawing as Prop 2.1 with its own omega,
+ * lambda and tau.  Each X pass reads X's indices once for a
  * group of K chains: the group's vectors are interleaved and a panel of the
  * gathered vectors holds K values per entry.  K is 2 for up to two chains,
  * else 4: five to eight chains run as two groups, one pass of each per CG
