@@ -219,6 +219,22 @@ def test_restart_steps_match_oracle(name, P, dt):
     check_restart_steps(name, Oracle(P, d, m, dt), gpu_steps(X, P, dt), b, starts, dt)
 
 
+@pytest.mark.parametrize("p", [20481, 20482])
+def test_fp32_direction_panel_at_the_fast_path_limit(p):
+    """The FP32 row pass forms its direction panel from every thread's pair
+    loads in one go while the panel holds at most 1024 x 10 pairs (20,481
+    entries: the last pairs plus the odd entry) and by the general loop
+    beyond (20,482): restart steps against the oracle on both sides, FP32
+    and FP64."""
+    P = synth.scaled_problem(1500, p, seed=40 + p % 2, tau=0.01)
+    X = pk.Matrix.from_problem(P)
+    b = draw_rhs(P)
+    starts = [("zero", None)] + oracle_iterates(P, b, (5,))
+    for dt in (pk.F32, pk.F64):
+        d, m = shrinkage(P, dt)
+        check_restart_steps(f"p={p}", Oracle(P, d, m, dt), gpu_steps(X, P, dt), b, starts, dt)
+
+
 @pytest.mark.parametrize("name", ["c0", "column_law", "empties", "intercept_40k"])
 def test_fixed_counts_from_zero_match_oracle(name):
     """K iterations from zero (tol 0, max_iter K) for K up to twice the count
