@@ -86,9 +86,10 @@ int sync_scal(ppcg_matrix* X, hipStream_t st) {
 // back into the other pinned slot), so the device does not idle while the
 // host checks.  `phase` (0: first solve, 1: refinement restart) selects the
 // iteration count of the handle's previous phase of that kind, which sizes
-// the first batch (see below).
+// the first batch (see below) unless `hinted` is false (a warm start, whose
+// count the previous solve does not predict).
 template <typename T>
-int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
+int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase, bool hinted,
              hipStream_t st) {
   const int ti = prec_index<T>();
   T* s = Bufs<T>::s(X);
@@ -213,7 +214,7 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
   // period, checked with nothing queued behind it (a short solve then runs
   // no launches after its stop).
   constexpr int kHintShort = 2, kHintTail = 3, kHintStep = 2;
-  const int32_t hint = X->iter_hint[phase][ti];
+  const int32_t hint = hinted ? X->iter_hint[phase][ti] : 0;
   int first = full;
   if (hint > 0) first = std::max(1, std::min(hint - kHintShort, o.max_iter));
   bool fin = false;
@@ -231,7 +232,8 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
       // a batch queued ahead exits launch by launch; the scalars no longer change
       if (ahead) PPCG_TRY_HIP(hipStreamSynchronize(st));
       if (cur != 0) X->h_sc[0] = X->h_sc[cur];
-      X->iter_hint[phase][ti] = X->h_sc[0].iters;
+      // (a run that hit its cap or broke down predicts nothing)
+      X->iter_hint[phase][ti] = X->h_sc[0].status == PPCG_OK ? X->h_sc[0].iters : 0;
       return PPCG_OK;
     }
     const int its = start[cur] + size[cur];  // iterations after batch cur
@@ -268,7 +270,7 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
       o.loop_factor > 0.0 ? o.loop_factor : ((sizeof(T) == 4) ? 0.5 : 1.0);
   PPCG_TRY_HIP(launch_cg_start(w, 0, X->b64, qx0, X->d, X->m, X->beta64, X->r64, X->z64, X->p,
                              o.tol, o.criterion, o.max_iter, loop_factor, st, &X->h_sc[2]));
-  int rc = run_loop<T>(X, omegaT, o, 0, st);
+  int rc = run_loop<T>(X, omegaT, o, 0, !have_beta0, st);
   if (rc) return rc;
   ppcg_info inf{};
   inf.status = X->h_sc->status;
@@ -294,7 +296,7 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
       PPCG_TRY_HIP(launch_cg_start(w, 1, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, X->z64,
                              X->p, o.tol, o.criterion, o.max_iter, loop_factor, st,
                              &X->h_sc[2]));
-      rc = run_loop<T>(X, omegaT, o, 1, st);
+      rc = run_loop<T>(X, omegaT, o, 1, true, st);
       if (rc) return rc;
       inf.refined = 1;
       inf.refine_iters = X->h_sc->iters;

@@ -247,11 +247,13 @@ def test_profile_samples_leave_draw_unchanged(problem_cache):
 
 def test_first_batch_from_an_unlike_earlier_solve(problem_cache):
     """The first check batch of a solve is sized from the handle's previous
-    solve.  When that one needed far more iterations (a draw at tol 1e-10)
-    than this one (a solve warm-started near its solution), the batch runs
+    converged solve.  When that one needed far more iterations (a draw at
+    tol 1e-10) than this one (a solve from zero at tol 1e-2), the batch runs
     past the stop: the launches after it return at once, and the result and
-    iteration count equal a fresh handle's; and the reverse order (a short
-    solve first) checks early and runs on to the same draw."""
+    iteration count equal a fresh handle's; in the reverse order (the short
+    solve first) the draw checks early and runs on to the same result.  A
+    warm-started solve does not take the count: it equals a fresh handle's
+    too."""
     P = problem_cache("c0")
     args = (t64(P.omega), t64(P.z), t64(P.lam), P.tau, 3, 1, 4)
     Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
@@ -260,17 +262,22 @@ def test_first_batch_from_an_unlike_earlier_solve(problem_cache):
     b = R.phi_matvec(Xs, P.omega, P.lam, P.tau, beta_true)
     beta0 = beta_true + 1e-7 * rng.standard_normal(P.p)
     solve_args = (t64(P.omega), t64(P.lam), P.tau, t64(b))
-    ref_d, ref_di = pk.draw(pk.Matrix.from_problem(P), *args, tol=1e-10)
-    ref_s, ref_si = pk.solve(pk.Matrix.from_problem(P), *solve_args, beta0=t64(beta0), tol=1e-8)
-    X = pk.Matrix.from_problem(P)
+    fresh = lambda: pk.Matrix.from_problem(P)  # noqa: E731
+    ref_d, ref_di = pk.draw(fresh(), *args, tol=1e-10)
+    ref_s, ref_si = pk.solve(fresh(), *solve_args, tol=1e-2)
+    ref_w, ref_wi = pk.solve(fresh(), *solve_args, beta0=t64(beta0), tol=1e-8)
+    X = fresh()
     d1, i1 = pk.draw(X, *args, tol=1e-10)
-    s1, j1 = pk.solve(X, *solve_args, beta0=t64(beta0), tol=1e-8)
+    s1, j1 = pk.solve(X, *solve_args, tol=1e-2)
     d2, i2 = pk.draw(X, *args, tol=1e-10)
-    say(f"[hint] draw {ref_di['iters']} iterations, warm solve {ref_si['iters']}")
-    assert ref_di["iters"] > 5 * max(ref_si["iters"], 1)
+    w1, k1 = pk.solve(X, *solve_args, beta0=t64(beta0), tol=1e-8)
+    say(f"[hint] draw {ref_di['iters']} iterations, loose solve {ref_si['iters']}, "
+        f"warm solve {ref_wi['iters']}")
+    assert ref_di["iters"] > 3 * max(ref_si["iters"], 1)
     assert torch.equal(s1, ref_s) and j1["iters"] == ref_si["iters"]
     assert torch.equal(d1, ref_d) and torch.equal(d2, ref_d)
     assert i1["iters"] == i2["iters"] == ref_di["iters"]
+    assert torch.equal(w1, ref_w) and k1["iters"] == ref_wi["iters"]
 
 
 @pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
