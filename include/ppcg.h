@@ -92,12 +92,12 @@ typedef struct ppcg_options {
                          a batch queued when the decay of the rule measure
                          predicts the end within one period is shortened to
                          the predicted remainder plus one iteration.  The
-                         first batch of a solve phase (first solve or
-                         refinement restart) runs to 2 iterations short of
-                         the same handle's previous phase of that kind and
+                         first batch of a solve phase (first solve from
+                         zero, first solve from a given beta0, refinement
+                         restart) runs to 2 iterations short of the same
+                         handle's previous phase of that kind and
                          precision, with 3 more queued behind it, when that
-                         phase converged (a warm-started first phase does
-                         not use it); results do not depend on batching */
+                         phase converged; results do not depend on batching */
   double loop_factor; /* the recursion runs to loop_factor * tol before the FP64
                          check (0: default, 0.5 for F32 and 1 for F64)         */
   int32_t no_graph;   /* batched loops: 0 (default) replays each check batch as a

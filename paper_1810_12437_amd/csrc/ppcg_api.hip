@@ -84,12 +84,12 @@ int sync_scal(ppcg_matrix* X, hipStream_t st) {
 // iterations (fewer near the predicted end, see below).  The next batch is
 // normally already queued when the host waits for a batch's flag (read
 // back into the other pinned slot), so the device does not idle while the
-// host checks.  `phase` (0: first solve, 1: refinement restart) selects the
-// iteration count of the handle's previous phase of that kind, which sizes
-// the first batch (see below) unless `hinted` is false (a warm start, whose
-// count the previous solve does not predict).
+// host checks.  `phase` (0: first solve from zero, 1: first solve from a
+// caller's start vector, 2: refinement restart) selects the iteration count
+// of the handle's previous phase of that kind, which sizes the first batch
+// (see below).
 template <typename T>
-int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase, bool hinted,
+int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase,
              hipStream_t st) {
   const int ti = prec_index<T>();
   T* s = Bufs<T>::s(X);
@@ -214,7 +214,7 @@ int run_loop(ppcg_matrix* X, const T* omegaT, const ppcg_options& o, int phase, 
   // period, checked with nothing queued behind it (a short solve then runs
   // no launches after its stop).
   constexpr int kHintShort = 2, kHintTail = 3, kHintStep = 2;
-  const int32_t hint = hinted ? X->iter_hint[phase][ti] : 0;
+  const int32_t hint = X->iter_hint[phase][ti];
   int first = full;
   if (hint > 0) first = std::max(1, std::min(hint - kHintShort, o.max_iter));
   bool fin = false;
@@ -270,7 +270,7 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
       o.loop_factor > 0.0 ? o.loop_factor : ((sizeof(T) == 4) ? 0.5 : 1.0);
   PPCG_TRY_HIP(launch_cg_start(w, 0, X->b64, qx0, X->d, X->m, X->beta64, X->r64, X->z64, X->p,
                              o.tol, o.criterion, o.max_iter, loop_factor, st, &X->h_sc[2]));
-  int rc = run_loop<T>(X, omegaT, o, 0, !have_beta0, st);
+  int rc = run_loop<T>(X, omegaT, o, have_beta0 ? 1 : 0, st);
   if (rc) return rc;
   ppcg_info inf{};
   inf.status = X->h_sc->status;
@@ -296,7 +296,7 @@ int solve_core(ppcg_matrix* X, const T* omegaT, const double* omega64, bool have
       PPCG_TRY_HIP(launch_cg_start(w, 1, X->b64, X->qx64, X->d, X->m, X->beta64, X->r64, X->z64,
                              X->p, o.tol, o.criterion, o.max_iter, loop_factor, st,
                              &X->h_sc[2]));
-      rc = run_loop<T>(X, omegaT, o, 1, true, st);
+      rc = run_loop<T>(X, omegaT, o, 2, st);
       if (rc) return rc;
       inf.refined = 1;
       inf.refine_iters = X->h_sc->iters;

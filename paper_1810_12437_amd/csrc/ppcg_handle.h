@@ -67,9 +67,10 @@ struct ppcg_matrix {
   ppcg::DevScal* h_sc = nullptr;  // pinned host mirror: [0] the result, [0..1] check slots,
                                   // [2] the scalars a start left
   hipEvent_t chk[2] = {};         // one per check slot: that batch's flags are on the host
-  // CG iterations of the last solve phase, [phase: 0 first, 1 refinement][table]: the
-  // first check batch of the next such phase is sized from it (0: none yet)
-  int32_t iter_hint[2][2] = {{0, 0}, {0, 0}};
+  // CG iterations of the last converged solve phase, [phase: 0 first from zero, 1 first
+  // from a caller's beta0, 2 refinement][table]: the first check batch of the next such
+  // phase is sized from it (0: none)
+  int32_t iter_hint[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   // pass timing (ppcg_matrix_profile)
   int profile = 0;
   std::vector<hipEvent_t> ev;  // 4 per iteration of a check batch

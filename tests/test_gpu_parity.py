@@ -252,8 +252,8 @@ def test_first_batch_from_an_unlike_earlier_solve(problem_cache):
     past the stop: the launches after it return at once, and the result and
     iteration count equal a fresh handle's; in the reverse order (the short
     solve first) the draw checks early and runs on to the same result.  A
-    warm-started solve does not take the count: it equals a fresh handle's
-    too."""
+    warm-started solve takes only a warm-started solve's count (none here):
+    it equals a fresh handle's too."""
     P = problem_cache("c0")
     args = (t64(P.omega), t64(P.z), t64(P.lam), P.tau, 3, 1, 4)
     Xs = R.csr_matrix(P.n, P.p, P.row_ptr, P.col_idx)
