@@ -581,8 +581,8 @@ def run_batched(args):
 
 def shared_summary(pk, torch, P, X, steps, warmup, tol, no_f32=False):
     """8 chains on the design of P (handle X for the single-chain path), each
-    with its own omega, z, lambda, tau and stream; every X pass serves all 8
-    (K = 8 interleaved vectors).  Per form: chain-draws/s over `steps`
+    with its own omega, z, lambda, tau and stream; every X pass serves one
+    group of four (K = 4 interleaved vectors).  Per form: chain-draws/s over `steps`
     batched draws against the same chains drawn one at a time."""
     import synth
 
