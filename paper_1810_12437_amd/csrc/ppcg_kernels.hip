@@ -480,9 +480,13 @@ __device__ __forceinline__ int asm_pair(int u, int tid, int rb, int nb, int npai
 // The loads of the direction panel (z in FP64, the old direction in the
 // pass's type), held in registers so that they are in flight while the pass
 // finishes the previous step (the ratio bc is not needed until the stores).
-// False (nothing loaded) when the panel is not aligned for pair loads, is
-// shorter than two entries or holds more pairs than kAsmPairs per thread
-// (FP32 panels beyond 20,480 entries).
+// False when the panel is not aligned for pair loads, is shorter than two
+// entries or holds more pairs than kAsmPairs per thread (FP32 panels beyond
+// 20,480 entries); the same loads are issued then too, all from the first
+// 16 bytes of `safe` (16 readable bytes on a 16-byte boundary), so that no
+// branch joins paths with different numbers of loads in flight: the waits
+// for the loads issued before these (the step's partials) then count them
+// exactly, instead of waiting for the whole panel.
 template <typename T>
 struct DirFast {
   f64x2 zv[kAsmPairs];
@@ -493,27 +497,30 @@ struct DirFast {
 };
 template <typename T>
 __device__ __forceinline__ bool dir_fast_load(DirFast<T>& L, const double* zp, const T* sp,
-                                              int wlen, int w) {
+                                              int wlen, int w, const void* safe) {
   const int npairs = wlen >> 1;
-  if (npairs < 1 || !aligned16(zp) || ((uintptr_t)sp & (2 * sizeof(T) - 1)) != 0) return false;
-  const int nb = (npairs + kPThreads - 1) / kPThreads;
-  if (nb > kAsmPairs) return false;
+  const int nbp = (npairs + kPThreads - 1) / kPThreads;
+  const bool ok = npairs >= 1 && aligned16(zp) && ((uintptr_t)sp & (2 * sizeof(T) - 1)) == 0 &&
+                  nbp <= kAsmPairs;
+  const int nb = ok ? nbp : 1;
+  const double* zb = ok ? zp : reinterpret_cast<const double*>(safe);
+  const T* sb = ok ? sp : reinterpret_cast<const T*>(safe);
   const int rb = w % nb;
   const int tid = threadIdx.x;
 #pragma unroll
   for (int u = 0; u < kAsmPairs; ++u) {
-    L.pi[u] = asm_pair(u, tid, rb, nb, npairs);
+    L.pi[u] = ok ? asm_pair(u, tid, rb, nb, npairs) : -1;
     const int at = L.pi[u] >= 0 ? 2 * L.pi[u] : 0;
-    L.zv[u] = *gview(reinterpret_cast<const f64x2*>(zp + at));
-    L.sv[u] = *gview(reinterpret_cast<const typename Pair2<T>::type*>(sp + at));
+    L.zv[u] = *gview(reinterpret_cast<const f64x2*>(zb + at));
+    L.sv[u] = *gview(reinterpret_cast<const typename Pair2<T>::type*>(sb + at));
   }
   // The odd entry, when wlen is odd (thread 0 stores it): a per-lane address
   // (entry 0 elsewhere), so that these are vector loads in flight with the
   // pairs rather than scalar loads waited for at once.
-  const int last = tid == 0 ? wlen - 1 : 0;
-  L.zt = gview(zp)[last];
-  L.st = gview(sp)[last];
-  return true;
+  const int last = (ok && tid == 0) ? wlen - 1 : 0;
+  L.zt = gview(zb)[last];
+  L.st = gview(sb)[last];
+  return ok;
 }
 
 // s = z + bc s_old from the loaded pairs into the panel: the first half's
@@ -649,7 +656,7 @@ __device__ __forceinline__ void panel_body(const PanelPass& t, const Combine<T>&
   bool dfl_ok = false;
   if constexpr (MODE == kPassDir && kFastDir<T, K>) {
     const T* s_old = dir.s + (int64_t)parity * dir.sstride;
-    dfl_ok = dir_fast_load(dfl, dir.z + g0, s_old + g0, wlen, w);
+    dfl_ok = dir_fast_load(dfl, dir.z + g0, s_old + g0, wlen, w, t.idx);
   }
   ChunkDesc D0{};
   if (c < c_end) D0 = read_desc(t.chunks, c);
@@ -1478,12 +1485,19 @@ static inline unsigned red_grid(int64_t p) {
 
 
 // The scalars copied word by word to snap by one thread, after that
-// thread's own writes to them (so its loads see them).
+// thread's own writes to them (so its loads see them): every word is loaded
+// before the first store, one round trip (the compiler cannot tell that snap
+// and sc do not overlap, and would otherwise wait for each load in turn).
 __device__ __forceinline__ void snapshot_scal(const DevScal* sc, DevScal* snap) {
   static_assert(sizeof(DevScal) % 8 == 0, "DevScal is copied in 8-byte words");
+  constexpr int kWords = (int)(sizeof(DevScal) / 8);
   const uint64_t* a = reinterpret_cast<const uint64_t*>(sc);
   uint64_t* b = reinterpret_cast<uint64_t*>(snap);
-  for (int i = 0; i < (int)(sizeof(DevScal) / 8); ++i) b[i] = a[i];
+  uint64_t v[kWords];
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) v[i] = a[i];
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) b[i] = v[i];
 }
 
 // Mode 1 restarts only a run that ended well but whose FP64 true residual
@@ -1571,6 +1585,10 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
                                              VGrid g, int parity = 0, DevScal* snap = nullptr) {
   DevScal* sc = w.sc;
   const bool snapper = PassFinish && snap != nullptr && g.bid == 0 && threadIdx.x == 0;
+  // the flag and rho requested first (written by the kernels before this
+  // one, on other XCDs: a round trip that the loads below then overlap)
+  const int32_t sc_done = sc->done;
+  const double rho = sc->rho;
   // The passes' partials and this thread's first element are requested
   // before the stop flag is tested (every read is in bounds either way) and
   // before the grid total below (the element does not depend on alpha), so
@@ -1587,11 +1605,13 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
   const int64_t j0 = (int64_t)g.bid * kWG + threadIdx.x;
   double s0 = 0.0, q0 = 0.0, d0 = 0.0, r0 = 0.0, m0 = 0.0;
   if (j0 < p) {
+    // (the plain loads first: the product's partials are summed behind
+    // branches, which the plain loads would otherwise wait for)
     s0 = (double)s[j0 * es];
-    q0 = (double)combine_at(qsrc, j0);
     d0 = d[j0];
     r0 = r[j0];
     m0 = m[j0];
+    q0 = (double)combine_at(qsrc, j0);
   }
   double a[1] = {0.0};
   if (fit) {
@@ -1601,11 +1621,10 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
     for (int q = threadIdx.x; q < n1; q += kWG) a[0] += p1[(int64_t)q * ps];
     for (int q = threadIdx.x; q < n2; q += kWG) a[0] += p2[(int64_t)q * ps];
   }
-  if (sc->done) {
+  if (sc_done) {
     if (snapper) snapshot_scal(sc, snap);
     return;
   }
-  const double rho = sc->rho;
   __shared__ double sq_sh;
   {
     block_sum<1>(a);
