@@ -63,9 +63,9 @@ PASS_SOURCES = ("paper_1810_12437_amd/csrc/ppcg_kernels.hip",
                 "paper_1810_12437_amd/csrc/ppcg_layout.h",
                 "paper_1810_12437_amd/csrc/ppcg_panels.h")
 TRAFFIC = {
-    "sources_sha256": "2dc50e8dee7777a5af1970cd84319dcf739daadf8bda3c2803a10499cbba0932",
+    "sources_sha256": "ea67f121b8d91bc57e260fe28354456bb61157b265666b9f720fc41bd0aea102",
     # mean of the row and column variants: (FETCH_SIZE KiB x 2.0 + WRITE_SIZE KiB x 1.0) x 1024
-    "bytes_per_launch": 75610266,
+    "bytes_per_launch": 75581235,
 }
 
 

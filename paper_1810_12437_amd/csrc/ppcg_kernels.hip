@@ -1585,10 +1585,6 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
                                              VGrid g, int parity = 0, DevScal* snap = nullptr) {
   DevScal* sc = w.sc;
   const bool snapper = PassFinish && snap != nullptr && g.bid == 0 && threadIdx.x == 0;
-  // the flag and rho requested first (written by the kernels before this
-  // one, on other XCDs: a round trip that the loads below then overlap)
-  const int32_t sc_done = sc->done;
-  const double rho = sc->rho;
   // The passes' partials and this thread's first element are requested
   // before the stop flag is tested (every read is in bounds either way) and
   // before the grid total below (the element does not depend on alpha), so
@@ -1605,13 +1601,11 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
   const int64_t j0 = (int64_t)g.bid * kWG + threadIdx.x;
   double s0 = 0.0, q0 = 0.0, d0 = 0.0, r0 = 0.0, m0 = 0.0;
   if (j0 < p) {
-    // (the plain loads first: the product's partials are summed behind
-    // branches, which the plain loads would otherwise wait for)
     s0 = (double)s[j0 * es];
+    q0 = (double)combine_at(qsrc, j0);
     d0 = d[j0];
     r0 = r[j0];
     m0 = m[j0];
-    q0 = (double)combine_at(qsrc, j0);
   }
   double a[1] = {0.0};
   if (fit) {
@@ -1621,10 +1615,11 @@ __device__ __forceinline__ void cg_step_body(VecWork w, const T* s, int es,
     for (int q = threadIdx.x; q < n1; q += kWG) a[0] += p1[(int64_t)q * ps];
     for (int q = threadIdx.x; q < n2; q += kWG) a[0] += p2[(int64_t)q * ps];
   }
-  if (sc_done) {
+  if (sc->done) {
     if (snapper) snapshot_scal(sc, snap);
     return;
   }
+  const double rho = sc->rho;
   __shared__ double sq_sh;
   {
     block_sum<1>(a);
