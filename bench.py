@@ -109,7 +109,7 @@ def sources_sha256():
 def int32_pass_bytes(P, sv):
     """Bytes one launch of each X pass would move in a plain int32 CSR / CSC
     format (index stream, offsets, gathered vector once, scale, output); the
-    int32-equivalent rate of the 16-bit panel format is reported beside its
+    int32-equivalent rate of the compact panel format is reported beside its
     own."""
     nnz, n, p = P.nnz, P.n, P.p
     rows = int(np.count_nonzero(np.diff(P.row_ptr)))
