@@ -36,6 +36,11 @@
  *   reported in ppcg_info.status and are also returned.
  * - No C++ exception crosses this interface.  A handle must not be used by
  *   two calls at the same time (it holds the solver's workspace).
+ * - Results are bitwise reproducible: every reduction is summed in a fixed
+ *   order (per-block partials, no floating-point atomics), so the same call
+ *   on the same inputs and handle gives the same bits, and a batched chain
+ *   gives the bits of the same chain drawn alone.  There is no
+ *   non-deterministic mode, hence no option to select one.
  */
 #ifndef PPCG_H
 #define PPCG_H
