@@ -39,8 +39,9 @@
  * - Results are bitwise reproducible: every reduction is summed in a fixed
  *   order (per-block partials, no floating-point atomics), so the same call
  *   on the same inputs and handle gives the same bits, and a batched chain
- *   gives the bits of the same chain drawn alone.  There is no
- *   non-deterministic mode, hence no option to select one.
+ *   on its own design gives the bits of the same chain drawn alone (chains
+ *   that share one design run the K-wide passes, summed in another order).
+ *   There is no non-deterministic mode, hence no option to select one.
  */
 #ifndef PPCG_H
 #define PPCG_H
