@@ -148,8 +148,11 @@ def shared_setup(nchains, dtype, n=6000, p=3000, seed=31):
     return base, chains, B, vecs
 
 
-@pytest.mark.parametrize("nchains", [3, 8])
+@pytest.mark.parametrize("nchains", [1, 2, 3, 8])
 def test_shared_solve_matches_cholesky(nchains):
+    """Shared-design solves against Cholesky at a tight tolerance: one and
+    two chains run the K = 2 passes (one of them with an empty slot), three
+    and eight the groups of four."""
     base, chains, B, vecs = shared_setup(nchains, pk.F64)
     say("shared solve", nchains, "chains, n", base.n, "p", base.p)
     rng = np.random.default_rng(nchains)
