@@ -213,8 +213,12 @@ def test_shared_slot_reassignment_keeps_draws():
         assert i1[c]["status"] == pk.OK
 
 
-def test_shared_f32_matches_f64_oracle():
-    base, chains, B, vecs = shared_setup(4, pk.F32)
+@pytest.mark.parametrize("nchains", [2, 4])
+def test_shared_f32_matches_f64_oracle(nchains):
+    """FP32 shared-design draws (with the refinement restart) against the FP64
+    oracle's Cholesky solution to 1e-5: two chains run the K = 2 passes, four
+    one group of four."""
+    base, chains, B, vecs = shared_setup(nchains, pk.F32)
     n = len(vecs)
     betas, infos = B.draw([v[0] for v in vecs], [v[1] for v in vecs], [v[2] for v in vecs],
                           [v[3] for v in vecs], [5] * n, list(range(n)), [0] * n, tol=1e-12)
